@@ -1,0 +1,576 @@
+// C ABI of the ICWF library (declared in include/icwf.h): validation, the
+// workspace layout, the host-side tables, the per-step launch plan and its
+// HIP-graph capture, and the copies in and out.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/icwf.h"
+#include "icwf_plan.hpp"
+
+using icwf::Bufs;
+using icwf::Dims;
+
+namespace {
+
+thread_local std::string g_create_error = "";
+
+bool is_pow2(int n) { return n > 0 && (n & (n - 1)) == 0; }
+
+// Layout of every device buffer inside the caller's workspace (256-byte
+// aligned pieces).  With base == nullptr it only sizes.
+struct Layout {
+    size_t off = 0;
+    char *base = nullptr;
+    template <typename T>
+    T *take(size_t count) {
+        off = (off + 255) & ~size_t(255);
+        T *p = base ? reinterpret_cast<T *>(base + off) : nullptr;
+        off += count * sizeof(T);
+        return p;
+    }
+};
+
+size_t obs_len(int nr, int nR, int n_bo) { return 1 + (size_t)nr + nR + n_bo + (size_t)n_bo * n_bo; }
+
+Bufs carve(const icwf_config &c, char *base, size_t *total) {
+    Layout L;
+    L.base = base;
+    const size_t Np = icwf::padded(c.n_traj), nr = c.n_r, nR = c.n_R, nbo = c.n_bo;
+    Bufs b{};
+    b.flags = L.take<int32_t>(icwf::kNumFlags);
+    b.scal = L.take<double>(8);
+    b.psi1 = L.take<double2>(Np * nr);
+    b.psi2 = L.take<double2>(Np * nR);
+    b.r = L.take<double>(Np);
+    b.R = L.take<double>(Np);
+    b.r_new = L.take<double>(Np);
+    b.R_new = L.take<double>(Np);
+    b.C = L.take<double2>(Np);
+    b.Cacc = L.take<double2>(Np);
+    b.Cstage = L.take<double2>(Np);
+    b.y = L.take<double2>(Np);
+    b.vstat_r = L.take<double>(nr);
+    b.vstat_R = L.take<double>(nR);
+    b.kin_r = L.take<double2>(nr);
+    b.kin_R = L.take<double2>(nR);
+    b.tw_r = L.take<double2>(nr);
+    b.tw_R = L.take<double2>(nR);
+    b.wc64 = L.take<double>(nr * nR);
+    b.wc32 = L.take<float>(nr * nR);
+    b.sinc_r = L.take<double>(Np * nr);
+    b.dsinc_r = L.take<double>(Np * nr);
+    b.sinc_R = L.take<double>(Np * nR);
+    b.dsinc_R = L.take<double>(Np * nR);
+    b.vpart = L.take<double2>((Np / 16) * Np * 3);
+    b.v_r = L.take<double>(Np);
+    b.v_R = L.take<double>(Np);
+    b.psi_at = L.take<double2>(Np);
+    b.G1a = L.take<double2>(Np * nr);
+    b.G1b = L.take<double2>(Np * nr);
+    b.G2a = L.take<double2>(Np * nR);
+    b.G2b = L.take<double2>(Np * nR);
+    double2 **mats[] = {&b.S1,      &b.S2,      &b.E1a,     &b.E1b,  &b.E2a,     &b.E2b,   &b.Wc,  &b.Smat[0],
+                        &b.Smat[1], &b.Kmat[0], &b.Kmat[1], &b.Kminus, &b.Kmid, &b.L[0], &b.L[1], &b.Lmid};
+    for (double2 **m : mats) *m = L.take<double2>(Np * Np);
+    b.chol_diag = L.take<double2>(2 * icwf::kCholNb * icwf::kCholNb);
+    b.bo = L.take<double>(std::max<size_t>(1, nR * nbo * nr));
+    b.obs_u = L.take<double2>(Np * std::max(nr, nR));
+    b.obs_chi = L.take<double2>(std::max<size_t>(1, nbo * nR));
+    b.obs_out = L.take<double>(obs_len(c.n_r, c.n_R, c.n_bo));
+    *total = (L.off + 255) & ~size_t(255);
+    return b;
+}
+
+const char *validate(const icwf_config *c) {
+    if (!c) return "config is NULL";
+    if (c->n_traj < 1 || c->n_traj > 4096) return "n_traj must be in [1, 4096]";
+    if (!is_pow2(c->n_r) || c->n_r < 32 || c->n_r > 4096) return "n_r must be a power of two in [32, 4096]";
+    if (!is_pow2(c->n_R) || c->n_R < 32 || c->n_R > 4096) return "n_R must be a power of two in [32, 4096]";
+    if (!(c->r_max > c->r_min) || !std::isfinite(c->r_min) || !std::isfinite(c->r_max)) return "bad r box";
+    if (!(c->R_max > c->R_min) || !std::isfinite(c->R_min) || !std::isfinite(c->R_max)) return "bad R box";
+    if (!(c->m_r > 0) || !(c->m_R > 0) || !std::isfinite(c->m_r) || !std::isfinite(c->m_R)) return "masses must be > 0";
+    if (!(c->dt > 0) || !std::isfinite(c->dt)) return "dt must be > 0";
+    if (!(c->tikhonov_eps >= 0) || !std::isfinite(c->tikhonov_eps)) return "tikhonov_eps must be >= 0";
+    if (c->model != ICWF_MODEL_SHIN_METIU && c->model != ICWF_MODEL_CAVITY) return "unknown model";
+    if (c->precision != ICWF_PREC_FP64 && c->precision != ICWF_PREC_MIXED) return "unknown precision";
+    if (c->n_bo < 0 || c->n_bo > c->n_r) return "n_bo must be in [0, n_r]";
+    for (int i = 0; i < 8; ++i)
+        if (!std::isfinite(c->model_params[i])) return "model parameters must be finite";
+    if (c->model == ICWF_MODEL_SHIN_METIU) {
+        if (!(c->model_params[1] > 0) || !(c->model_params[2] > 0) || !(c->model_params[3] > 0))
+            return "Shin-Metiu softening lengths must be > 0";
+    }
+    return nullptr;
+}
+
+// ---- host model (tables only; the step evaluates the model on the device) --------------------
+double h_erfx(double x, double a) {
+    const double ax = std::fabs(x), z = ax / a;
+    if (z < 1e-4) return 2.0 / (std::sqrt(M_PI) * a) * (1.0 - z * z / 3.0 + z * z * z * z / 10.0);
+    return std::erf(z) / ax;
+}
+double h_v1(const icwf_config &c, double r) {
+    const double *p = c.model_params;
+    if (c.model == ICWF_MODEL_SHIN_METIU) return -h_erfx(r - 0.5 * p[0], p[3]) - h_erfx(r + 0.5 * p[0], p[2]);
+    return -p[0] / std::sqrt(r * r + p[1] * p[1]);
+}
+double h_v2(const icwf_config &c, double R) {
+    const double *p = c.model_params;
+    if (c.model == ICWF_MODEL_SHIN_METIU) return 1.0 / std::fabs(0.5 * p[0] - R) + 1.0 / std::fabs(0.5 * p[0] + R);
+    return 0.5 * p[2] * p[2] * R * R;
+}
+double h_wc(const icwf_config &c, double r, double R) {
+    const double *p = c.model_params;
+    if (c.model == ICWF_MODEL_SHIN_METIU) return -h_erfx(r - R, p[1]);
+    return p[3] * R * r;
+}
+
+struct Timer {
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> recs;
+    int64_t launches = 0;
+    double total_ms = 0.0;
+};
+
+}  // namespace
+
+struct icwf_sim {
+    icwf_config cfg{};
+    Dims d{};
+    Bufs b{};
+    int Np = 0;
+    hipStream_t stream = nullptr;
+    hipStream_t capture_stream = nullptr;
+    hipGraphExec_t exec[2] = {nullptr, nullptr};
+    int parity = 0;
+    int64_t step = 0;
+    double t = 0.0;
+    int status = ICWF_OK;        // sticky device error once seen
+    bool timing = false;
+    std::map<std::string, Timer> timers;
+    std::vector<hipEvent_t> event_pool;
+    std::string err;
+};
+
+namespace {
+
+icwf_status fail(icwf_sim *s, icwf_status st, const std::string &msg) {
+    if (s) s->err = msg;
+    else g_create_error = msg;
+    return st;
+}
+
+#define HIP_OK(call, sim)                                                                               \
+    do {                                                                                                \
+        hipError_t e_ = (call);                                                                         \
+        if (e_ != hipSuccess) return fail(sim, ICWF_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+hipEvent_t get_event(icwf_sim *s) {
+    if (!s->event_pool.empty()) {
+        hipEvent_t e = s->event_pool.back();
+        s->event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    (void)hipEventCreate(&e);
+    return e;
+}
+
+// Runs `fn` on stream st, bracketed by an event pair when timing.
+template <typename F>
+void timed(icwf_sim *s, const char *name, hipStream_t st, F fn) {
+    if (!s->timing) {
+        fn();
+        return;
+    }
+    hipEvent_t a = get_event(s), b = get_event(s);
+    (void)hipEventRecord(a, st);
+    fn();
+    (void)hipEventRecord(b, st);
+    s->timers[name].recs.emplace_back(a, b);
+}
+
+void enqueue_step(icwf_sim *s, int parity, hipStream_t st) {
+    const Dims &d = s->d;
+    const Bufs &b = s->b;
+    timed(s, "velocity", st, [&] { icwf::launch_velocity(d, b, true, st); });
+    timed(s, "propagate", st, [&] {
+        icwf::launch_propagate(d, b, 1, st);
+        icwf::launch_propagate(d, b, 2, st);
+    });
+    timed(s, "zgemm", st, [&] {
+        icwf::launch_cond_kets(d, b, st);
+        icwf::launch_single_species(d, b, true, st);
+    });
+    timed(s, "wc_contract", st, [&] { icwf::launch_wc(d, b, st); });
+    timed(s, "assemble", st, [&] { icwf::launch_assemble(d, b, parity, false, st); });
+    timed(s, "cholesky", st, [&] { icwf::launch_cholesky(d, b, b.Lmid, b.L[1 - parity], 2, st); });
+    timed(s, "rk4", st, [&] { icwf::launch_rk4(d, b, parity, st); });
+}
+
+icwf_status device_status(icwf_sim *s) {
+    int32_t flags[icwf::kNumFlags];
+    HIP_OK(hipStreamSynchronize(s->stream), s);
+    HIP_OK(hipMemcpy(flags, s->b.flags, sizeof(flags), hipMemcpyDeviceToHost), s);
+    if (flags[icwf::kFlagNode]) {
+        s->status = ICWF_ENODE;
+        return fail(s, ICWF_ENODE, "a trajectory sits at a node of the ansatz wavefunction (|Psi| < 1e-300)");
+    }
+    if (flags[icwf::kFlagSolve]) {
+        s->status = ICWF_ESOLVE;
+        return fail(s, ICWF_ESOLVE, "S + eps I is not numerically positive definite");
+    }
+    if (flags[icwf::kFlagNonfinite]) {
+        s->status = ICWF_ENONFINITE;
+        return fail(s, ICWF_ENONFINITE, "non-finite value in the coefficients or positions");
+    }
+    return ICWF_OK;
+}
+
+icwf_status capture_graphs(icwf_sim *s) {
+    for (int p = 0; p < 2; ++p) {
+        hipGraph_t g = nullptr;
+        HIP_OK(hipStreamBeginCapture(s->capture_stream, hipStreamCaptureModeThreadLocal), s);
+        enqueue_step(s, p, s->capture_stream);
+        HIP_OK(hipStreamEndCapture(s->capture_stream, &g), s);
+        HIP_OK(hipGraphInstantiate(&s->exec[p], g, nullptr, nullptr, 0), s);
+        HIP_OK(hipGraphDestroy(g), s);
+    }
+    return ICWF_OK;
+}
+
+// strided copy of the leading N x N block of an Np x Np complex matrix
+icwf_status copy_matrix_out(icwf_sim *s, const double2 *dev, double *host) {
+    const int N = s->cfg.n_traj;
+    HIP_OK(hipMemcpy2D(host, sizeof(double2) * N, dev, sizeof(double2) * s->Np, sizeof(double2) * N, N,
+                       hipMemcpyDeviceToHost),
+           s);
+    return ICWF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t icwf_workspace_bytes(const icwf_config *cfg) {
+    if (validate(cfg)) return 0;
+    size_t total = 0;
+    carve(*cfg, nullptr, &total);
+    return total;
+}
+
+icwf_status icwf_create(const icwf_config *cfg, const double *r0, const double *R0, const double *psi1_0,
+                        const double *psi2_0, const double *C0, const double *b0, const double *bo_states,
+                        void *workspace, size_t ws_bytes, void *hip_stream, icwf_sim **out) {
+    if (!out) return fail(nullptr, ICWF_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (const char *m = validate(cfg)) return fail(nullptr, ICWF_EINVAL, m);
+    if (!r0 || !R0 || !psi1_0 || !psi2_0) return fail(nullptr, ICWF_EINVAL, "positions and CWFs are required");
+    if (!C0 && !b0) return fail(nullptr, ICWF_EINVAL, "one of C0 and b0 is required");
+    if (cfg->n_bo > 0 && !bo_states) return fail(nullptr, ICWF_EINVAL, "n_bo > 0 needs bo_states");
+    if (!workspace) return fail(nullptr, ICWF_EINVAL, "workspace is NULL");
+    if (reinterpret_cast<uintptr_t>(workspace) & 255) return fail(nullptr, ICWF_EINVAL, "workspace must be 256-byte aligned");
+    size_t need = 0;
+    carve(*cfg, nullptr, &need);
+    if (ws_bytes < need) return fail(nullptr, ICWF_ENOMEM, "workspace smaller than icwf_workspace_bytes()");
+
+    const int N = cfg->n_traj, nr = cfg->n_r, nR = cfg->n_R, nbo = cfg->n_bo;
+    const int Np = icwf::padded(N);
+    auto finite = [](const double *p, size_t n) {
+        for (size_t i = 0; i < n; ++i)
+            if (!std::isfinite(p[i])) return false;
+        return true;
+    };
+    if (!finite(r0, N) || !finite(R0, N) || !finite(psi1_0, 2 * (size_t)N * nr) ||
+        !finite(psi2_0, 2 * (size_t)N * nR) || (C0 && !finite(C0, 2 * (size_t)N)) || (!C0 && !finite(b0, 2 * (size_t)N)) ||
+        (nbo > 0 && !finite(bo_states, (size_t)nR * nbo * nr)))
+        return fail(nullptr, ICWF_ENONFINITE, "non-finite input");
+
+    icwf_sim *s = new icwf_sim();
+    s->cfg = *cfg;
+    s->Np = Np;
+    s->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    size_t total = 0;
+    s->b = carve(*cfg, reinterpret_cast<char *>(workspace), &total);
+    Dims &d = s->d;
+    d.N = N;
+    d.nr = nr;
+    d.nR = nR;
+    d.n_bo = nbo;
+    d.prec = cfg->precision;
+    d.r_min = cfg->r_min;
+    d.hr = (cfg->r_max - cfg->r_min) / nr;
+    d.R_min = cfg->R_min;
+    d.hR = (cfg->R_max - cfg->R_min) / nR;
+    d.m_r = cfg->m_r;
+    d.m_R = cfg->m_R;
+    d.dt = cfg->dt;
+    d.eps = cfg->tikhonov_eps;
+    d.mp.kind = cfg->model;
+    for (int i = 0; i < 8; ++i) d.mp.p[i] = cfg->model_params[i];
+
+    auto cleanup_fail = [&](icwf_status st, const std::string &m) {
+        g_create_error = m;
+        icwf_destroy(s);
+        return st;
+    };
+    auto hipchk = [&](hipError_t e, const char *what) -> bool {
+        if (e != hipSuccess) {
+            g_create_error = std::string(what) + ": " + hipGetErrorString(e);
+            return false;
+        }
+        return true;
+    };
+#define CREATE_HIP(call)                                \
+    do {                                                \
+        if (!hipchk((call), #call)) {                   \
+            std::string m_ = g_create_error;            \
+            return cleanup_fail(ICWF_EDEVICE, m_);      \
+        }                                               \
+    } while (0)
+
+    // ---- host tables
+    std::vector<double> vr(nr), vR(nR), wc(static_cast<size_t>(nr) * nR);
+    std::vector<float> wc32(static_cast<size_t>(nr) * nR);
+    std::vector<double2> kin_r(nr), kin_R(nR), tw_r(nr), tw_R(nR);
+    for (int i = 0; i < nr; ++i) vr[i] = h_v1(*cfg, d.r_min + i * d.hr);
+    for (int j = 0; j < nR; ++j) vR[j] = h_v2(*cfg, d.R_min + j * d.hR);
+    for (int i = 0; i < nr; ++i)
+        for (int j = 0; j < nR; ++j) {
+            const double w = h_wc(*cfg, d.r_min + i * d.hr, d.R_min + j * d.hR);
+            wc[(size_t)i * nR + j] = w;
+            wc32[(size_t)i * nR + j] = static_cast<float>(w);
+        }
+    if (!finite(vr.data(), nr) || !finite(vR.data(), nR) || !finite(wc.data(), wc.size()))
+        return cleanup_fail(ICWF_ENONFINITE, "the model is singular on the grid");
+    auto fill_k = [&](std::vector<double2> &kin, std::vector<double2> &tw, int n, double h, double m) {
+        for (int k = 0; k < n; ++k) {
+            const int kk = (k <= n / 2) ? k : k - n;
+            const double kw = 2.0 * M_PI * kk / (n * h);
+            const double ph = -0.5 * d.dt * kw * kw / m;
+            kin[k] = make_double2(std::cos(ph), std::sin(ph));
+            const double a = -2.0 * M_PI * k / n;
+            tw[k] = make_double2(std::cos(a), std::sin(a));
+        }
+    };
+    fill_k(kin_r, tw_r, nr, d.hr, d.m_r);
+    fill_k(kin_R, tw_R, nR, d.hR, d.m_R);
+
+    // ---- padded state
+    std::vector<double> rp(Np, cfg->r_min), Rp(Np, cfg->R_min);
+    std::copy(r0, r0 + N, rp.begin());
+    std::copy(R0, R0 + N, Rp.begin());
+
+    hipStream_t st = s->stream;
+    const Bufs &b = s->b;
+    CREATE_HIP(hipMemsetAsync(workspace, 0, total, st));
+    CREATE_HIP(hipMemcpyAsync(b.psi1, psi1_0, sizeof(double2) * (size_t)N * nr, hipMemcpyHostToDevice, st));
+    CREATE_HIP(hipMemcpyAsync(b.psi2, psi2_0, sizeof(double2) * (size_t)N * nR, hipMemcpyHostToDevice, st));
+    CREATE_HIP(hipMemcpyAsync(b.r, rp.data(), sizeof(double) * Np, hipMemcpyHostToDevice, st));
+    CREATE_HIP(hipMemcpyAsync(b.R, Rp.data(), sizeof(double) * Np, hipMemcpyHostToDevice, st));
+    CREATE_HIP(hipMemcpyAsync(b.r_new, rp.data(), sizeof(double) * Np, hipMemcpyHostToDevice, st));
+    CREATE_HIP(hipMemcpyAsync(b.R_new, Rp.data(), sizeof(double) * Np, hipMemcpyHostToDevice, st));
+    CREATE_HIP(hipMemcpyAsync(b.vstat_r, vr.data(), sizeof(double) * nr, hipMemcpyHostToDevice, st));
+    CREATE_HIP(hipMemcpyAsync(b.vstat_R, vR.data(), sizeof(double) * nR, hipMemcpyHostToDevice, st));
+    CREATE_HIP(hipMemcpyAsync(b.kin_r, kin_r.data(), sizeof(double2) * nr, hipMemcpyHostToDevice, st));
+    CREATE_HIP(hipMemcpyAsync(b.kin_R, kin_R.data(), sizeof(double2) * nR, hipMemcpyHostToDevice, st));
+    CREATE_HIP(hipMemcpyAsync(b.tw_r, tw_r.data(), sizeof(double2) * nr, hipMemcpyHostToDevice, st));
+    CREATE_HIP(hipMemcpyAsync(b.tw_R, tw_R.data(), sizeof(double2) * nR, hipMemcpyHostToDevice, st));
+    CREATE_HIP(hipMemcpyAsync(b.wc64, wc.data(), sizeof(double) * wc.size(), hipMemcpyHostToDevice, st));
+    CREATE_HIP(hipMemcpyAsync(b.wc32, wc32.data(), sizeof(float) * wc32.size(), hipMemcpyHostToDevice, st));
+    if (nbo > 0)
+        CREATE_HIP(hipMemcpyAsync(b.bo, bo_states, sizeof(double) * (size_t)nR * nbo * nr, hipMemcpyHostToDevice, st));
+    if (C0) CREATE_HIP(hipMemcpyAsync(b.C, C0, sizeof(double2) * N, hipMemcpyHostToDevice, st));
+    else CREATE_HIP(hipMemcpyAsync(b.y, b0, sizeof(double2) * N, hipMemcpyHostToDevice, st));
+
+    // ---- initial S_0, K_0 and the factor of S_0 + eps I
+    icwf::launch_cond_kets(d, b, st);
+    icwf::launch_single_species(d, b, false, st);
+    icwf::launch_wc(d, b, st);
+    icwf::launch_assemble(d, b, 0, true, st);
+    icwf::launch_cholesky(d, b, b.L[0], b.L[0], 1, st);
+    if (!C0) icwf::launch_solve_initial(d, b, 0, b.y, st);
+    CREATE_HIP(hipGetLastError());
+    const icwf_status ds = device_status(s);
+    if (ds != ICWF_OK) {
+        std::string m = s->err;
+        return cleanup_fail(ds, m);
+    }
+    CREATE_HIP(hipStreamCreateWithFlags(&s->capture_stream, hipStreamNonBlocking));
+    if (capture_graphs(s) != ICWF_OK) {
+        std::string m = s->err;
+        return cleanup_fail(ICWF_EDEVICE, m);
+    }
+#undef CREATE_HIP
+    *out = s;
+    return ICWF_OK;
+}
+
+icwf_status icwf_step(icwf_sim *s, int32_t n_steps) {
+    if (!s) return fail(nullptr, ICWF_EINVAL, "sim is NULL");
+    if (n_steps < 0) return fail(s, ICWF_EINVAL, "n_steps must be >= 0");
+    if (s->status != ICWF_OK) return fail(s, ICWF_ESTATE, "the simulation stopped on an earlier error");
+    for (int k = 0; k < n_steps; ++k) {
+        if (s->timing) {
+            enqueue_step(s, s->parity, s->stream);
+            HIP_OK(hipGetLastError(), s);
+        } else {
+            HIP_OK(hipGraphLaunch(s->exec[s->parity], s->stream), s);
+        }
+        s->parity ^= 1;
+        s->step += 1;
+        s->t += s->d.dt;
+    }
+    return ICWF_OK;
+}
+
+icwf_status icwf_sync(icwf_sim *s) {
+    if (!s) return fail(nullptr, ICWF_EINVAL, "sim is NULL");
+    if (s->status != ICWF_OK) return static_cast<icwf_status>(s->status);
+    return device_status(s);
+}
+
+icwf_status icwf_observables(icwf_sim *s, icwf_obs *o) {
+    if (!s || !o) return fail(s, ICWF_EINVAL, "NULL argument");
+    icwf_status st = icwf_sync(s);
+    const Dims &d = s->d;
+    icwf::launch_observables(d, s->b, s->parity, s->stream);
+    HIP_OK(hipGetLastError(), s);
+    std::vector<double> buf(obs_len(d.nr, d.nR, d.n_bo));
+    HIP_OK(hipMemcpyAsync(buf.data(), s->b.obs_out, sizeof(double) * buf.size(), hipMemcpyDeviceToHost, s->stream), s);
+    int32_t flags[icwf::kNumFlags];
+    double scal[8];
+    HIP_OK(hipMemcpyAsync(flags, s->b.flags, sizeof(flags), hipMemcpyDeviceToHost, s->stream), s);
+    HIP_OK(hipMemcpyAsync(scal, s->b.scal, sizeof(scal), hipMemcpyDeviceToHost, s->stream), s);
+    HIP_OK(hipStreamSynchronize(s->stream), s);
+    o->t = s->t;
+    o->step = s->step;
+    o->norm = buf[0];
+    if (o->rho_r) std::copy(buf.begin() + 1, buf.begin() + 1 + d.nr, o->rho_r);
+    if (o->rho_R) std::copy(buf.begin() + 1 + d.nr, buf.begin() + 1 + d.nr + d.nR, o->rho_R);
+    const size_t po = 1 + d.nr + d.nR;
+    if (o->pop && d.n_bo) std::copy(buf.begin() + po, buf.begin() + po + d.n_bo, o->pop);
+    if (o->D && d.n_bo) std::copy(buf.begin() + po + d.n_bo, buf.begin() + po + d.n_bo + d.n_bo * d.n_bo, o->D);
+    if (o->r) HIP_OK(hipMemcpy(o->r, s->b.r, sizeof(double) * d.N, hipMemcpyDeviceToHost), s);
+    if (o->R) HIP_OK(hipMemcpy(o->R, s->b.R, sizeof(double) * d.N, hipMemcpyDeviceToHost), s);
+    if (o->C) HIP_OK(hipMemcpy(o->C, s->b.C, sizeof(double2) * d.N, hipMemcpyDeviceToHost), s);
+    o->n_out_of_box = flags[icwf::kFlagOut];
+    uint64_t bits;
+    std::memcpy(&bits, &scal[0], sizeof(bits));
+    double mn;
+    std::memcpy(&mn, &bits, sizeof(mn));
+    o->min_abs_psi = (s->step == 0) ? INFINITY : mn;
+    return st;
+}
+
+icwf_status icwf_get_state(icwf_sim *s, double *r, double *R, double *psi1, double *psi2, double *C) {
+    if (!s) return fail(nullptr, ICWF_EINVAL, "sim is NULL");
+    HIP_OK(hipStreamSynchronize(s->stream), s);
+    const Dims &d = s->d;
+    if (r) HIP_OK(hipMemcpy(r, s->b.r, sizeof(double) * d.N, hipMemcpyDeviceToHost), s);
+    if (R) HIP_OK(hipMemcpy(R, s->b.R, sizeof(double) * d.N, hipMemcpyDeviceToHost), s);
+    if (psi1) HIP_OK(hipMemcpy(psi1, s->b.psi1, sizeof(double2) * (size_t)d.N * d.nr, hipMemcpyDeviceToHost), s);
+    if (psi2) HIP_OK(hipMemcpy(psi2, s->b.psi2, sizeof(double2) * (size_t)d.N * d.nR, hipMemcpyDeviceToHost), s);
+    if (C) HIP_OK(hipMemcpy(C, s->b.C, sizeof(double2) * d.N, hipMemcpyDeviceToHost), s);
+    return static_cast<icwf_status>(s->status);
+}
+
+icwf_status icwf_get_matrices(icwf_sim *s, double *S, double *K, double *Wc) {
+    if (!s) return fail(nullptr, ICWF_EINVAL, "sim is NULL");
+    HIP_OK(hipStreamSynchronize(s->stream), s);
+    if (S && copy_matrix_out(s, s->b.Smat[s->parity], S) != ICWF_OK) return ICWF_EDEVICE;
+    if (K && copy_matrix_out(s, s->b.Kmat[s->parity], K) != ICWF_OK) return ICWF_EDEVICE;
+    if (Wc) {
+        if (copy_matrix_out(s, s->b.Wc, Wc) != ICWF_OK) return ICWF_EDEVICE;
+        const int N = s->cfg.n_traj;
+        for (int b = 0; b < N; ++b)
+            for (int a = 0; a < b; ++a) {   // lower = conj(upper): only b <= a is computed
+                Wc[2 * ((size_t)b * N + a)] = Wc[2 * ((size_t)a * N + b)];
+                Wc[2 * ((size_t)b * N + a) + 1] = -Wc[2 * ((size_t)a * N + b) + 1];
+            }
+    }
+    return static_cast<icwf_status>(s->status);
+}
+
+icwf_status icwf_velocities(icwf_sim *s, double *v_r, double *v_R, double *psi_at) {
+    if (!s) return fail(nullptr, ICWF_EINVAL, "sim is NULL");
+    if (s->status != ICWF_OK) return fail(s, ICWF_ESTATE, "the simulation stopped on an earlier error");
+    icwf::launch_velocity(s->d, s->b, false, s->stream);
+    HIP_OK(hipGetLastError(), s);
+    icwf_status st = device_status(s);
+    const Dims &d = s->d;
+    if (v_r) HIP_OK(hipMemcpy(v_r, s->b.v_r, sizeof(double) * d.N, hipMemcpyDeviceToHost), s);
+    if (v_R) HIP_OK(hipMemcpy(v_R, s->b.v_R, sizeof(double) * d.N, hipMemcpyDeviceToHost), s);
+    if (psi_at) HIP_OK(hipMemcpy(psi_at, s->b.psi_at, sizeof(double2) * d.N, hipMemcpyDeviceToHost), s);
+    return st;
+}
+
+icwf_status icwf_set_timing(icwf_sim *s, int32_t enable) {
+    if (!s) return fail(nullptr, ICWF_EINVAL, "sim is NULL");
+    HIP_OK(hipStreamSynchronize(s->stream), s);
+    for (auto &kv : s->timers)
+        for (auto &pr : kv.second.recs) {
+            s->event_pool.push_back(pr.first);
+            s->event_pool.push_back(pr.second);
+        }
+    s->timers.clear();
+    s->timing = enable != 0;
+    return ICWF_OK;
+}
+
+icwf_status icwf_kernel_time(icwf_sim *s, const char *name, int64_t *launches, double *total_ms) {
+    if (!s || !name) return fail(s, ICWF_EINVAL, "NULL argument");
+    HIP_OK(hipStreamSynchronize(s->stream), s);
+    Timer &tm = s->timers[name];
+    for (auto &pr : tm.recs) {
+        float ms = 0.0f;
+        HIP_OK(hipEventElapsedTime(&ms, pr.first, pr.second), s);
+        tm.total_ms += ms;
+        tm.launches += 1;
+        s->event_pool.push_back(pr.first);
+        s->event_pool.push_back(pr.second);
+    }
+    tm.recs.clear();
+    if (launches) *launches = tm.launches;
+    if (total_ms) *total_ms = tm.total_ms;
+    return ICWF_OK;
+}
+
+void icwf_destroy(icwf_sim *s) {
+    if (!s) return;
+    if (s->stream || s->capture_stream) (void)hipStreamSynchronize(s->stream);
+    for (auto &e : s->exec)
+        if (e) (void)hipGraphExecDestroy(e);
+    if (s->capture_stream) (void)hipStreamDestroy(s->capture_stream);
+    for (auto &kv : s->timers)
+        for (auto &pr : kv.second.recs) {
+            (void)hipEventDestroy(pr.first);
+            (void)hipEventDestroy(pr.second);
+        }
+    for (auto e : s->event_pool) (void)hipEventDestroy(e);
+    delete s;
+}
+
+const char *icwf_last_error(const icwf_sim *s) { return s ? s->err.c_str() : g_create_error.c_str(); }
+
+const char *icwf_status_string(int32_t st) {
+    switch (st) {
+        case ICWF_OK: return "ICWF_OK";
+        case ICWF_EINVAL: return "ICWF_EINVAL";
+        case ICWF_ENOMEM: return "ICWF_ENOMEM";
+        case ICWF_EDEVICE: return "ICWF_EDEVICE";
+        case ICWF_ENONFINITE: return "ICWF_ENONFINITE";
+        case ICWF_ENODE: return "ICWF_ENODE";
+        case ICWF_ESOLVE: return "ICWF_ESOLVE";
+        case ICWF_ESTATE: return "ICWF_ESTATE";
+        default: return "unknown";
+    }
+}
+
+}  // extern "C"

@@ -1,0 +1,98 @@
+// Internal plan of one ICWF simulation: sizes, device buffers carved from the
+// caller's workspace, and the host-side launchers of every kernel.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "icwf_device.hpp"
+
+namespace icwf {
+
+struct Dims {
+    int N, nr, nR, n_bo, prec;
+    double r_min, hr, R_min, hR, m_r, m_R, dt, eps;
+    ModelParams mp;
+};
+
+// Trajectory count padded to the tile size every kernel assumes.  Padding
+// rows hold zero CWFs and zero coefficients, so they add nothing to any sum,
+// and S + eps I is eps I on them.
+constexpr int kPad = 64;
+inline int padded(int N) { return (N + kPad - 1) / kPad * kPad; }
+constexpr int kCholNb = 64;      // Cholesky panel width
+
+struct Bufs {
+    double2 *psi1, *psi2;                 // [N][nr], [N][nR] CWFs (Eq. 7)
+    double *r, *R, *r_new, *R_new;        // trajectory positions at t_k and t_k+1
+    double2 *C, *Cacc, *Cstage;           // coefficients and RK4 stage vectors
+    double2 *y;                           // matvec output K v
+    double *vstat_r, *vstat_R;            // V_1(r_i), V_2(R_j)
+    double2 *kin_r, *kin_R;               // exp(-i k^2 dt / 2m), FFT order
+    double2 *tw_r, *tw_R;                 // exp(-2 pi i k / n)
+    double *wc64;                         // [nr][nR] W_c(r_i, R_j)
+    float *wc32;                          // [nr][nR] FP32 rounding of wc64 (mixed form)
+    double *sinc_r, *dsinc_r;             // [N][nr] periodic sinc and derivative at r^a
+    double *sinc_R, *dsinc_R;             // [N][nR]
+    double2 *vpart;                       // [Np/16][Np][3] velocity partial sums
+    double *v_r, *v_R;                    // [N] velocities
+    double2 *psi_at;                      // [N] Psi(r^a, R^a)
+    double2 *G1a, *G1b;                   // [N][nr] W_c(r_i, R^a) psi_1^a_i at x_k, x_k+1
+    double2 *G2a, *G2b;                   // [N][nR] W_c(r^a, R_j) psi_2^a_j at x_k, x_k+1
+    double2 *S1, *S2;                     // [N][N] single-species overlaps
+    double2 *E1a, *E1b, *E2a, *E2b;       // [N][N] W_c-conditioned single-species integrals
+    double2 *Wc;                          // [N][N] two-body contraction (W_c part of Eq. 9b)
+    double2 *Smat[2], *Kmat[2];           // S_k, K_k (current / next by step parity)
+    double2 *Kminus, *Kmid;               // K(psi_k+1, x_k) and the midpoint K
+    double2 *L[2], *Lmid;                 // Cholesky factors of S + eps I (lower)
+    double2 *chol_diag;                   // [2][64][64] factored diagonal blocks in flight
+    double *bo;                           // [nR][n_bo][nr] BO states
+    double2 *obs_u, *obs_v;               // observables scratch [N][max(nr,nR)]
+    double2 *obs_chi;                     // [n_bo][nR]
+    double *obs_out;                      // packed observables
+    int32_t *flags;                       // kNumFlags status flags
+    double *scal;                         // small device scalars (min |Psi|, ...)
+};
+
+// ---- launchers (each defined next to its kernels) -------------------------------------------
+
+// Split-operator step of every CWF of one species; species 1 = electronic
+// (conditioned on R^a), 2 = nuclear (conditioned on r^a).
+void launch_propagate(const Dims &d, const Bufs &b, int species, hipStream_t s);
+
+// Periodic-sinc tables at the current positions, velocity contraction and
+// reduction; writes v_r, v_R, psi_at, r_new, R_new (x + dt v) and the flags.
+void launch_velocity(const Dims &d, const Bufs &b, bool update_positions, hipStream_t s);
+
+// Conditioned kets G = W_c(., x) psi for the two conditionings x_k, x_k+1.
+void launch_cond_kets(const Dims &d, const Bufs &b, hipStream_t s);
+
+// Batched h * conj(X) Y^T complex products: S1, S2, E1a, E1b, E2a, E2b.
+void launch_single_species(const Dims &d, const Bufs &b, bool both_conditionings, hipStream_t s);
+
+// Two-body contraction Wc (upper pair tiles), FP64 or FP32 matrix cores.
+void launch_wc(const Dims &d, const Bufs &b, hipStream_t s);
+
+// S_next, K_minus, K_next, and the midpoint / regularised matrices.
+void launch_assemble(const Dims &d, const Bufs &b, int parity, bool initial, hipStream_t s);
+
+// In-place lower Cholesky of `count` matrices (pointers in A), each N x N.
+void launch_cholesky(const Dims &d, const Bufs &b, double2 *A0, double2 *A1, int count, hipStream_t s);
+
+// One RK4 step of Eq. 8 with the factors / matrices of the given parity.
+void launch_rk4(const Dims &d, const Bufs &b, int parity, hipStream_t s);
+
+// C = (L L^H)^-1 rhs with L = b.L[parity] (initial coefficients).
+void launch_solve_initial(const Dims &d, const Bufs &b, int parity, double2 *rhs, hipStream_t s);
+
+// Copy x_k+1 -> x_k (end of a step).
+void launch_commit_positions(const Dims &d, const Bufs &b, hipStream_t s);
+
+// Observables into b.obs_out (layout in icwf_api.cpp).
+void launch_observables(const Dims &d, const Bufs &b, int parity, hipStream_t s);
+
+// Fill n int32 with a value (graph-safe replacement for a memset).
+void launch_fill_i32(int32_t *p, int n, int32_t v, hipStream_t s);
+
+}  // namespace icwf

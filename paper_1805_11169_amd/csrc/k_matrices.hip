@@ -1,0 +1,282 @@
+// The single-species matrices of Eq. 9 (9a, and the conditioned factors of
+// 9c-9d) and the two-body contraction of Eq. 9b.
+//
+// Single species (k_zgemm): out[b][a] = h sum_k conj(X[b][k]) Y[a][k] for the
+// pairs (X, Y) = (psi1, psi1) -> S1, (psi1, G1) -> E1, (psi2, psi2) -> S2,
+// (psi2, G2) -> E2, where G is the ket weighted by the coupling potential at
+// the ket's own trajectory: G1^a_i = W_c(r_i, R^a) psi1^a_i, G2^a_j =
+// W_c(r^a, R_j) psi2^a_j.  Complex = four real FP64 MFMA products.
+//
+// Two-body (k_wc): Wc[b][a] = hr hR sum_j conj(psi2^b_j) psi2^a_j
+//                             sum_i conj(psi1^b_i) psi1^a_i W_c(r_i, R_j)
+// for b <= a (the matrix is Hermitian).  The inner i-sum is a real GEMM whose
+// A operand, the pair product P1 = conj(psi1^b) psi1^a, is generated in
+// registers (never stored) and whose B operand is the W_c table; the j-sum
+// with the pair product P2 is fused into the epilogue of every 32-wide j
+// tile.  FP64: v_mfma_f64_16x16x4 throughout.  Mixed: P1 and the table in
+// FP32 on v_mfma_f32_16x16x4 with FP32 accumulation over i inside a j tile,
+// the epilogue and the sum over j tiles in FP64.
+#include "icwf_plan.hpp"
+
+namespace icwf {
+
+namespace {
+
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+typedef float flt4 __attribute__((ext_vector_type(4)));
+
+__device__ inline dbl4 mfma(double a, double b, dbl4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ inline flt4 mfma(float a, float b, flt4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// ---------------------------------------------------------------- conditioned kets
+__global__ void k_cond_kets(const double2 *__restrict__ psi, int n, double x_min, double h,
+                            const double *__restrict__ cond_a, const double *__restrict__ cond_b, int species,
+                            ModelParams mp, double2 *__restrict__ Ga, double2 *__restrict__ Gb, int Np,
+                            const int32_t *__restrict__ flags) {
+    if (flags[kFlagHalt]) return;
+    const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (size_t)Np * n) return;
+    const int a = (int)(idx / n);
+    const int i = (int)(idx - (size_t)a * n);
+    const double x = x_min + i * h;
+    const double2 p = psi[idx];
+    double wa, wb;
+    if (species == 1) {
+        wa = model_wc(mp, x, cond_a[a]);
+        wb = model_wc(mp, x, cond_b[a]);
+    } else {
+        wa = model_wc(mp, cond_a[a], x);
+        wb = model_wc(mp, cond_b[a], x);
+    }
+    Ga[idx] = cscale(p, wa);
+    if (Gb) Gb[idx] = cscale(p, wb);
+}
+
+// ---------------------------------------------------------------- batched conj-NT complex GEMM
+struct ZBatch {
+    const double2 *X[6];
+    const double2 *Y[6];
+    double2 *out[6];
+    int K[6];
+    double scale[6];
+};
+
+// One wave per 32 x 32 output tile (2 x 2 MFMA fragments).  Lane l holds
+// A = X[b0 + 16 f + l%16][k], B = Y[a0 + 16 g + l%16][k], k split in four
+// contiguous quarters by l/16; accumulator register v of lane l is row
+// mfma_row_f64(l, v), column l%16 of its fragment.
+__global__ void __launch_bounds__(64) k_zgemm(ZBatch zb, int Np, const int32_t *__restrict__ flags) {
+    if (flags[kFlagHalt]) return;
+    const int z = blockIdx.z;
+    const double2 *__restrict__ X = zb.X[z];
+    const double2 *__restrict__ Y = zb.Y[z];
+    const int K = zb.K[z];
+    const int lane = threadIdx.x;
+    const int row = lane & 15, quarter = lane >> 4;
+    const int b0 = blockIdx.y * 32, a0 = blockIdx.x * 32;
+    const int q = K >> 2;
+    dbl4 re[2][2], im[2][2];
+#pragma unroll
+    for (int f = 0; f < 2; ++f)
+#pragma unroll
+        for (int g = 0; g < 2; ++g) {
+            re[f][g] = dbl4{0, 0, 0, 0};
+            im[f][g] = dbl4{0, 0, 0, 0};
+        }
+    const double2 *xp[2], *yp[2];
+#pragma unroll
+    for (int f = 0; f < 2; ++f) {
+        xp[f] = X + (size_t)(b0 + 16 * f + row) * K + quarter * q;
+        yp[f] = Y + (size_t)(a0 + 16 * f + row) * K + quarter * q;
+    }
+    for (int s = 0; s < q; ++s) {
+        double2 xv[2], yv[2];
+#pragma unroll
+        for (int f = 0; f < 2; ++f) {
+            xv[f] = xp[f][s];
+            yv[f] = yp[f][s];
+        }
+#pragma unroll
+        for (int f = 0; f < 2; ++f)
+#pragma unroll
+            for (int g = 0; g < 2; ++g) {
+                // conj(x) y = (xr yr + xi yi) + i (xr yi - xi yr)
+                re[f][g] = mfma(xv[f].x, yv[g].x, re[f][g]);
+                re[f][g] = mfma(xv[f].y, yv[g].y, re[f][g]);
+                im[f][g] = mfma(xv[f].x, yv[g].y, im[f][g]);
+                im[f][g] = mfma(-xv[f].y, yv[g].x, im[f][g]);
+            }
+    }
+    const double sc = zb.scale[z];
+    double2 *out = zb.out[z];
+#pragma unroll
+    for (int f = 0; f < 2; ++f)
+#pragma unroll
+        for (int g = 0; g < 2; ++g)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int b = b0 + 16 * f + mfma_row_f64(lane, v);
+                const int a = a0 + 16 * g + row;
+                out[(size_t)b * Np + a] = make_double2(sc * re[f][g][v], sc * im[f][g][v]);
+            }
+}
+
+// ---------------------------------------------------------------- two-body contraction
+template <typename T>
+struct WcTraits;
+template <>
+struct WcTraits<double> {
+    typedef dbl4 acc4;
+};
+template <>
+struct WcTraits<float> {
+    typedef flt4 acc4;
+};
+
+// Block = 4 waves on a 16 (b) x 16 (a) tile of the upper triangle (tile
+// index tb <= ta); wave w owns b = b_tile + 4w .. 4w + 3 against all 16 a.
+// MFMA rows are a, columns are j, k is i.
+template <typename T>
+__global__ void __launch_bounds__(256) k_wc(const double2 *__restrict__ psi1, const double2 *__restrict__ psi2,
+                                            const T *__restrict__ wtab, int nr, int nR, double scale,
+                                            double2 *__restrict__ Wc, int Np, const int32_t *__restrict__ flags) {
+    typedef typename WcTraits<T>::acc4 acc4;
+    if (flags[kFlagHalt]) return;
+    // triangle index -> (tb, ta), tb <= ta
+    const int t = blockIdx.x;
+    int ta = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+    while ((ta + 1) * (ta + 2) / 2 <= t) ++ta;
+    while (ta * (ta + 1) / 2 > t) --ta;
+    const int tb = t - ta * (ta + 1) / 2;
+
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int row = lane & 15, quarter = lane >> 4;
+    const int a_base = ta * 16;
+    const int b_base = tb * 16 + 4 * wave;
+    const int q = nr >> 2;
+
+    const double2 *pa = psi1 + (size_t)(a_base + row) * nr + quarter * q;
+    const double2 *pb[4];
+#pragma unroll
+    for (int bb = 0; bb < 4; ++bb) pb[bb] = psi1 + (size_t)(b_base + bb) * nr + quarter * q;
+
+    double2 wsum[4][4];   // [b][v]: partial Wc for (b_base + bb, a_base + mfma_row(T, lane, v))
+#pragma unroll
+    for (int bb = 0; bb < 4; ++bb)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) wsum[bb][v] = make_double2(0, 0);
+
+    for (int j0 = 0; j0 < nR; j0 += 32) {
+        acc4 acc[4][2][2];   // [b][re/im][j fragment]
+#pragma unroll
+        for (int bb = 0; bb < 4; ++bb)
+#pragma unroll
+            for (int c = 0; c < 2; ++c)
+#pragma unroll
+                for (int jf = 0; jf < 2; ++jf) acc[bb][c][jf] = acc4{0, 0, 0, 0};
+        const T *wrow = wtab + (size_t)(quarter * q) * nR + j0 + row;
+        for (int s = 0; s < q; ++s) {
+            const double2 xa = pa[s];
+            const T w0 = wrow[(size_t)s * nR];
+            const T w1 = wrow[(size_t)s * nR + 16];
+#pragma unroll
+            for (int bb = 0; bb < 4; ++bb) {
+                const double2 p = cmulc(pb[bb][s], xa);   // conj(psi1^b_i) psi1^a_i
+                const T pr = (T)p.x, pi = (T)p.y;
+                acc[bb][0][0] = mfma(pr, w0, acc[bb][0][0]);
+                acc[bb][1][0] = mfma(pi, w0, acc[bb][1][0]);
+                acc[bb][0][1] = mfma(pr, w1, acc[bb][0][1]);
+                acc[bb][1][1] = mfma(pi, w1, acc[bb][1][1]);
+            }
+        }
+        // epilogue: lane holds T(b, a = a_base + mfma_row(T, lane, v), j = j0 + 16 jf + row)
+#pragma unroll
+        for (int jf = 0; jf < 2; ++jf) {
+            const int j = j0 + 16 * jf + row;
+            double2 p2a[4];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) p2a[v] = psi2[(size_t)(a_base + mfma_row(T(0), lane, v)) * nR + j];
+#pragma unroll
+            for (int bb = 0; bb < 4; ++bb) {
+                const double2 p2b = psi2[(size_t)(b_base + bb) * nR + j];
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const double2 P2 = cmulc(p2b, p2a[v]);
+                    const double2 Tv = make_double2((double)acc[bb][0][jf][v], (double)acc[bb][1][jf][v]);
+                    wsum[bb][v] = cadd(wsum[bb][v], cmul(P2, Tv));
+                }
+            }
+        }
+    }
+    // sum over the 16 j columns held by the lanes of each quarter
+#pragma unroll
+    for (int bb = 0; bb < 4; ++bb)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            double2 x = wsum[bb][v];
+#pragma unroll
+            for (int off = 8; off > 0; off >>= 1) {
+                x.x += __shfl_xor(x.x, off, 16);
+                x.y += __shfl_xor(x.y, off, 16);
+            }
+            if (row == 0) {
+                const int b = b_base + bb, a = a_base + mfma_row(T(0), lane, v);
+                Wc[(size_t)b * Np + a] = cscale(x, scale);
+            }
+        }
+}
+
+}  // namespace
+
+void launch_cond_kets(const Dims &d, const Bufs &b, hipStream_t s) {
+    const int Np = padded(d.N);
+    size_t tot = (size_t)Np * d.nr;
+    hipLaunchKernelGGL(k_cond_kets, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, b.psi1, d.nr, d.r_min,
+                       d.hr, b.R, b.R_new, 1, d.mp, b.G1a, b.G1b, Np, b.flags);
+    tot = (size_t)Np * d.nR;
+    hipLaunchKernelGGL(k_cond_kets, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, b.psi2, d.nR, d.R_min,
+                       d.hR, b.r, b.r_new, 2, d.mp, b.G2a, b.G2b, Np, b.flags);
+}
+
+void launch_single_species(const Dims &d, const Bufs &b, bool both, hipStream_t s) {
+    const int Np = padded(d.N);
+    ZBatch zb{};
+    int c = 0;
+    auto add = [&](const double2 *X, const double2 *Y, double2 *o, int K, double sc) {
+        zb.X[c] = X;
+        zb.Y[c] = Y;
+        zb.out[c] = o;
+        zb.K[c] = K;
+        zb.scale[c] = sc;
+        ++c;
+    };
+    add(b.psi1, b.psi1, b.S1, d.nr, d.hr);
+    add(b.psi2, b.psi2, b.S2, d.nR, d.hR);
+    add(b.psi1, b.G1a, b.E1a, d.nr, d.hr);
+    add(b.psi2, b.G2a, b.E2a, d.nR, d.hR);
+    if (both) {
+        add(b.psi1, b.G1b, b.E1b, d.nr, d.hr);
+        add(b.psi2, b.G2b, b.E2b, d.nR, d.hR);
+    }
+    hipLaunchKernelGGL(k_zgemm, dim3(Np / 32, Np / 32, c), dim3(64), 0, s, zb, Np, b.flags);
+}
+
+void launch_wc(const Dims &d, const Bufs &b, hipStream_t s) {
+    const int Np = padded(d.N);
+    const int T16 = Np / 16;
+    const int blocks = T16 * (T16 + 1) / 2;
+    const double scale = d.hr * d.hR;
+    if (d.prec == 1) {
+        hipLaunchKernelGGL(k_wc<float>, dim3(blocks), dim3(256), 0, s, b.psi1, b.psi2, b.wc32, d.nr, d.nR, scale,
+                           b.Wc, Np, b.flags);
+    } else {
+        hipLaunchKernelGGL(k_wc<double>, dim3(blocks), dim3(256), 0, s, b.psi1, b.psi2, b.wc64, d.nr, d.nR, scale,
+                           b.Wc, Np, b.flags);
+    }
+}
+
+}  // namespace icwf

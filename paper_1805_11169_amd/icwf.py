@@ -1,0 +1,240 @@
+"""Python binding of the ICWF C ABI (include/icwf.h): argument marshalling only.
+
+Every step of the method runs in libicwf.so's HIP kernels.  PyTorch provides
+the device workspace (one uint8 tensor) and the HIP stream; nothing is
+computed here.  If the library is not built, or no GPU is present, the calls
+raise -- there is no fallback.
+"""
+
+import ctypes
+import os
+from ctypes import POINTER, byref, c_char_p, c_double, c_int32, c_int64, c_size_t, c_void_p
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libicwf.so")
+
+OK, EINVAL, ENOMEM, EDEVICE, ENONFINITE, ENODE, ESOLVE, ESTATE = 0, -1, -2, -3, -4, -5, -6, -7
+MODEL_SHIN_METIU, MODEL_CAVITY = 1, 2
+PREC_FP64, PREC_MIXED = 0, 1
+
+# the entry points include/icwf.h declares
+EXPORTS = ("icwf_workspace_bytes", "icwf_create", "icwf_step", "icwf_sync", "icwf_observables",
+           "icwf_get_state", "icwf_get_matrices", "icwf_velocities", "icwf_set_timing", "icwf_kernel_time",
+           "icwf_destroy", "icwf_last_error", "icwf_status_string")
+
+
+class Config(ctypes.Structure):
+    _fields_ = [("n_traj", c_int32), ("n_r", c_int32), ("n_R", c_int32),
+                ("r_min", c_double), ("r_max", c_double), ("R_min", c_double), ("R_max", c_double),
+                ("m_r", c_double), ("m_R", c_double), ("dt", c_double),
+                ("model", c_int32), ("model_params", c_double * 8), ("tikhonov_eps", c_double),
+                ("precision", c_int32), ("n_bo", c_int32)]
+
+
+_DP = POINTER(c_double)
+
+
+class Obs(ctypes.Structure):
+    _fields_ = [("t", c_double), ("step", c_int64), ("norm", c_double),
+                ("rho_r", _DP), ("rho_R", _DP), ("pop", _DP), ("D", _DP),
+                ("r", _DP), ("R", _DP), ("C", _DP),
+                ("n_out_of_box", c_int32), ("min_abs_psi", c_double)]
+
+
+class ICWFError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"{status_string(status)}: {message}")
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    """The loaded libicwf.so (raises if it is not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run `python -m paper_1805_11169_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        L.icwf_workspace_bytes.argtypes = [POINTER(Config)]
+        L.icwf_workspace_bytes.restype = c_size_t
+        L.icwf_create.argtypes = [POINTER(Config), _DP, _DP, _DP, _DP, _DP, _DP, _DP, c_void_p, c_size_t,
+                                  c_void_p, POINTER(c_void_p)]
+        L.icwf_create.restype = c_int32
+        L.icwf_step.argtypes = [c_void_p, c_int32]
+        L.icwf_step.restype = c_int32
+        L.icwf_sync.argtypes = [c_void_p]
+        L.icwf_sync.restype = c_int32
+        L.icwf_observables.argtypes = [c_void_p, POINTER(Obs)]
+        L.icwf_observables.restype = c_int32
+        L.icwf_get_state.argtypes = [c_void_p, _DP, _DP, _DP, _DP, _DP]
+        L.icwf_get_state.restype = c_int32
+        L.icwf_get_matrices.argtypes = [c_void_p, _DP, _DP, _DP]
+        L.icwf_get_matrices.restype = c_int32
+        L.icwf_velocities.argtypes = [c_void_p, _DP, _DP, _DP]
+        L.icwf_velocities.restype = c_int32
+        L.icwf_set_timing.argtypes = [c_void_p, c_int32]
+        L.icwf_set_timing.restype = c_int32
+        L.icwf_kernel_time.argtypes = [c_void_p, c_char_p, POINTER(c_int64), POINTER(c_double)]
+        L.icwf_kernel_time.restype = c_int32
+        L.icwf_destroy.argtypes = [c_void_p]
+        L.icwf_destroy.restype = None
+        L.icwf_last_error.argtypes = [c_void_p]
+        L.icwf_last_error.restype = c_char_p
+        L.icwf_status_string.argtypes = [c_int32]
+        L.icwf_status_string.restype = c_char_p
+        _lib = L
+    return _lib
+
+
+def status_string(st):
+    return lib().icwf_status_string(st).decode()
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(_DP)
+
+
+def _f64(a, n=None):
+    """Contiguous float64 view; complex arrays become interleaved (re, im)."""
+    if a is None:
+        return None
+    a = np.ascontiguousarray(a)
+    if np.iscomplexobj(a):
+        a = np.ascontiguousarray(a, dtype=np.complex128).view(np.float64)
+    else:
+        a = np.ascontiguousarray(a, dtype=np.float64)
+    return a
+
+
+def make_config(n_traj, n_r, n_R, r_box, R_box, m_r, m_R, dt, model, model_params, eps=1e-8,
+                precision=PREC_FP64, n_bo=0):
+    c = Config()
+    c.n_traj, c.n_r, c.n_R = int(n_traj), int(n_r), int(n_R)
+    c.r_min, c.r_max = float(r_box[0]), float(r_box[1])
+    c.R_min, c.R_max = float(R_box[0]), float(R_box[1])
+    c.m_r, c.m_R, c.dt = float(m_r), float(m_R), float(dt)
+    c.model = int(model)
+    params = list(model_params) + [0.0] * (8 - len(model_params))
+    for i in range(8):
+        c.model_params[i] = float(params[i])
+    c.tikhonov_eps = float(eps)
+    c.precision = int(precision)
+    c.n_bo = int(n_bo)
+    return c
+
+
+def config_from_workload(wl, precision=PREC_FP64, eps=None):
+    return make_config(wl.n_traj, wl.n_r, wl.n_R, (wl.r_min, wl.r_max), (wl.R_min, wl.R_max), wl.m_r, wl.m_R,
+                       wl.dt, wl.model, wl.model_params, wl.eps if eps is None else eps, precision, wl.n_bo)
+
+
+def workspace_bytes(cfg):
+    return int(lib().icwf_workspace_bytes(byref(cfg)))
+
+
+class Simulation:
+    """One ICWF simulation on one GPU (icwf_create ... icwf_destroy)."""
+
+    def __init__(self, cfg, r0, R0, psi1, psi2, C0=None, b0=None, bo=None, device=0, stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("the ICWF library needs a GPU; none is visible")
+        L = lib()
+        self.cfg = cfg
+        self.N, self.n_r, self.n_R, self.n_bo = cfg.n_traj, cfg.n_r, cfg.n_R, cfg.n_bo
+        nbytes = L.icwf_workspace_bytes(byref(cfg))
+        if nbytes == 0:
+            raise ICWFError(EINVAL, "invalid configuration")
+        dev = torch.device("cuda", device) if isinstance(device, int) else torch.device(device)
+        self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
+        base = self.ws.data_ptr()
+        aligned = (base + 255) & ~255
+        self.stream = stream if stream is not None else torch.cuda.current_stream(dev)
+        keep = [_f64(r0), _f64(R0), _f64(psi1), _f64(psi2), _f64(C0), _f64(b0), _f64(bo)]
+        handle = c_void_p()
+        st = L.icwf_create(byref(cfg), *[_ptr(a) for a in keep], c_void_p(aligned), c_size_t(nbytes),
+                           c_void_p(self.stream.cuda_stream), byref(handle))
+        if st != OK:
+            raise ICWFError(st, L.icwf_last_error(None).decode())
+        self.h = handle
+
+    @classmethod
+    def from_workload(cls, wl, precision=PREC_FP64, C0=None, **kw):
+        cfg = config_from_workload(wl, precision)
+        return cls(cfg, wl.r0, wl.R0, wl.psi1, wl.psi2, C0=C0, b0=None if C0 is not None else wl.b0,
+                   bo=wl.bo, **kw)
+
+    def _check(self, st):
+        if st != OK:
+            raise ICWFError(st, lib().icwf_last_error(self.h).decode())
+        return st
+
+    def step(self, n=1):
+        self._check(lib().icwf_step(self.h, int(n)))
+
+    def sync(self):
+        return self._check(lib().icwf_sync(self.h))
+
+    def observables(self, check=True):
+        N, nr, nR, nb = self.N, self.n_r, self.n_R, self.n_bo
+        out = dict(rho_r=np.zeros(nr), rho_R=np.zeros(nR), pop=np.zeros(max(nb, 1)),
+                   D=np.zeros(max(nb * nb, 1)), r=np.zeros(N), R=np.zeros(N), C=np.zeros(2 * N))
+        o = Obs()
+        for k, v in out.items():
+            setattr(o, k, _ptr(v))
+        st = lib().icwf_observables(self.h, byref(o))
+        if check:
+            self._check(st)
+        res = dict(t=o.t, step=o.step, norm=o.norm, rho_r=out["rho_r"], rho_R=out["rho_R"],
+                   r=out["r"], R=out["R"], C=out["C"].view(np.complex128), n_out_of_box=o.n_out_of_box,
+                   min_abs_psi=o.min_abs_psi, status=st)
+        if nb:
+            res["pop"] = out["pop"][:nb]
+            res["D"] = out["D"][:nb * nb].reshape(nb, nb)
+        return res
+
+    def state(self):
+        N, nr, nR = self.N, self.n_r, self.n_R
+        r, R = np.zeros(N), np.zeros(N)
+        p1, p2 = np.zeros((N, nr), np.complex128), np.zeros((N, nR), np.complex128)
+        C = np.zeros(N, np.complex128)
+        self._check(lib().icwf_get_state(self.h, _ptr(r), _ptr(R), _ptr(p1.view(np.float64)),
+                                         _ptr(p2.view(np.float64)), _ptr(C.view(np.float64))))
+        return dict(r=r, R=R, psi1=p1, psi2=p2, C=C)
+
+    def matrices(self):
+        N = self.N
+        S, K, W = (np.zeros((N, N), np.complex128) for _ in range(3))
+        self._check(lib().icwf_get_matrices(self.h, _ptr(S.view(np.float64)), _ptr(K.view(np.float64)),
+                                            _ptr(W.view(np.float64))))
+        return S, K, W
+
+    def velocities(self):
+        N = self.N
+        vr, vR = np.zeros(N), np.zeros(N)
+        pa = np.zeros(N, np.complex128)
+        self._check(lib().icwf_velocities(self.h, _ptr(vr), _ptr(vR), _ptr(pa.view(np.float64))))
+        return vr, vR, pa
+
+    def set_timing(self, enable):
+        self._check(lib().icwf_set_timing(self.h, 1 if enable else 0))
+
+    def kernel_time(self, name):
+        n, ms = c_int64(), c_double()
+        self._check(lib().icwf_kernel_time(self.h, name.encode(), byref(n), byref(ms)))
+        return n.value, ms.value
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().icwf_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

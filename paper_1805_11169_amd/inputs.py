@@ -208,6 +208,38 @@ def cavity(N, n_r=1024, n_R=256, r_box=(-50.0, 50.0), R_box=(-20.0, 20.0), param
                           r_box, R_box, 1.0, 1.0, dt, n_steps, eps, phi_V, chi0, sample_R, seed, n_bo)
 
 
+def gaussian_basis(N, n_r=128, n_R=64, r_box=(-20.0, 20.0), R_box=(-6.0, 6.0), model=MODEL_SHIN_METIU,
+                   params=None, m_R=1836.0, dt=0.05, eps=1e-8, seed=0, name=None):
+    """A generic (not rank-one) basis for parity checks: N random complex Gaussian
+    CWFs per species (random centre, width, momentum), unit-normalised, random
+    trajectory positions inside the Gaussians' support and random unit-norm C0."""
+    if params is None:
+        params = SHIN_METIU_PARAMS if model == MODEL_SHIN_METIU else CAVITY_PARAMS
+    rng = np.random.default_rng(seed)
+    r, hr = _grid(*r_box, n_r)
+    R, hR = _grid(*R_box, n_R)
+    Lr, LR = r_box[1] - r_box[0], R_box[1] - R_box[0]
+
+    def gaussians(x, h, L, lo, n):
+        c = lo + L * rng.uniform(0.3, 0.7, (n, 1))
+        w = L * rng.uniform(0.04, 0.1, (n, 1))
+        k = rng.uniform(-0.3, 0.3, (n, 1)) * np.pi / h
+        g = np.exp(-(x[None, :] - c) ** 2 / (2 * w * w) + 1j * k * x[None, :])
+        return g / np.sqrt(h * np.sum(np.abs(g) ** 2, axis=1, keepdims=True)), c[:, 0], w[:, 0]
+
+    psi1, c1, w1 = gaussians(r, hr, Lr, r_box[0], N)
+    psi2, c2, w2 = gaussians(R, hR, LR, R_box[0], N)
+    r0 = c1 + 0.5 * w1 * rng.standard_normal(N)
+    R0 = c2 + 0.5 * w2 * rng.standard_normal(N)
+    C0 = rng.standard_normal(N) + 1j * rng.standard_normal(N)
+    C0 /= np.linalg.norm(C0)
+    m_R_ = m_R if model == MODEL_SHIN_METIU else 1.0
+    wl = Workload(name or f"gaussians_N{N}_{n_r}x{n_R}", model, list(params), N, n_r, n_R, r_box[0],
+                  r_box[1], R_box[0], R_box[1], 1.0, m_R_, dt, 0, eps, r0, R0, psi1.astype(np.complex128),
+                  psi2.astype(np.complex128), np.zeros(N, np.complex128), None, dict(C0=C0, seed=seed))
+    return wl
+
+
 # Named workloads: the parity case, the headline throughput case, the cavity
 # case and the large-grid contraction stress case.
 def preset(name, **kw):

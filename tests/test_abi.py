@@ -1,0 +1,85 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, exports
+every entry point include/icwf.h declares, sizes workspaces, and rejects
+invalid configurations before touching the device."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1805_11169_amd import icwf
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_entry_points():
+    text = open(os.path.join(ROOT, "include", "icwf.h")).read()
+    decl = r"^(?:size_t|icwf_status|void|const char \*)\s*(icwf_[a-z_]+)\s*\("
+    return sorted(set(re.findall(decl, text, flags=re.MULTILINE)))
+
+
+def test_header_and_binding_agree():
+    assert declared_entry_points() == sorted(icwf.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    if not os.path.exists(icwf.LIB_PATH):
+        pytest.fail("libicwf.so is not built (python -m paper_1805_11169_amd.build)")
+    L = ctypes.CDLL(icwf.LIB_PATH)
+    for name in declared_entry_points():
+        assert hasattr(L, name), name
+
+
+def _cfg(**kw):
+    base = dict(n_traj=64, n_r=512, n_R=256, r_box=(-75, 75), R_box=(-9, 9), m_r=1.0, m_R=1836.0, dt=0.1,
+                model=icwf.MODEL_SHIN_METIU, model_params=[19.0, 5.0, 3.1, 4.0], eps=1e-8, n_bo=3)
+    base.update(kw)
+    return icwf.make_config(**base)
+
+
+def test_workspace_bytes_scales_with_n_squared():
+    small = icwf.workspace_bytes(_cfg(n_traj=64))
+    big = icwf.workspace_bytes(_cfg(n_traj=1024))
+    assert small > 0 and big > 0
+    # sixteen N x N complex matrices dominate at N = 1024
+    assert big > 16 * 1024 * 1024 * 16
+    assert icwf.workspace_bytes(_cfg(n_traj=65)) == icwf.workspace_bytes(_cfg(n_traj=128))
+
+
+@pytest.mark.parametrize("bad", [dict(n_traj=0), dict(n_traj=5000), dict(n_r=500), dict(n_R=8),
+                                 dict(r_box=(1, 1)), dict(m_r=0.0), dict(dt=-0.1), dict(eps=-1.0),
+                                 dict(model=7), dict(precision=3), dict(n_bo=-1), dict(n_bo=1000),
+                                 dict(model_params=[19.0, 0.0, 3.1, 4.0])])
+def test_invalid_configs_are_rejected_on_the_host(bad):
+    cfg = _cfg(**bad)
+    assert icwf.workspace_bytes(cfg) == 0
+    L = icwf.lib()
+    h = ctypes.c_void_p()
+    one = (ctypes.c_double * 8192)()
+    st = L.icwf_create(ctypes.byref(cfg), one, one, one, one, None, one, one, ctypes.c_void_p(256),
+                       ctypes.c_size_t(1 << 40), None, ctypes.byref(h))
+    assert st == icwf.EINVAL
+    assert L.icwf_last_error(None)
+
+
+def test_too_small_workspace_and_missing_inputs():
+    cfg = _cfg(n_traj=4, n_r=32, n_R=32, n_bo=0)
+    L = icwf.lib()
+    h = ctypes.c_void_p()
+    one = (ctypes.c_double * 4096)()
+    need = icwf.workspace_bytes(cfg)
+    st = L.icwf_create(ctypes.byref(cfg), one, one, one, one, None, one, None, ctypes.c_void_p(256),
+                       ctypes.c_size_t(need - 1), None, ctypes.byref(h))
+    assert st == icwf.ENOMEM
+    st = L.icwf_create(ctypes.byref(cfg), one, one, one, one, None, None, None, ctypes.c_void_p(256),
+                       ctypes.c_size_t(need), None, ctypes.byref(h))
+    assert st == icwf.EINVAL          # neither C0 nor b0
+    nan = (ctypes.c_double * 4096)(*([float("nan")] * 4096))
+    st = L.icwf_create(ctypes.byref(cfg), nan, one, one, one, None, one, None, ctypes.c_void_p(256),
+                       ctypes.c_size_t(need), None, ctypes.byref(h))
+    assert st == icwf.ENONFINITE
+    st = L.icwf_create(ctypes.byref(cfg), one, one, one, one, None, one, None, ctypes.c_void_p(257),
+                       ctypes.c_size_t(need), None, ctypes.byref(h))
+    assert st == icwf.EINVAL          # misaligned workspace
+    assert icwf.status_string(icwf.ESOLVE) == "ICWF_ESOLVE"

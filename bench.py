@@ -1,0 +1,144 @@
+"""ICWF throughput benchmark on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp64|mixed] [--no-cpu-baseline]
+
+One step = one full pass of the ICWF hot path (Bohmian velocities and
+trajectory update, split-operator propagation of all 2N conditional
+wavefunctions, the Eq. 9 matrices including the N^2 two-body contraction,
+two Tikhonov-regularised Cholesky factorisations and the RK4 coefficient
+update) on the Shin-Metiu workload with N = 1024 trajectories on a 512 x 256
+grid.  Inputs are seeded and synthetic and resident in HBM before timing.
+
+Prints one JSON line: traj-steps/s over exactly K timed steps, the roofline
+of the dominant kernel (the two-body contraction, timed live with HIP events
+on the stream it runs on), and the FP64 oracle timed on a bounded sample on the
+host cores.
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK = {"fp64": 78.6, "mixed": 157.3}          # dense matrix-core TFLOP/s of MI355X (FP64, FP32)
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=20)
+    p.add_argument("--warmup", type=int, default=3)
+    p.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
+    p.add_argument("--workload", default="sm_n1024")
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--cpu-steps", type=int, default=2)
+    return p.parse_args()
+
+
+def algorithmic_counts(N, nr, nR):
+    """Flops / bytes the method must do per step (not what a kernel happens to do)."""
+    wc = 2.0 * N * (N + 1) * nr * nR                     # Hermitian two-body contraction (Eq. 9b)
+    single = 4.0 * N * (N + 1) * (nr + nR) + 16.0 * N * N * (nr + nR)   # S1, S2 and E1, E2 at two conditionings
+    prop_bytes = 2.0 * N * (nr + nR) * 16                # read + write every CWF once (complex128)
+    return wc, single, prop_bytes
+
+
+def cpu_baseline(wl, steps):
+    import numpy as np  # noqa: F401
+    import oracle
+    from oracle import icwf as oicwf
+    from oracle import models
+    setup = oicwf.Setup(models.make("shin_metiu", wl.model_params), wl.r_min, wl.r_max, wl.n_r, wl.R_min,
+                        wl.R_max, wl.n_R, wl.m_r, wl.m_R, wl.dt, wl.eps)
+    st = oicwf.init(setup, wl.r0, wl.R0, wl.psi1, wl.psi2, b0=wl.b0)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        st = oicwf.step(setup, st)
+    dt = time.perf_counter() - t0
+    return {"value": wl.n_traj * steps / dt, "unit": "traj-steps/s", "cores": oracle.blas_threads() or os.cpu_count(),
+            "kind": "oracle",
+            "sample": f"{steps} oracle steps of the same workload (N={wl.n_traj}, {wl.n_r}x{wl.n_R}) from t=0, "
+                      f"{dt:.1f} s on the host"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU sharding is a design "
+              "in DESIGN.md, not a measured path", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    from paper_1805_11169_amd import icwf, inputs
+
+    wl = inputs.preset(args.workload, n_bo=0)
+    prec = icwf.PREC_MIXED if args.precision == "mixed" else icwf.PREC_FP64
+    N, nr, nR = wl.n_traj, wl.n_r, wl.n_R
+    sim = icwf.Simulation.from_workload(wl, precision=prec, device=0)
+    stream = sim.stream
+
+    sim.step(args.warmup)
+    sim.sync()
+    sim.set_timing(True)          # kernel-by-kernel launches with an event pair around each kernel
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(args.steps)
+    sim.sync()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+
+    kt = {}
+    for name in ("wc_contract", "zgemm", "velocity", "propagate", "assemble", "cholesky", "rk4"):
+        n, ms = sim.kernel_time(name)
+        kt[name] = (n, ms)
+    sim.set_timing(False)
+    obs = sim.observables()
+    sim.close()
+    del stream
+
+    wc_flops, single_flops, prop_bytes = algorithmic_counts(N, nr, nR)
+    n_wc, ms_wc = kt["wc_contract"]
+    wc_avg_s = ms_wc / 1e3 / n_wc
+    achieved = wc_flops / wc_avg_s / 1e12
+    n_zg, ms_zg = kt["zgemm"]
+    build_tflops = (wc_flops + single_flops) / ((ms_wc + ms_zg) / 1e3 / n_wc) / 1e12
+    n_pr, ms_pr = kt["propagate"]
+    prop_gbs = prop_bytes / (ms_pr / 1e3 / n_pr) / 1e9
+
+    value = N * args.steps / elapsed
+    line = {
+        "metric": "ICWF traj-steps/s at N=1024",
+        "value": value,
+        "unit": "traj-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if prec == icwf.PREC_FP64 else "f32-contraction/f64",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "model": "shin_metiu", "n_traj": N, "n_r": nr, "n_R": nR,
+                   "dt": wl.dt, "precision": args.precision, "timing": "kernel-by-kernel with HIP events"},
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK[args.precision], "unit": "TFLOP/s",
+                     "frac": achieved / PEAK[args.precision], "traffic": None,
+                     "kernel": "wc_contract", "flops_per_launch": wc_flops, "avg_launch_ms": wc_avg_s * 1e3},
+        "sh_build_tflops": build_tflops,
+        "propagation": {"achieved_gbs": prop_gbs, "peak_gbs": HBM_PEAK_GBS, "frac": prop_gbs / HBM_PEAK_GBS,
+                        "avg_launch_ms": ms_pr / n_pr},
+        "kernel_ms_per_step": {k: (ms / n if n else None) for k, (n, ms) in kt.items()},
+        "final_norm": obs["norm"],
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(wl, args.cpu_steps)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -55,6 +55,7 @@ Bufs carve(const icwf_config &c, char *base, size_t *total) {
     b.Cacc = L.take<double2>(Np);
     b.Cstage = L.take<double2>(Np);
     b.y = L.take<double2>(Np);
+    b.rhs = L.take<double2>(Np);
     b.vstat_r = L.take<double>(nr);
     b.vstat_R = L.take<double>(nR);
     b.kin_r = L.take<double2>(nr);
@@ -63,6 +64,8 @@ Bufs carve(const icwf_config &c, char *base, size_t *total) {
     b.tw_R = L.take<double2>(nR);
     b.wc64 = L.take<double>(nr * nR);
     b.wc32 = L.take<float>(nr * nR);
+    b.lr_u = L.take<double>(icwf::kLowRankMax * nr);
+    b.lr_v = L.take<double>(icwf::kLowRankMax * nR);
     b.sinc_r = L.take<double>(Np * nr);
     b.dsinc_r = L.take<double>(Np * nr);
     b.sinc_R = L.take<double>(Np * nR);
@@ -79,6 +82,8 @@ Bufs carve(const icwf_config &c, char *base, size_t *total) {
                         &b.Smat[1], &b.Kmat[0], &b.Kmat[1], &b.Kminus, &b.Kmid, &b.L[0], &b.L[1], &b.Lmid};
     for (double2 **m : mats) *m = L.take<double2>(Np * Np);
     b.chol_diag = L.take<double2>(2 * icwf::kCholNb * icwf::kCholNb);
+    b.xsol = L.take<double2>(Np);
+    b.solve_sync = L.take<int32_t>(130);
     b.bo = L.take<double>(std::max<size_t>(1, nR * nbo * nr));
     b.obs_u = L.take<double2>(Np * std::max(nr, nR));
     b.obs_chi = L.take<double2>(std::max<size_t>(1, nbo * nR));
@@ -130,6 +135,41 @@ double h_wc(const icwf_config &c, double r, double R) {
     if (c.model == ICWF_MODEL_SHIN_METIU) return -h_erfx(r - R, p[1]);
     return p[3] * R * r;
 }
+
+// Adaptive cross approximation with full pivoting of an n x m row-major
+// table: W = sum_k u_k v_k^T + R.  On return W holds the residual R; the
+// factors are appended to U ([k][n]) and V ([k][m]).  Stops when
+// max |R| <= tol max |W| or after kmax terms.  (Each step takes the largest
+// remaining entry as pivot, so the residual's maximum never grows.)
+int cross_approximation(std::vector<double> &W, int n, int m, double tol, int kmax, std::vector<double> &U,
+                        std::vector<double> &V) {
+    double wmax = 0.0;
+    for (double w : W) wmax = std::max(wmax, std::fabs(w));
+    int k = 0;
+    for (; k < kmax; ++k) {
+        size_t piv = 0;
+        double best = -1.0;
+        for (size_t e = 0; e < W.size(); ++e)
+            if (std::fabs(W[e]) > best) {
+                best = std::fabs(W[e]);
+                piv = e;
+            }
+        if (best <= tol * wmax || best == 0.0) break;
+        const int pi = (int)(piv / m), pj = (int)(piv % m);
+        const double p = W[piv];
+        std::vector<double> u(n), v(m);
+        for (int i = 0; i < n; ++i) u[i] = W[(size_t)i * m + pj];
+        for (int j = 0; j < m; ++j) v[j] = W[(size_t)pi * m + j] / p;
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < m; ++j) W[(size_t)i * m + j] -= u[i] * v[j];
+        U.insert(U.end(), u.begin(), u.end());
+        V.insert(V.end(), v.begin(), v.end());
+    }
+    return k;
+}
+
+// Relative size of the residual the mixed form leaves to FP32.
+constexpr double kMixedSplitTol = 1e-4;
 
 struct Timer {
     std::vector<std::pair<hipEvent_t, hipEvent_t>> recs;
@@ -225,6 +265,10 @@ icwf_status device_status(icwf_sim *s) {
     if (flags[icwf::kFlagSolve]) {
         s->status = ICWF_ESOLVE;
         return fail(s, ICWF_ESOLVE, "S + eps I is not numerically positive definite");
+    }
+    if (flags[icwf::kFlagHang]) {
+        s->status = ICWF_EDEVICE;
+        return fail(s, ICWF_EDEVICE, "a device-side wait between work-groups timed out");
     }
     if (flags[icwf::kFlagNonfinite]) {
         s->status = ICWF_ENONFINITE;
@@ -349,6 +393,14 @@ icwf_status icwf_create(const icwf_config *cfg, const double *r0, const double *
         }
     if (!finite(vr.data(), nr) || !finite(vR.data(), nR) || !finite(wc.data(), wc.size()))
         return cleanup_fail(ICWF_ENONFINITE, "the model is singular on the grid");
+    // mixed form: W_c = (rank-K part, FP64) + (residual, FP32 matrix cores)
+    std::vector<double> lr_u, lr_v;
+    d.lr_rank = 0;
+    if (cfg->precision == ICWF_PREC_MIXED) {
+        std::vector<double> res = wc;
+        d.lr_rank = cross_approximation(res, nr, nR, kMixedSplitTol, icwf::kLowRankMax, lr_u, lr_v);
+        for (size_t e = 0; e < res.size(); ++e) wc32[e] = static_cast<float>(res[e]);
+    }
     auto fill_k = [&](std::vector<double2> &kin, std::vector<double2> &tw, int n, double h, double m) {
         for (int k = 0; k < n; ++k) {
             const int kk = (k <= n / 2) ? k : k - n;
@@ -384,10 +436,14 @@ icwf_status icwf_create(const icwf_config *cfg, const double *r0, const double *
     CREATE_HIP(hipMemcpyAsync(b.tw_R, tw_R.data(), sizeof(double2) * nR, hipMemcpyHostToDevice, st));
     CREATE_HIP(hipMemcpyAsync(b.wc64, wc.data(), sizeof(double) * wc.size(), hipMemcpyHostToDevice, st));
     CREATE_HIP(hipMemcpyAsync(b.wc32, wc32.data(), sizeof(float) * wc32.size(), hipMemcpyHostToDevice, st));
+    if (d.lr_rank > 0) {
+        CREATE_HIP(hipMemcpyAsync(b.lr_u, lr_u.data(), sizeof(double) * lr_u.size(), hipMemcpyHostToDevice, st));
+        CREATE_HIP(hipMemcpyAsync(b.lr_v, lr_v.data(), sizeof(double) * lr_v.size(), hipMemcpyHostToDevice, st));
+    }
     if (nbo > 0)
         CREATE_HIP(hipMemcpyAsync(b.bo, bo_states, sizeof(double) * (size_t)nR * nbo * nr, hipMemcpyHostToDevice, st));
     if (C0) CREATE_HIP(hipMemcpyAsync(b.C, C0, sizeof(double2) * N, hipMemcpyHostToDevice, st));
-    else CREATE_HIP(hipMemcpyAsync(b.y, b0, sizeof(double2) * N, hipMemcpyHostToDevice, st));
+    else CREATE_HIP(hipMemcpyAsync(b.Cstage, b0, sizeof(double2) * N, hipMemcpyHostToDevice, st));
 
     // ---- initial S_0, K_0 and the factor of S_0 + eps I
     icwf::launch_cond_kets(d, b, st);
@@ -395,7 +451,7 @@ icwf_status icwf_create(const icwf_config *cfg, const double *r0, const double *
     icwf::launch_wc(d, b, st);
     icwf::launch_assemble(d, b, 0, true, st);
     icwf::launch_cholesky(d, b, b.L[0], b.L[0], 1, st);
-    if (!C0) icwf::launch_solve_initial(d, b, 0, b.y, st);
+    if (!C0) icwf::launch_solve_initial(d, b, 0, b.Cstage, st);
     CREATE_HIP(hipGetLastError());
     const icwf_status ds = device_status(s);
     if (ds != ICWF_OK) {

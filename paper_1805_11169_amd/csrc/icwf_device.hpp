@@ -91,6 +91,24 @@ __device__ inline int mfma_row(float, int lane, int v) { return mfma_row_f32(lan
 
 // Device status flags (one int32 each, in the workspace).
 enum Flag : int32_t { kFlagHalt = 0, kFlagNode = 1, kFlagSolve = 2, kFlagNonfinite = 3, kFlagOut = 4,
-                      kNumFlags = 8 };
+                      kFlagHang = 5, kNumFlags = 8 };
+
+// Bounded wait of one thread for an int32 flag written by another
+// work-group (agent-scope acquire).  Every wait ends: after ~2^22 polls it
+// raises kFlagHang and kFlagHalt and returns false, and the caller goes on
+// with whatever is in memory (the host then reports the error).
+__device__ inline bool wait_flag(const int32_t *flag, int32_t *status) {
+    for (int it = 0; it < (1 << 22); ++it) {
+        if (__hip_atomic_load(flag, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != 0) return true;
+        __builtin_amdgcn_s_sleep(2);
+    }
+    atomicOr(&status[kFlagHang], 1);
+    atomicOr(&status[kFlagHalt], 1);
+    return false;
+}
+
+__device__ inline void set_flag(int32_t *flag) {
+    __hip_atomic_store(flag, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
 
 }  // namespace icwf

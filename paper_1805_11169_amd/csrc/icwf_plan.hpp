@@ -12,6 +12,7 @@ namespace icwf {
 
 struct Dims {
     int N, nr, nR, n_bo, prec;
+    int lr_rank;                          // rank of the FP64 part of the mixed contraction
     double r_min, hr, R_min, hR, m_r, m_R, dt, eps;
     ModelParams mp;
 };
@@ -22,17 +23,20 @@ struct Dims {
 constexpr int kPad = 64;
 inline int padded(int N) { return (N + kPad - 1) / kPad * kPad; }
 constexpr int kCholNb = 64;      // Cholesky panel width
+constexpr int kLowRankMax = 32;  // largest rank of the FP64 part of the mixed contraction
 
 struct Bufs {
     double2 *psi1, *psi2;                 // [N][nr], [N][nR] CWFs (Eq. 7)
     double *r, *R, *r_new, *R_new;        // trajectory positions at t_k and t_k+1
     double2 *C, *Cacc, *Cstage;           // coefficients and RK4 stage vectors
-    double2 *y;                           // matvec output K v
+    double2 *y;                           // forward-substitution result of an RK stage
+    double2 *rhs;                         // K v of an RK stage
     double *vstat_r, *vstat_R;            // V_1(r_i), V_2(R_j)
     double2 *kin_r, *kin_R;               // exp(-i k^2 dt / 2m), FFT order
     double2 *tw_r, *tw_R;                 // exp(-2 pi i k / n)
     double *wc64;                         // [nr][nR] W_c(r_i, R_j)
-    float *wc32;                          // [nr][nR] FP32 rounding of wc64 (mixed form)
+    float *wc32;                          // [nr][nR] FP32 residual of the rank-K split (mixed form)
+    double *lr_u, *lr_v;                  // [kLowRankMax][nr], [kLowRankMax][nR] rank-K factors
     double *sinc_r, *dsinc_r;             // [N][nr] periodic sinc and derivative at r^a
     double *sinc_R, *dsinc_R;             // [N][nR]
     double2 *vpart;                       // [Np/16][Np][3] velocity partial sums
@@ -47,6 +51,8 @@ struct Bufs {
     double2 *Kminus, *Kmid;               // K(psi_k+1, x_k) and the midpoint K
     double2 *L[2], *Lmid;                 // Cholesky factors of S + eps I (lower)
     double2 *chol_diag;                   // [2][64][64] factored diagonal blocks in flight
+    double2 *xsol;                        // [Np] back-substitution result of an RK stage
+    int32_t *solve_sync;                  // [130] block flags and tickets of the stage solves
     double *bo;                           // [nR][n_bo][nr] BO states
     double2 *obs_u, *obs_v;               // observables scratch [N][max(nr,nR)]
     double2 *obs_chi;                     // [n_bo][nR]

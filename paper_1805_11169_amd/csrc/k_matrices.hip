@@ -137,21 +137,30 @@ struct WcTraits<float> {
     typedef flt4 acc4;
 };
 
+__device__ inline void triangle_tile(int t, int *tb, int *ta) {
+    int a = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+    while ((a + 1) * (a + 2) / 2 <= t) ++a;
+    while (a * (a + 1) / 2 > t) --a;
+    *ta = a;
+    *tb = t - a * (a + 1) / 2;
+}
+
 // Block = 4 waves on a 16 (b) x 16 (a) tile of the upper triangle (tile
 // index tb <= ta); wave w owns b = b_tile + 4w .. 4w + 3 against all 16 a.
-// MFMA rows are a, columns are j, k is i.
+// MFMA rows are a, columns are j, k is i; lane l supplies A = P1(b, a0 + l%16,
+// i) and B = W_c(i, j0 + l%16) with i in the quarter l/16 of the i range.
+// The operands of k-step s + 1 are loaded while the 16 products of step s
+// issue; the j-sums of the epilogue go to LDS once per j tile.
 template <typename T>
-__global__ void __launch_bounds__(256) k_wc(const double2 *__restrict__ psi1, const double2 *__restrict__ psi2,
-                                            const T *__restrict__ wtab, int nr, int nR, double scale,
-                                            double2 *__restrict__ Wc, int Np, const int32_t *__restrict__ flags) {
+__global__ void __launch_bounds__(256, 2) k_wc(const double2 *__restrict__ psi1, const double2 *__restrict__ psi2,
+                                               const T *__restrict__ wtab, int nr, int nR, double scale,
+                                               double2 *__restrict__ Wc, int Np, int accumulate,
+                                               const int32_t *__restrict__ flags) {
     typedef typename WcTraits<T>::acc4 acc4;
     if (flags[kFlagHalt]) return;
-    // triangle index -> (tb, ta), tb <= ta
-    const int t = blockIdx.x;
-    int ta = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
-    while ((ta + 1) * (ta + 2) / 2 <= t) ++ta;
-    while (ta * (ta + 1) / 2 > t) --ta;
-    const int tb = t - ta * (ta + 1) / 2;
+    __shared__ double2 wl[4][4][16];   // [wave][b][a] block partial of Wc
+    int tb, ta;
+    triangle_tile(blockIdx.x, &tb, &ta);
 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int row = lane & 15, quarter = lane >> 4;
@@ -159,16 +168,10 @@ __global__ void __launch_bounds__(256) k_wc(const double2 *__restrict__ psi1, co
     const int b_base = tb * 16 + 4 * wave;
     const int q = nr >> 2;
 
-    const double2 *pa = psi1 + (size_t)(a_base + row) * nr + quarter * q;
-    const double2 *pb[4];
-#pragma unroll
-    for (int bb = 0; bb < 4; ++bb) pb[bb] = psi1 + (size_t)(b_base + bb) * nr + quarter * q;
+    for (int e = lane; e < 64; e += 64) wl[wave][e >> 4][e & 15] = make_double2(0, 0);
 
-    double2 wsum[4][4];   // [b][v]: partial Wc for (b_base + bb, a_base + mfma_row(T, lane, v))
-#pragma unroll
-    for (int bb = 0; bb < 4; ++bb)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) wsum[bb][v] = make_double2(0, 0);
+    const double2 *pa = psi1 + (size_t)(a_base + row) * nr + quarter * q;
+    const double2 *pb = psi1 + (size_t)b_base * nr + quarter * q;
 
     for (int j0 = 0; j0 < nR; j0 += 32) {
         acc4 acc[4][2][2];   // [b][re/im][j fragment]
@@ -179,21 +182,41 @@ __global__ void __launch_bounds__(256) k_wc(const double2 *__restrict__ psi1, co
 #pragma unroll
                 for (int jf = 0; jf < 2; ++jf) acc[bb][c][jf] = acc4{0, 0, 0, 0};
         const T *wrow = wtab + (size_t)(quarter * q) * nR + j0 + row;
+        double2 xa = pa[0];
+        double2 xb[4];
+#pragma unroll
+        for (int bb = 0; bb < 4; ++bb) xb[bb] = pb[(size_t)bb * nr];
+        T w0 = wrow[0], w1 = wrow[16];
         for (int s = 0; s < q; ++s) {
-            const double2 xa = pa[s];
-            const T w0 = wrow[(size_t)s * nR];
-            const T w1 = wrow[(size_t)s * nR + 16];
+            const int sn = (s + 1 < q) ? s + 1 : s;
+            const double2 xa_n = pa[sn];
+            double2 xb_n[4];
+#pragma unroll
+            for (int bb = 0; bb < 4; ++bb) xb_n[bb] = pb[(size_t)bb * nr + sn];
+            const T w0_n = wrow[(size_t)sn * nR];
+            const T w1_n = wrow[(size_t)sn * nR + 16];
 #pragma unroll
             for (int bb = 0; bb < 4; ++bb) {
-                const double2 p = cmulc(pb[bb][s], xa);   // conj(psi1^b_i) psi1^a_i
+                const double2 p = cmulc(xb[bb], xa);   // conj(psi1^b_i) psi1^a_i
                 const T pr = (T)p.x, pi = (T)p.y;
                 acc[bb][0][0] = mfma(pr, w0, acc[bb][0][0]);
                 acc[bb][1][0] = mfma(pi, w0, acc[bb][1][0]);
                 acc[bb][0][1] = mfma(pr, w1, acc[bb][0][1]);
                 acc[bb][1][1] = mfma(pi, w1, acc[bb][1][1]);
             }
+            xa = xa_n;
+#pragma unroll
+            for (int bb = 0; bb < 4; ++bb) xb[bb] = xb_n[bb];
+            w0 = w0_n;
+            w1 = w1_n;
         }
-        // epilogue: lane holds T(b, a = a_base + mfma_row(T, lane, v), j = j0 + 16 jf + row)
+        // epilogue: lane holds T(b, a = a_base + mfma_row(T, lane, v), j = j0 + 16 jf + row);
+        // multiply by P2 = conj(psi2^b_j) psi2^a_j and sum over the 16 j of the fragment
+        double2 ws[4][4];
+#pragma unroll
+        for (int bb = 0; bb < 4; ++bb)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) ws[bb][v] = make_double2(0, 0);
 #pragma unroll
         for (int jf = 0; jf < 2; ++jf) {
             const int j = j0 + 16 * jf + row;
@@ -207,27 +230,124 @@ __global__ void __launch_bounds__(256) k_wc(const double2 *__restrict__ psi1, co
                 for (int v = 0; v < 4; ++v) {
                     const double2 P2 = cmulc(p2b, p2a[v]);
                     const double2 Tv = make_double2((double)acc[bb][0][jf][v], (double)acc[bb][1][jf][v]);
-                    wsum[bb][v] = cadd(wsum[bb][v], cmul(P2, Tv));
+                    ws[bb][v] = cadd(ws[bb][v], cmul(P2, Tv));
                 }
             }
         }
-    }
-    // sum over the 16 j columns held by the lanes of each quarter
 #pragma unroll
-    for (int bb = 0; bb < 4; ++bb)
+        for (int bb = 0; bb < 4; ++bb)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            double2 x = wsum[bb][v];
+            for (int v = 0; v < 4; ++v) {
+                double2 x = ws[bb][v];
 #pragma unroll
-            for (int off = 8; off > 0; off >>= 1) {
-                x.x += __shfl_xor(x.x, off, 16);
-                x.y += __shfl_xor(x.y, off, 16);
+                for (int off = 8; off > 0; off >>= 1) {
+                    x.x += __shfl_xor(x.x, off, 16);
+                    x.y += __shfl_xor(x.y, off, 16);
+                }
+                if (row == 0) {
+                    double2 &dst = wl[wave][bb][mfma_row(T(0), lane, v)];
+                    dst = cadd(dst, x);
+                }
             }
-            if (row == 0) {
-                const int b = b_base + bb, a = a_base + mfma_row(T(0), lane, v);
-                Wc[(size_t)b * Np + a] = cscale(x, scale);
+    }
+    __syncthreads();
+    // write the 4 x 16 partials of this wave
+    {
+        const int bb = lane >> 4, a = lane & 15;
+        const double2 x = cscale(wl[wave][bb][a], scale);
+        double2 *dst = Wc + (size_t)(b_base + bb) * Np + a_base + a;
+        *dst = accumulate ? cadd(*dst, x) : x;
+    }
+}
+
+// FP64 rank-K part of the two-body contraction for the mixed form:
+//     Wc[b][a] += sum_k (hr sum_i conj(psi1^b_i) u_k(r_i) psi1^a_i)
+//                       (hR sum_j conj(psi2^b_j) v_k(R_j) psi2^a_j),
+// with W_c ~ sum_k u_k(r) v_k(R) + residual.  One wave per 32 x 32 tile of the
+// upper triangle (32-tiles); each factor is a conj-NT complex product with the
+// ket weighted by u_k (or v_k) in registers, multiplied elementwise in the epilogue.
+__global__ void __launch_bounds__(64) k_wc_lowrank(const double2 *__restrict__ psi1,
+                                                   const double2 *__restrict__ psi2,
+                                                   const double *__restrict__ U, const double *__restrict__ V,
+                                                   int rank, int nr, int nR, double hr, double hR,
+                                                   double2 *__restrict__ Wc, int Np,
+                                                   const int32_t *__restrict__ flags) {
+    if (flags[kFlagHalt]) return;
+    int tb, ta;
+    triangle_tile(blockIdx.x, &tb, &ta);
+    const int lane = threadIdx.x, row = lane & 15, quarter = lane >> 4;
+    const int b0 = tb * 32, a0 = ta * 32;
+    dbl4 wr[2][2], wi[2][2];
+#pragma unroll
+    for (int f = 0; f < 2; ++f)
+#pragma unroll
+        for (int g = 0; g < 2; ++g) {
+            wr[f][g] = dbl4{0, 0, 0, 0};
+            wi[f][g] = dbl4{0, 0, 0, 0};
+        }
+    for (int k = 0; k < rank; ++k) {
+        dbl4 ur[2][2], ui[2][2], vr[2][2], vi[2][2];
+#pragma unroll
+        for (int f = 0; f < 2; ++f)
+#pragma unroll
+            for (int g = 0; g < 2; ++g) {
+                ur[f][g] = dbl4{0, 0, 0, 0};
+                ui[f][g] = dbl4{0, 0, 0, 0};
+                vr[f][g] = dbl4{0, 0, 0, 0};
+                vi[f][g] = dbl4{0, 0, 0, 0};
+            }
+        for (int sp = 0; sp < 2; ++sp) {
+            const double2 *X = sp == 0 ? psi1 : psi2;
+            const double *wgt = (sp == 0 ? U + (size_t)k * nr : V + (size_t)k * nR);
+            const int n = sp == 0 ? nr : nR;
+            const int q = n >> 2;
+            for (int s = 0; s < q; ++s) {
+                const int i = quarter * q + s;
+                const double w = wgt[i];
+                double2 xv[2], yv[2];
+#pragma unroll
+                for (int f = 0; f < 2; ++f) {
+                    xv[f] = X[(size_t)(b0 + 16 * f + row) * n + i];
+                    yv[f] = cscale(X[(size_t)(a0 + 16 * f + row) * n + i], w);
+                }
+#pragma unroll
+                for (int f = 0; f < 2; ++f)
+#pragma unroll
+                    for (int g = 0; g < 2; ++g) {
+                        dbl4 &re = sp == 0 ? ur[f][g] : vr[f][g];
+                        dbl4 &im = sp == 0 ? ui[f][g] : vi[f][g];
+                        re = mfma(xv[f].x, yv[g].x, re);
+                        re = mfma(xv[f].y, yv[g].y, re);
+                        im = mfma(xv[f].x, yv[g].y, im);
+                        im = mfma(-xv[f].y, yv[g].x, im);
+                    }
             }
         }
+#pragma unroll
+        for (int f = 0; f < 2; ++f)
+#pragma unroll
+            for (int g = 0; g < 2; ++g)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const double2 u = make_double2(ur[f][g][v], ui[f][g][v]);
+                    const double2 w = make_double2(vr[f][g][v], vi[f][g][v]);
+                    const double2 p = cmul(u, w);
+                    wr[f][g][v] += p.x;
+                    wi[f][g][v] += p.y;
+                }
+    }
+    const double sc = hr * hR;
+#pragma unroll
+    for (int f = 0; f < 2; ++f)
+#pragma unroll
+        for (int g = 0; g < 2; ++g)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int b = b0 + 16 * f + mfma_row_f64(lane, v);
+                const int a = a0 + 16 * g + row;
+                double2 *dst = Wc + (size_t)b * Np + a;
+                *dst = cadd(*dst, make_double2(sc * wr[f][g][v], sc * wi[f][g][v]));
+            }
 }
 
 }  // namespace
@@ -271,11 +391,17 @@ void launch_wc(const Dims &d, const Bufs &b, hipStream_t s) {
     const int blocks = T16 * (T16 + 1) / 2;
     const double scale = d.hr * d.hR;
     if (d.prec == 1) {
+        // mixed: FP32 matrix cores on the residual of the rank-K split, FP64 rank-K part added
         hipLaunchKernelGGL(k_wc<float>, dim3(blocks), dim3(256), 0, s, b.psi1, b.psi2, b.wc32, d.nr, d.nR, scale,
-                           b.Wc, Np, b.flags);
+                           b.Wc, Np, 0, b.flags);
+        if (d.lr_rank > 0) {
+            const int T32 = Np / 32;
+            hipLaunchKernelGGL(k_wc_lowrank, dim3(T32 * (T32 + 1) / 2), dim3(64), 0, s, b.psi1, b.psi2, b.lr_u,
+                               b.lr_v, d.lr_rank, d.nr, d.nR, d.hr, d.hR, b.Wc, Np, b.flags);
+        }
     } else {
         hipLaunchKernelGGL(k_wc<double>, dim3(blocks), dim3(256), 0, s, b.psi1, b.psi2, b.wc64, d.nr, d.nR, scale,
-                           b.Wc, Np, b.flags);
+                           b.Wc, Np, 0, b.flags);
     }
 }
 

@@ -11,16 +11,23 @@
 // the regularised matrices handed to the factorisation.
 //
 // Cholesky (lower, in place, two matrices per launch): right-looking with
-// 64-wide panels.  k_chol_panel factors the 64 x 64 diagonal block in LDS (every
-// work-group redundantly; work-group 0 stores it) and solves its 64 rows of
-// the panel, x L11^H = a, one row per lane.  k_chol_update subtracts
-// L21 L21^H from the trailing lower triangle on FP64 matrix cores.  A pivot
-// that is not positive raises the solve flag and halts the step.
+// 64-wide panels.  k_chol_panel factors the 64 x 64 diagonal block with the
+// block's rows held in registers (thread = one row quarter, the pivot column
+// broadcast through LDS), then solves 64 rows of the panel, x L11^H = a, per
+// work-group (the solved column broadcast within each row's four lanes).
+// k_chol_update subtracts L21 L21^H from the trailing lower triangle on FP64
+// matrix cores.  A pivot that is not positive raises the solve flag.
 //
 // RK4 (classical, S and K linear in time between the step ends, so the
-// midpoint is their average): each stage is a matvec K v over many
-// work-groups, then one work-group solves L L^H z = K v by blocked forward and
-// back substitution in LDS and applies the stage update k = -i z.
+// midpoint is their average).  Each stage is a matvec K v over many
+// work-groups and two launches over the 64-row blocks of the factor.
+// k_rk_fwd: a work-group solves L y = K v for its block after the blocks
+// above it are done (it waits on their flags and subtracts their
+// contributions as they arrive).
+// k_rk_bwd: the same for L^H x = y from the bottom up, then the stage update
+// k = -i x of its rows.  Work-groups take blocks in ticket order, so a
+// work-group only ever waits on work-groups that are already running, and
+// every wait is bounded.
 #include "icwf_plan.hpp"
 
 namespace icwf {
@@ -58,7 +65,7 @@ __global__ void k_assemble(const double2 *__restrict__ S1, const double2 *__rest
     }
     const double reg = (a == b) ? eps : 0.0;
     if (initial) {
-        // start of the run: S_0, K_0 = K(psi_0, x_0) -> next slots of parity 0 == current
+        // start of the run: S_0, K_0 = K(psi_0, x_0) -> the slots of parity 0
         Snext[idx] = S;
         Knext[idx] = csub(csub(csub(w, cmul(E1a[idx], s2)), cmul(s1, E2a[idx])), cscale(S, ca));
         Anext[idx] = make_double2(S.x + reg, S.y);
@@ -84,78 +91,129 @@ __device__ inline void raise_solve(int32_t *flags) {
     atomicOr(&flags[kFlagHalt], 1);
 }
 
-// Factor the NB x NB diagonal block (lower) held in LDS tile[NB][NB]; 64 threads.
-__device__ void factor_diag(double2 (*tile)[NB], int32_t *flags) {
-    const int t = threadIdx.x;
-    for (int j = 0; j < NB; ++j) {
-        double d = tile[j][j].x;
-        if (!(d > 0.0)) {                       // not positive definite (or NaN)
-            if (t == 0) raise_solve(flags);
-            d = 1.0;
-        }
-        d = sqrt(d);
-        __syncthreads();
-        if (t == j) tile[j][j] = make_double2(d, 0.0);
-        if (t > j) tile[t][j] = cscale(tile[t][j], 1.0 / d);
-        __syncthreads();
-        // trailing update of column k = t (rows i >= k): tile[i][k] -= L[i][j] conj(L[k][j])
-        if (t > j) {
-            const double2 lkj = cconj(tile[t][j]);
-            for (int i = t; i < NB; ++i) tile[i][t] = csub(tile[i][t], cmul(tile[i][j], lkj));
-        }
-        __syncthreads();
-    }
-}
+// Packed lower-triangular tile of NB x NB entries in LDS, column-major:
+// entry (row k, column j), k >= j, at colofs(j) + k - j.
+__host__ __device__ constexpr int colofs(int j) { return j * NB - j * (j - 1) / 2; }
+// Row-major packing: entry (row j, column i), i <= j, at rowofs(j) + i.
+__host__ __device__ constexpr int rowofs(int j) { return j * (j + 1) / 2; }
+constexpr int kPacked = NB * (NB + 1) / 2;
 
+// 256 threads: thread t owns row i = t / 4, columns 16 q .. 16 q + 15 with
+// q = t % 4 (the four lanes of a row are adjacent in one wave).
+//
 // The factored diagonal block goes to a scratch tile, not into A: other
 // work-groups of the same launch may still be reading the unfactored block.
 // Work-group 0 of the next launch (or k_chol_flush after the last panel) copies
 // it into place.
-__global__ void __launch_bounds__(64) k_chol_panel(double2 *A0, double2 *A1, int Np, int kb,
-                                                   double2 *__restrict__ diag, int32_t *__restrict__ flags) {
+__global__ void __launch_bounds__(256) k_chol_panel(double2 *A0, double2 *A1, int Np, int kb,
+                                                    double2 *__restrict__ diag, int32_t *__restrict__ flags) {
     if (flags[kFlagHalt]) return;
-    __shared__ double2 tile[NB][NB];
+    __shared__ double2 LP[kPacked];      // the factored block, packed lower, column-major
+    __shared__ double2 colbuf[2][NB];    // pivot columns, alternating with j so that
+                                         // writing column j + 1 never races with reads of column j
+    __shared__ double rdiag[NB];
     double2 *A = blockIdx.y ? A1 : A0;
     double2 *D = diag + (size_t)blockIdx.y * NB * NB;
-    const int t = threadIdx.x;
+    const int t = threadIdx.x, i = t >> 2, q = t & 3, k0 = 16 * q;
     if (blockIdx.x == 0 && kb > 0) {
         const int pb = kb - NB;
-        for (int i = 0; i < NB; ++i)
-            if (t <= i) A[(size_t)(pb + i) * Np + pb + t] = D[i * NB + t];
+        for (int e = t; e < NB * NB; e += 256) {
+            const int rr = e / NB, cc = e % NB;
+            if (cc <= rr) A[(size_t)(pb + rr) * Np + pb + cc] = D[e];
+        }
     }
-    for (int i = 0; i < NB; ++i) tile[i][t] = A[(size_t)(kb + i) * Np + kb + t];
+    for (int e = t; e < 2 * NB; e += 256) colbuf[e / NB][e % NB] = make_double2(0.0, 0.0);
+    double2 a[16];
+#pragma unroll
+    for (int c = 0; c < 16; ++c) a[c] = A[(size_t)(kb + i) * Np + kb + k0 + c];
+    bool bad = false;
+    // j = 16 qj + cj; the quarter loop stays rolled (code size), the column
+    // loop is unrolled so that a[cj] is a register.
+#pragma unroll 1
+    for (int qj = 0; qj < 4; ++qj)
+#pragma unroll
+    for (int cj = 0; cj < 16; ++cj) {
+        const int j = 16 * qj + cj;
+        double2 *col = colbuf[cj & 1];
+        if (q == qj && i == j) {
+            double dd = a[cj].x;
+            if (!(dd > 0.0)) {
+                bad = true;
+                dd = 1.0;
+            }
+            col[j] = make_double2(sqrt(dd), 0.0);
+        }
+        __syncthreads();
+        const double dj = col[j].x;
+        if (q == qj) {
+            if (i > j) {
+                const double2 l = cscale(a[cj], 1.0 / dj);
+                a[cj] = l;
+                col[i] = l;
+            } else if (i == j) {
+                a[cj] = make_double2(dj, 0.0);
+            }
+        }
+        __syncthreads();
+        if (i > j) {
+            const double2 li = col[i];
+#pragma unroll
+            for (int c = 0; c < 16; ++c) {
+                const int k = k0 + c;
+                if (k > j && k <= i) a[c] = csub(a[c], cmul(li, cconj(col[k])));
+            }
+        }
+    }
+    if (bad) raise_solve(flags);
+#pragma unroll
+    for (int c = 0; c < 16; ++c) {
+        const int k = k0 + c;
+        if (k <= i) {
+            LP[colofs(k) + i - k] = a[c];
+            if (blockIdx.x == 0) D[i * NB + k] = a[c];
+        }
+    }
     __syncthreads();
-    factor_diag(tile, flags);
-    if (blockIdx.x == 0) {
-        for (int i = 0; i < NB; ++i) D[i * NB + t] = tile[i][t];
-    }
+    if (t < NB) rdiag[t] = 1.0 / LP[colofs(t)].x;
+    __syncthreads();
     // rows of the panel below the block: x L11^H = a, column by column
-    // (right-looking): x_j = a_j / L11[j][j], then a_k -= x_j conj(L11[k][j])
-    // for k > j.  Only the not yet solved part of the row stays live.
-    const int i = kb + NB + blockIdx.x * 64 + t;
-    if (i >= Np) return;
-    double2 *arow = A + (size_t)i * Np + kb;
-    double2 a[NB];
+    // (right-looking): x_j = a_j / L11[j][j], then a_k -= x_j conj(L11[k][j]) for k > j.
+    const int row = kb + NB + blockIdx.x * 64 + i;
+    if (row >= Np) return;
+    double2 *arow = A + (size_t)row * Np + kb + k0;
 #pragma unroll
-    for (int j = 0; j < NB; ++j) a[j] = arow[j];
+    for (int c = 0; c < 16; ++c) a[c] = arow[c];
+    const int lane = t & 63;
+#pragma unroll 1
+    for (int qj = 0; qj < 4; ++qj)
 #pragma unroll
-    for (int j = 0; j < NB; ++j) {
-        const double2 xj = cscale(a[j], 1.0 / tile[j][j].x);
-        arow[j] = xj;
+    for (int cj = 0; cj < 16; ++cj) {
+        const int j = 16 * qj + cj;
+        double2 x = make_double2(0, 0);
+        if (q == qj) x = cscale(a[cj], rdiag[j]);
+        x.x = __shfl(x.x, (lane & ~3) | qj);
+        x.y = __shfl(x.y, (lane & ~3) | qj);
+        if (q == qj) a[cj] = x;
 #pragma unroll
-        for (int k = j + 1; k < NB; ++k) a[k] = csub(a[k], cmul(xj, cconj(tile[k][j])));
+        for (int c = 0; c < 16; ++c) {
+            const int k = k0 + c;
+            if (k > j) a[c] = csub(a[c], cmul(x, cconj(LP[colofs(j) + k - j])));
+        }
     }
+#pragma unroll
+    for (int c = 0; c < 16; ++c) arow[c] = a[c];
 }
 
-__global__ void __launch_bounds__(64) k_chol_flush(double2 *A0, double2 *A1, int Np, int kb,
-                                                   const double2 *__restrict__ diag,
-                                                   const int32_t *__restrict__ flags) {
+__global__ void __launch_bounds__(256) k_chol_flush(double2 *A0, double2 *A1, int Np, int kb,
+                                                    const double2 *__restrict__ diag,
+                                                    const int32_t *__restrict__ flags) {
     if (flags[kFlagHalt]) return;
     double2 *A = blockIdx.y ? A1 : A0;
     const double2 *D = diag + (size_t)blockIdx.y * NB * NB;
-    const int t = threadIdx.x;
-    for (int i = 0; i < NB; ++i)
-        if (t <= i) A[(size_t)(kb + i) * Np + kb + t] = D[i * NB + t];
+    for (int e = threadIdx.x; e < NB * NB; e += 256) {
+        const int rr = e / NB, cc = e % NB;
+        if (cc <= rr) A[(size_t)(kb + rr) * Np + kb + cc] = D[e];
+    }
 }
 
 // Trailing update A[i][k] -= sum_j L[i][j] conj(L[k][j]) over the lower
@@ -220,8 +278,42 @@ __global__ void __launch_bounds__(64) k_chol_update(double2 *A0, double2 *A1, in
             }
 }
 
-// ------------------------------------------------------------------ RK4
-// y = M v, one wave per row.
+// ------------------------------------------------------------------ RK4 stage solves
+// Synchronisation words in the workspace (int32): [0, 64) forward block
+// flags, [64, 128) backward block flags, [128] forward ticket, [129] backward
+// ticket.  Each kernel clears the other kernel's words for its next launch.
+constexpr int kMaxBlocks = 64;
+constexpr int kSyncFwd = 0, kSyncBwd = 64, kSyncTicketF = 128, kSyncTicketB = 129;
+
+__device__ inline int take_ticket(int32_t *ctr, int *slot) {
+    if (threadIdx.x == 0) *slot = atomicAdd(ctr, 1);
+    __syncthreads();
+    return *slot;
+}
+
+// Wait (thread 0, bounded) for a block flag, then let every wave acquire it.
+__device__ inline void wait_block(const int32_t *flag, int32_t *status) {
+    if (threadIdx.x == 0) wait_flag(flag, status);
+    __syncthreads();
+    (void)__hip_atomic_load(flag, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ inline void publish_block(int32_t *flag) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        set_flag(flag);
+    }
+}
+
+// Broadcast lane `src` (wave-uniform) of a double to the whole wave.
+__device__ inline double bcast(double v, int src) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), src);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), src);
+    return __hiloint2double(hi, lo);
+}
+
+// y = M v, one wave per row, four rows per work-group.
 __global__ void __launch_bounds__(256) k_matvec(const double2 *__restrict__ M, const double2 *__restrict__ v,
                                                 double2 *__restrict__ y, int Np,
                                                 const int32_t *__restrict__ flags) {
@@ -239,117 +331,150 @@ __global__ void __launch_bounds__(256) k_matvec(const double2 *__restrict__ M, c
     if (lane == 0) y[rowi] = acc;
 }
 
-// Solve L L^H z = z in place (z in LDS), L lower Np x Np; 1024 threads.
-__device__ void chol_solve(const double2 *__restrict__ L, int Np, double2 *z, double2 (*red)[64]) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;   // 16 waves
-    // forward: L w = z
-    for (int B = 0; B < Np; B += 64) {
-        // partial sums over the columns left of the block: 4 rows per wave
-        for (int rr = 0; rr < 4; ++rr) {
-            const int i = B + 4 * wave + rr;
-            const double2 *Li = L + (size_t)i * Np;
-            double2 acc = make_double2(0, 0);
-            for (int c = lane; c < B; c += 64) acc = cadd(acc, cmul(Li[c], z[c]));
+// Forward stage kernel: y_B = L_BB^-1 (rhs_B - sum_{C<B} L_BC y_C).
+// 256 threads; thread t: row i = t / 4 of the block, quarter q = t % 4.  The
+// 64-step substitution inside the diagonal block runs in one wave with the
+// solved entry broadcast by readlane and the pivots' reciprocals precomputed.
+__global__ void __launch_bounds__(256) k_rk_fwd(const double2 *__restrict__ rhs, const double2 *__restrict__ L,
+                                                double2 *__restrict__ ybuf, int Np, int32_t *__restrict__ sync,
+                                                int32_t *__restrict__ flags) {
+    __shared__ double2 LPk[kPacked];  // diagonal block L[B64 + i][B64 + j], i >= j, packed column-major
+    __shared__ double2 pr[NB];
+    __shared__ int slot;
+    const int B = take_ticket(&sync[kSyncTicketF], &slot);
+    if (B == 0) {
+        for (int e = threadIdx.x; e < kMaxBlocks; e += 256) sync[kSyncBwd + e] = 0;
+        if (threadIdx.x == 0) sync[kSyncTicketB] = 0;
+    }
+    const bool halted = flags[kFlagHalt] != 0;
+    const int t = threadIdx.x, i = t >> 2, q = t & 3, lane = t & 63, wave = t >> 6;
+    const int r0 = B * NB;
+    if (!halted) {
+        for (int e = t; e < NB * NB; e += 256) {
+            const int rr = e / NB, cc = e % NB;
+            if (cc <= rr) LPk[colofs(cc) + rr - cc] = L[(size_t)(r0 + rr) * Np + r0 + cc];
+        }
+    }
+    // contributions of the blocks above, as they complete
+    double2 part = make_double2(0, 0);
+    for (int C = 0; C < B; ++C) {
+        wait_block(&sync[kSyncFwd + C], flags);
+        if (halted) continue;
+        const double2 *lrow = L + (size_t)(r0 + i) * Np + C * NB + 16 * q;
+        const double2 *yc = ybuf + C * NB + 16 * q;
 #pragma unroll
-            for (int off = 32; off > 0; off >>= 1) {
-                acc.x += __shfl_xor(acc.x, off);
-                acc.y += __shfl_xor(acc.y, off);
-            }
-            if (lane == 0) red[0][4 * wave + rr] = acc;
-        }
-        __syncthreads();
-        if (wave == 0) {
-            double2 tv = csub(z[B + lane], red[0][lane]);
-            const double2 *Lrow = L + (size_t)(B + lane) * Np + B;
-            for (int jj = 0; jj < 64; ++jj) {
-                double2 xj = make_double2(0, 0);
-                if (lane == jj) xj = cscale(tv, 1.0 / Lrow[jj].x);
-                xj.x = __shfl(xj.x, jj);
-                xj.y = __shfl(xj.y, jj);
-                if (lane > jj) tv = csub(tv, cmul(Lrow[jj], xj));
-                if (lane == jj) tv = xj;
-            }
-            z[B + lane] = tv;
-        }
-        __syncthreads();
+        for (int c = 0; c < 16; ++c) part = cadd(part, cmul(lrow[c], yc[c]));
     }
-    // backward: L^H x = w
-    for (int B = Np - 64; B >= 0; B -= 64) {
-        double2 acc = make_double2(0, 0);
-        for (int i = B + 64 + wave; i < Np; i += 16) acc = cadd(acc, cmul(cconj(L[(size_t)i * Np + B + lane]), z[i]));
-        red[wave][lane] = acc;
-        __syncthreads();
-        if (wave == 0) {
-            double2 u = z[B + lane];
-            for (int w = 0; w < 16; ++w) u = csub(u, red[w][lane]);
-            for (int jj = 63; jj >= 0; --jj) {
-                const double2 *Lrow = L + (size_t)(B + jj) * Np + B;
-                double2 xj = make_double2(0, 0);
-                if (lane == jj) xj = cscale(u, 1.0 / Lrow[jj].x);
-                xj.x = __shfl(xj.x, jj);
-                xj.y = __shfl(xj.y, jj);
-                if (lane < jj) u = csub(u, cmul(cconj(Lrow[lane]), xj));
-                if (lane == jj) u = xj;
-            }
-            z[B + lane] = u;
+    part.x += __shfl_xor(part.x, 1);
+    part.y += __shfl_xor(part.y, 1);
+    part.x += __shfl_xor(part.x, 2);
+    part.y += __shfl_xor(part.y, 2);
+    if (q == 0) pr[i] = part;
+    __syncthreads();
+    if (!halted && wave == 0) {
+        double2 u = csub(rhs[r0 + lane], pr[lane]);
+        const double inv = 1.0 / LPk[colofs(lane)].x;
+        for (int j = 0; j < NB; ++j) {
+            const double xr = bcast(u.x * inv, j), xi = bcast(u.y * inv, j);
+            // lanes <= j read an earlier column's entry (in bounds, finite), masked out
+            const double m = (lane > j) ? 1.0 : 0.0;
+            u = csub(u, cmul(LPk[colofs(j) + lane - j], make_double2(m * xr, m * xi)));
+            if (lane == j) u = make_double2(xr, xi);
         }
-        __syncthreads();
+        ybuf[r0 + lane] = u;
     }
+    publish_block(&sync[kSyncFwd + B]);
 }
 
-constexpr int kSolveLdsMax = 3072;
-
-// stage: 1..4 of RK4; 0 = initial coefficients (C = solve(y)).
-__global__ void __launch_bounds__(1024) k_rk_stage(const double2 *__restrict__ L, double2 *__restrict__ y,
-                                                   int stage, double dt, int N, int Np, double2 *__restrict__ C,
-                                                   double2 *__restrict__ Cacc, double2 *__restrict__ Cstage,
-                                                   double *__restrict__ r, double *__restrict__ R,
-                                                   const double *__restrict__ r_new,
-                                                   const double *__restrict__ R_new, int32_t *__restrict__ flags) {
-    if (flags[kFlagHalt]) return;
-    extern __shared__ double2 zlds[];
-    __shared__ double2 red[16][64];
-    // z lives in LDS when it fits beside red (64 KB per work-group), else in
-    // the y buffer itself (global memory; the block barrier orders it).
-    double2 *zs = (Np <= kSolveLdsMax) ? zlds : const_cast<double2 *>(y);
-    if (Np <= kSolveLdsMax) {
-        for (int i = threadIdx.x; i < Np; i += blockDim.x) zs[i] = y[i];
+// Backward stage kernel: x_B = L_BB^-H (y_B - sum_{C>B} L_CB^H x_C), blocks
+// from the bottom up; then the RK4 stage update of the block's rows.
+// stage: 1..4; 0 = initial coefficients (C = x).
+__global__ void __launch_bounds__(256) k_rk_bwd(const double2 *__restrict__ L, const double2 *__restrict__ ybuf,
+                                                double2 *__restrict__ xbuf, int Np, int nblk, int stage, double dt,
+                                                int N, double2 *__restrict__ C, double2 *__restrict__ Cacc,
+                                                double2 *__restrict__ Cstage, double *__restrict__ r,
+                                                double *__restrict__ R, const double *__restrict__ r_new,
+                                                const double *__restrict__ R_new, int32_t *__restrict__ sync,
+                                                int32_t *__restrict__ flags) {
+    __shared__ double2 LPr[kPacked];  // diagonal block L[B64 + j][B64 + i], i <= j, packed row-major
+    __shared__ double2 pr[NB];
+    __shared__ int slot;
+    const int ticket = take_ticket(&sync[kSyncTicketB], &slot);
+    const int B = nblk - 1 - ticket;
+    if (ticket == 0) {
+        for (int e = threadIdx.x; e < kMaxBlocks; e += 256) sync[kSyncFwd + e] = 0;
+        if (threadIdx.x == 0) sync[kSyncTicketF] = 0;
     }
-    __syncthreads();
-    chol_solve(L, Np, zs, red);
-    int bad = 0;
-    for (int i = threadIdx.x; i < Np; i += blockDim.x) {
-        const double2 z = zs[i];
-        if (stage == 0) {
-            C[i] = (i < N) ? z : make_double2(0, 0);
-            bad |= !(isfinite(z.x) && isfinite(z.y));
-            continue;
+    const bool halted = flags[kFlagHalt] != 0;
+    const int t = threadIdx.x, i = t >> 2, q = t & 3, lane = t & 63, wave = t >> 6;
+    const int r0 = B * NB;
+    if (!halted) {
+        for (int e = t; e < NB * NB; e += 256) {
+            const int rr = e / NB, cc = e % NB;
+            if (cc <= rr) LPr[rowofs(rr) + cc] = L[(size_t)(r0 + rr) * Np + r0 + cc];
         }
-        const double2 k = make_double2(z.y, -z.x);   // -i z
-        const double2 c = C[i];
-        if (stage == 1) {
-            Cacc[i] = k;
-            Cstage[i] = cadd(c, cscale(k, 0.5 * dt));
-        } else if (stage == 2) {
-            Cacc[i] = cadd(Cacc[i], cscale(k, 2.0));
-            Cstage[i] = cadd(c, cscale(k, 0.5 * dt));
-        } else if (stage == 3) {
-            Cacc[i] = cadd(Cacc[i], cscale(k, 2.0));
-            Cstage[i] = cadd(c, cscale(k, dt));
+    }
+    // contributions of the blocks below (already solved): sum_k conj(L[C64+k][B64+i]) x[C64+k]
+    double2 part = make_double2(0, 0);
+    for (int Cb = nblk - 1; Cb > B; --Cb) {
+        wait_block(&sync[kSyncBwd + Cb], flags);
+        if (halted) continue;
+        const double2 *lcol = L + (size_t)(Cb * NB + 16 * q) * Np + r0 + i;
+        const double2 *xc = xbuf + Cb * NB + 16 * q;
+#pragma unroll
+        for (int c = 0; c < 16; ++c) part = cadd(part, cmul(cconj(lcol[(size_t)c * Np]), xc[c]));
+    }
+    part.x += __shfl_xor(part.x, 1);
+    part.y += __shfl_xor(part.y, 1);
+    part.x += __shfl_xor(part.x, 2);
+    part.y += __shfl_xor(part.y, 2);
+    if (q == 0) pr[i] = part;
+    __syncthreads();
+    if (!halted && wave == 0) {
+        double2 u = csub(ybuf[r0 + lane], pr[lane]);
+        const double inv = 1.0 / LPr[rowofs(lane) + lane].x;
+        for (int j = NB - 1; j >= 0; --j) {
+            const double xr = bcast(u.x * inv, j), xi = bcast(u.y * inv, j);
+            // lanes >= j read a later row's entry (in bounds, finite), masked out
+            const double m = (lane < j) ? 1.0 : 0.0;
+            u = csub(u, cmul(cconj(LPr[rowofs(j) + lane]), make_double2(m * xr, m * xi)));
+            if (lane == j) u = make_double2(xr, xi);
+        }
+        xbuf[r0 + lane] = u;
+        // stage update of this block's rows
+        const int ii = r0 + lane;
+        bool bad = false;
+        if (stage == 0) {
+            C[ii] = (ii < N) ? u : make_double2(0, 0);
+            bad = !(isfinite(u.x) && isfinite(u.y));
         } else {
-            const double2 cn = cadd(c, cscale(cadd(Cacc[i], k), dt / 6.0));
-            C[i] = cn;
-            bad |= !(isfinite(cn.x) && isfinite(cn.y));
-            if (i < N) {
-                r[i] = r_new[i];
-                R[i] = R_new[i];
+            const double2 k = make_double2(u.y, -u.x);   // -i x
+            const double2 c = C[ii];
+            if (stage == 1) {
+                Cacc[ii] = k;
+                Cstage[ii] = cadd(c, cscale(k, 0.5 * dt));
+            } else if (stage == 2) {
+                Cacc[ii] = cadd(Cacc[ii], cscale(k, 2.0));
+                Cstage[ii] = cadd(c, cscale(k, 0.5 * dt));
+            } else if (stage == 3) {
+                Cacc[ii] = cadd(Cacc[ii], cscale(k, 2.0));
+                Cstage[ii] = cadd(c, cscale(k, dt));
+            } else {
+                const double2 cn = cadd(c, cscale(cadd(Cacc[ii], k), dt / 6.0));
+                C[ii] = cn;
+                bad = !(isfinite(cn.x) && isfinite(cn.y));
+                if (ii < N) {
+                    r[ii] = r_new[ii];
+                    R[ii] = R_new[ii];
+                }
             }
         }
+        if (bad) {
+            atomicOr(&flags[kFlagNonfinite], 1);
+            atomicOr(&flags[kFlagHalt], 1);
+        }
     }
-    if (bad) {
-        atomicOr(&flags[kFlagNonfinite], 1);
-        atomicOr(&flags[kFlagHalt], 1);
-    }
+    publish_block(&sync[kSyncBwd + B]);
 }
 
 __global__ void k_fill_i32(int32_t *p, int n, int32_t v) {
@@ -374,35 +499,35 @@ void launch_cholesky(const Dims &d, const Bufs &b, double2 *A0, double2 *A1, int
     for (int kb = 0; kb < Np; kb += NB) {
         const int below = Np - kb - NB;
         const int gx = below > 0 ? below / 64 : 1;
-        hipLaunchKernelGGL(k_chol_panel, dim3(gx, count), dim3(64), 0, s, A0, A1, Np, kb, b.chol_diag, b.flags);
+        hipLaunchKernelGGL(k_chol_panel, dim3(gx, count), dim3(256), 0, s, A0, A1, Np, kb, b.chol_diag, b.flags);
         if (below > 0) {
             const int mt = below / 32;
             hipLaunchKernelGGL(k_chol_update, dim3(mt * (mt + 1) / 2, count), dim3(64), 0, s, A0, A1, Np, kb,
                                b.flags);
         }
     }
-    hipLaunchKernelGGL(k_chol_flush, dim3(1, count), dim3(64), 0, s, A0, A1, Np, Np - NB, b.chol_diag, b.flags);
+    hipLaunchKernelGGL(k_chol_flush, dim3(1, count), dim3(256), 0, s, A0, A1, Np, Np - NB, b.chol_diag, b.flags);
 }
 
 void launch_rk4(const Dims &d, const Bufs &b, int parity, hipStream_t s) {
-    const int Np = padded(d.N);
+    const int Np = padded(d.N), nblk = Np / NB;
     const int cur = parity, nxt = 1 - parity;
     const double2 *Ks[4] = {b.Kmat[cur], b.Kmid, b.Kmid, b.Kminus};
     const double2 *Ls[4] = {b.L[cur], b.Lmid, b.Lmid, b.L[nxt]};
-    const size_t lds = Np <= kSolveLdsMax ? sizeof(double2) * Np : 0;
     for (int st = 1; st <= 4; ++st) {
         const double2 *v = (st == 1) ? b.C : b.Cstage;
-        hipLaunchKernelGGL(k_matvec, dim3(Np / 4), dim3(256), 0, s, Ks[st - 1], v, b.y, Np, b.flags);
-        hipLaunchKernelGGL(k_rk_stage, dim3(1), dim3(1024), lds, s, Ls[st - 1], b.y, st, d.dt, d.N, Np, b.C,
-                           b.Cacc, b.Cstage, b.r, b.R, b.r_new, b.R_new, b.flags);
+        hipLaunchKernelGGL(k_matvec, dim3(Np / 4), dim3(256), 0, s, Ks[st - 1], v, b.rhs, Np, b.flags);
+        hipLaunchKernelGGL(k_rk_fwd, dim3(nblk), dim3(256), 0, s, b.rhs, Ls[st - 1], b.y, Np, b.solve_sync, b.flags);
+        hipLaunchKernelGGL(k_rk_bwd, dim3(nblk), dim3(256), 0, s, Ls[st - 1], b.y, b.xsol, Np, nblk, st, d.dt, d.N,
+                           b.C, b.Cacc, b.Cstage, b.r, b.R, b.r_new, b.R_new, b.solve_sync, b.flags);
     }
 }
 
 void launch_solve_initial(const Dims &d, const Bufs &b, int parity, double2 *rhs, hipStream_t s) {
-    const int Np = padded(d.N);
-    const size_t lds = Np <= kSolveLdsMax ? sizeof(double2) * Np : 0;
-    hipLaunchKernelGGL(k_rk_stage, dim3(1), dim3(1024), lds, s, b.L[parity], rhs, 0, d.dt, d.N, Np, b.C, b.Cacc,
-                       b.Cstage, b.r, b.R, b.r_new, b.R_new, b.flags);
+    const int Np = padded(d.N), nblk = Np / NB;
+    hipLaunchKernelGGL(k_rk_fwd, dim3(nblk), dim3(256), 0, s, rhs, b.L[parity], b.y, Np, b.solve_sync, b.flags);
+    hipLaunchKernelGGL(k_rk_bwd, dim3(nblk), dim3(256), 0, s, b.L[parity], b.y, b.xsol, Np, nblk, 0, d.dt, d.N,
+                       b.C, b.Cacc, b.Cstage, b.r, b.R, b.r_new, b.R_new, b.solve_sync, b.flags);
 }
 
 void launch_fill_i32(int32_t *p, int n, int32_t v, hipStream_t s) {

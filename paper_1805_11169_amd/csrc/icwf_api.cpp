@@ -64,6 +64,9 @@ Bufs carve(const icwf_config &c, char *base, size_t *total) {
     b.tw_R = L.take<double2>(nR);
     b.wc64 = L.take<double>(nr * nR);
     b.wc32 = L.take<float>(nr * nR);
+    const bool mixed = c.precision == ICWF_PREC_MIXED;
+    b.lr_part = L.take<double2>(mixed ? 4 * Np * Np : 1);
+    b.psi1_f32 = L.take<float2>(mixed ? Np * nr : 1);
     b.lr_u = L.take<double>(icwf::kLowRankMax * nr);
     b.lr_v = L.take<double>(icwf::kLowRankMax * nR);
     b.sinc_r = L.take<double>(Np * nr);
@@ -446,6 +449,7 @@ icwf_status icwf_create(const icwf_config *cfg, const double *r0, const double *
     else CREATE_HIP(hipMemcpyAsync(b.Cstage, b0, sizeof(double2) * N, hipMemcpyHostToDevice, st));
 
     // ---- initial S_0, K_0 and the factor of S_0 + eps I
+    if (d.prec == ICWF_PREC_MIXED) icwf::launch_psi1_f32(d, b, st);
     icwf::launch_cond_kets(d, b, st);
     icwf::launch_single_species(d, b, false, st);
     icwf::launch_wc(d, b, st);

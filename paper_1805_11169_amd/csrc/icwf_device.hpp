@@ -33,6 +33,10 @@ __host__ __device__ inline double2 cmul(double2 a, double2 b) {
 __host__ __device__ inline double2 cmulc(double2 a, double2 b) {
     return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
 }
+// conj(a) * b in FP32
+__host__ __device__ inline float2 cmulc(float2 a, float2 b) {
+    return make_float2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
+}
 __host__ __device__ inline double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
 __host__ __device__ inline double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
 __host__ __device__ inline double2 cscale(double2 a, double s) { return make_double2(a.x * s, a.y * s); }

@@ -37,6 +37,8 @@ struct Bufs {
     double *wc64;                         // [nr][nR] W_c(r_i, R_j)
     float *wc32;                          // [nr][nR] FP32 residual of the rank-K split (mixed form)
     double *lr_u, *lr_v;                  // [kLowRankMax][nr], [kLowRankMax][nR] rank-K factors
+    double2 *lr_part;                     // [4][Np][Np] rank-group partials (mixed form only)
+    float2 *psi1_f32;                     // [Np][nr] FP32 copy of psi1 (mixed form only)
     double *sinc_r, *dsinc_r;             // [N][nr] periodic sinc and derivative at r^a
     double *sinc_R, *dsinc_R;             // [N][nR]
     double2 *vpart;                       // [Np/16][Np][3] velocity partial sums
@@ -97,6 +99,9 @@ void launch_commit_positions(const Dims &d, const Bufs &b, hipStream_t s);
 
 // Observables into b.obs_out (layout in icwf_api.cpp).
 void launch_observables(const Dims &d, const Bufs &b, int parity, hipStream_t s);
+
+// FP32 copy of psi1 (mixed form; the propagation keeps it current afterwards).
+void launch_psi1_f32(const Dims &d, const Bufs &b, hipStream_t s);
 
 // Fill n int32 with a value (graph-safe replacement for a memset).
 void launch_fill_i32(int32_t *p, int n, int32_t v, hipStream_t s);

@@ -131,10 +131,12 @@ struct WcTraits;
 template <>
 struct WcTraits<double> {
     typedef dbl4 acc4;
+    typedef double2 cplx;   // psi1 operand
 };
 template <>
 struct WcTraits<float> {
     typedef flt4 acc4;
+    typedef float2 cplx;    // FP32 copy of psi1 (written by the propagation)
 };
 
 __device__ inline void triangle_tile(int t, int *tb, int *ta) {
@@ -152,11 +154,13 @@ __device__ inline void triangle_tile(int t, int *tb, int *ta) {
 // The operands of k-step s + 1 are loaded while the 16 products of step s
 // issue; the j-sums of the epilogue go to LDS once per j tile.
 template <typename T>
-__global__ void __launch_bounds__(256, 2) k_wc(const double2 *__restrict__ psi1, const double2 *__restrict__ psi2,
+__global__ void __launch_bounds__(256, 2) k_wc(const typename WcTraits<T>::cplx *__restrict__ psi1,
+                                               const double2 *__restrict__ psi2,
                                                const T *__restrict__ wtab, int nr, int nR, double scale,
                                                double2 *__restrict__ Wc, int Np, int accumulate,
                                                const int32_t *__restrict__ flags) {
     typedef typename WcTraits<T>::acc4 acc4;
+    typedef typename WcTraits<T>::cplx C2;
     if (flags[kFlagHalt]) return;
     __shared__ double2 wl[4][4][16];   // [wave][b][a] block partial of Wc
     int tb, ta;
@@ -170,8 +174,8 @@ __global__ void __launch_bounds__(256, 2) k_wc(const double2 *__restrict__ psi1,
 
     for (int e = lane; e < 64; e += 64) wl[wave][e >> 4][e & 15] = make_double2(0, 0);
 
-    const double2 *pa = psi1 + (size_t)(a_base + row) * nr + quarter * q;
-    const double2 *pb = psi1 + (size_t)b_base * nr + quarter * q;
+    const C2 *pa = psi1 + (size_t)(a_base + row) * nr + quarter * q;
+    const C2 *pb = psi1 + (size_t)b_base * nr + quarter * q;
 
     for (int j0 = 0; j0 < nR; j0 += 32) {
         acc4 acc[4][2][2];   // [b][re/im][j fragment]
@@ -182,22 +186,22 @@ __global__ void __launch_bounds__(256, 2) k_wc(const double2 *__restrict__ psi1,
 #pragma unroll
                 for (int jf = 0; jf < 2; ++jf) acc[bb][c][jf] = acc4{0, 0, 0, 0};
         const T *wrow = wtab + (size_t)(quarter * q) * nR + j0 + row;
-        double2 xa = pa[0];
-        double2 xb[4];
+        C2 xa = pa[0];
+        C2 xb[4];
 #pragma unroll
         for (int bb = 0; bb < 4; ++bb) xb[bb] = pb[(size_t)bb * nr];
         T w0 = wrow[0], w1 = wrow[16];
         for (int s = 0; s < q; ++s) {
             const int sn = (s + 1 < q) ? s + 1 : s;
-            const double2 xa_n = pa[sn];
-            double2 xb_n[4];
+            const C2 xa_n = pa[sn];
+            C2 xb_n[4];
 #pragma unroll
             for (int bb = 0; bb < 4; ++bb) xb_n[bb] = pb[(size_t)bb * nr + sn];
             const T w0_n = wrow[(size_t)sn * nR];
             const T w1_n = wrow[(size_t)sn * nR + 16];
 #pragma unroll
             for (int bb = 0; bb < 4; ++bb) {
-                const double2 p = cmulc(xb[bb], xa);   // conj(psi1^b_i) psi1^a_i
+                const C2 p = cmulc(xb[bb], xa);   // conj(psi1^b_i) psi1^a_i
                 const T pr = (T)p.x, pi = (T)p.y;
                 acc[bb][0][0] = mfma(pr, w0, acc[bb][0][0]);
                 acc[bb][1][0] = mfma(pi, w0, acc[bb][1][0]);
@@ -264,17 +268,23 @@ __global__ void __launch_bounds__(256, 2) k_wc(const double2 *__restrict__ psi1,
 //     Wc[b][a] += sum_k (hr sum_i conj(psi1^b_i) u_k(r_i) psi1^a_i)
 //                       (hR sum_j conj(psi2^b_j) v_k(R_j) psi2^a_j),
 // with W_c ~ sum_k u_k(r) v_k(R) + residual.  One wave per 32 x 32 tile of the
-// upper triangle (32-tiles); each factor is a conj-NT complex product with the
-// ket weighted by u_k (or v_k) in registers, multiplied elementwise in the epilogue.
+// upper triangle (32-tiles) and rank group g = blockIdx.y (ranks g, g + G, ...);
+// each factor is a conj-NT complex product with the ket weighted by u_k (or
+// v_k) in registers, multiplied elementwise in the epilogue.  Group g writes
+// its partial sum to part[g]; k_lr_reduce adds the groups into Wc in a fixed
+// order (no atomics, so the result does not depend on scheduling).
+constexpr int kLrGroups = 4;
+
 __global__ void __launch_bounds__(64) k_wc_lowrank(const double2 *__restrict__ psi1,
                                                    const double2 *__restrict__ psi2,
                                                    const double *__restrict__ U, const double *__restrict__ V,
                                                    int rank, int nr, int nR, double hr, double hR,
-                                                   double2 *__restrict__ Wc, int Np,
+                                                   double2 *__restrict__ part, int Np,
                                                    const int32_t *__restrict__ flags) {
     if (flags[kFlagHalt]) return;
     int tb, ta;
     triangle_tile(blockIdx.x, &tb, &ta);
+    double2 *Wc = part + (size_t)blockIdx.y * Np * Np;
     const int lane = threadIdx.x, row = lane & 15, quarter = lane >> 4;
     const int b0 = tb * 32, a0 = ta * 32;
     dbl4 wr[2][2], wi[2][2];
@@ -285,7 +295,7 @@ __global__ void __launch_bounds__(64) k_wc_lowrank(const double2 *__restrict__ p
             wr[f][g] = dbl4{0, 0, 0, 0};
             wi[f][g] = dbl4{0, 0, 0, 0};
         }
-    for (int k = 0; k < rank; ++k) {
+    for (int k = blockIdx.y; k < rank; k += gridDim.y) {
         dbl4 ur[2][2], ui[2][2], vr[2][2], vi[2][2];
 #pragma unroll
         for (int f = 0; f < 2; ++f)
@@ -345,9 +355,22 @@ __global__ void __launch_bounds__(64) k_wc_lowrank(const double2 *__restrict__ p
             for (int v = 0; v < 4; ++v) {
                 const int b = b0 + 16 * f + mfma_row_f64(lane, v);
                 const int a = a0 + 16 * g + row;
-                double2 *dst = Wc + (size_t)b * Np + a;
-                *dst = cadd(*dst, make_double2(sc * wr[f][g][v], sc * wi[f][g][v]));
+                Wc[(size_t)b * Np + a] = make_double2(sc * wr[f][g][v], sc * wi[f][g][v]);
             }
+}
+
+// Wc[b][a] += sum_g part[g][b][a] over the upper triangle b <= a (the half
+// every reader of Wc uses), groups summed in index order.
+__global__ void k_lr_reduce(const double2 *__restrict__ part, int groups, double2 *__restrict__ Wc, int Np,
+                            const int32_t *__restrict__ flags) {
+    if (flags[kFlagHalt]) return;
+    const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (size_t)Np * Np) return;
+    const int b = (int)(idx / Np), a = (int)(idx - (size_t)b * Np);
+    if (b > a) return;
+    double2 s = Wc[idx];
+    for (int g = 0; g < groups; ++g) s = cadd(s, part[(size_t)g * Np * Np + idx]);
+    Wc[idx] = s;
 }
 
 }  // namespace
@@ -392,12 +415,16 @@ void launch_wc(const Dims &d, const Bufs &b, hipStream_t s) {
     const double scale = d.hr * d.hR;
     if (d.prec == 1) {
         // mixed: FP32 matrix cores on the residual of the rank-K split, FP64 rank-K part added
-        hipLaunchKernelGGL(k_wc<float>, dim3(blocks), dim3(256), 0, s, b.psi1, b.psi2, b.wc32, d.nr, d.nR, scale,
-                           b.Wc, Np, 0, b.flags);
+        hipLaunchKernelGGL(k_wc<float>, dim3(blocks), dim3(256), 0, s, b.psi1_f32, b.psi2, b.wc32, d.nr, d.nR,
+                           scale, b.Wc, Np, 0, b.flags);
         if (d.lr_rank > 0) {
             const int T32 = Np / 32;
-            hipLaunchKernelGGL(k_wc_lowrank, dim3(T32 * (T32 + 1) / 2), dim3(64), 0, s, b.psi1, b.psi2, b.lr_u,
-                               b.lr_v, d.lr_rank, d.nr, d.nR, d.hr, d.hR, b.Wc, Np, b.flags);
+            const int groups = d.lr_rank < kLrGroups ? d.lr_rank : kLrGroups;
+            hipLaunchKernelGGL(k_wc_lowrank, dim3(T32 * (T32 + 1) / 2, groups), dim3(64), 0, s, b.psi1, b.psi2,
+                               b.lr_u, b.lr_v, d.lr_rank, d.nr, d.nR, d.hr, d.hR, b.lr_part, Np, b.flags);
+            const size_t tot = (size_t)Np * Np;
+            hipLaunchKernelGGL(k_lr_reduce, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, b.lr_part, groups,
+                               b.Wc, Np, b.flags);
         }
     } else {
         hipLaunchKernelGGL(k_wc<double>, dim3(blocks), dim3(256), 0, s, b.psi1, b.psi2, b.wc64, d.nr, d.nR, scale,

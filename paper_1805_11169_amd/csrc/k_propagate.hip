@@ -89,7 +89,7 @@ __device__ inline void fft_forward(double2 *sh, int n, int log2n, const double2 
 __global__ void k_propagate(double2 *__restrict__ psi, int n, int log2n, const double *__restrict__ vstat,
                             double x_min, double h, const double *__restrict__ cond, int species,
                             ModelParams mp, const double2 *__restrict__ kin, const double2 *__restrict__ tw,
-                            double dt, const int32_t *__restrict__ flags) {
+                            double dt, float2 *__restrict__ psi_f32, const int32_t *__restrict__ flags) {
     if (flags[kFlagHalt]) return;
     extern __shared__ double2 sh[];
     const int T = blockDim.x;
@@ -121,7 +121,12 @@ __global__ void k_propagate(double2 *__restrict__ psi, int n, int log2n, const d
 #pragma unroll
     for (int q = 0; q < kMaxPts; ++q) {
         const int i = tid + q * T;
-        if (i < n) p[i] = cmul(ph[q], cscale(cconj(sh[i]), inv_n));
+        if (i < n) {
+            const double2 v = cmul(ph[q], cscale(cconj(sh[i]), inv_n));
+            p[i] = v;
+            // FP32 copy for the mixed form's FP32 contraction
+            if (psi_f32) psi_f32[(size_t)blockIdx.x * n + i] = make_float2((float)v.x, (float)v.y);
+        }
     }
 }
 
@@ -139,11 +144,24 @@ void launch_propagate(const Dims &d, const Bufs &b, int species, hipStream_t s) 
     const size_t lds = sizeof(double2) * n;
     if (species == 1) {
         hipLaunchKernelGGL(k_propagate, dim3(d.N), dim3(T), lds, s, b.psi1, n, ilog2(n), b.vstat_r, d.r_min,
-                           d.hr, b.R, 1, d.mp, b.kin_r, b.tw_r, d.dt, b.flags);
+                           d.hr, b.R, 1, d.mp, b.kin_r, b.tw_r, d.dt, d.prec == 1 ? b.psi1_f32 : nullptr,
+                           b.flags);
     } else {
         hipLaunchKernelGGL(k_propagate, dim3(d.N), dim3(T), lds, s, b.psi2, n, ilog2(n), b.vstat_R, d.R_min,
-                           d.hR, b.r, 2, d.mp, b.kin_R, b.tw_R, d.dt, b.flags);
+                           d.hR, b.r, 2, d.mp, b.kin_R, b.tw_R, d.dt, nullptr, b.flags);
     }
+}
+
+namespace {
+__global__ void k_to_f32(const double2 *__restrict__ src, float2 *__restrict__ dst, size_t n) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = make_float2((float)src[i].x, (float)src[i].y);
+}
+}  // namespace
+
+void launch_psi1_f32(const Dims &d, const Bufs &b, hipStream_t s) {
+    const size_t n = (size_t)padded(d.N) * d.nr;
+    hipLaunchKernelGGL(k_to_f32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, b.psi1, b.psi1_f32, n);
 }
 
 }  // namespace icwf

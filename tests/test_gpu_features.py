@@ -1,0 +1,98 @@
+"""Library behaviour on the GPU beyond parity: graph replay equals
+kernel-by-kernel launches bitwise, runs are bitwise repeatable, a checkpoint
+resumes bitwise, and device-side error conditions surface as status codes."""
+
+import numpy as np
+import pytest
+
+from paper_1805_11169_amd import icwf, inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def wl():
+    w = inputs.gaussian_basis(100, n_r=128, n_R=64, seed=21)
+    print(f"[case] {w.name}", flush=True)
+    return w
+
+
+def _run(wl, steps, timing=False, precision=icwf.PREC_FP64):
+    sim = icwf.Simulation.from_workload(wl, precision=precision, C0=wl.extra["C0"])
+    if timing:
+        sim.set_timing(True)
+    sim.step(steps)
+    sim.sync()
+    st = sim.state()
+    sim.close()
+    return st
+
+
+def _same(a, b):
+    return all(np.array_equal(a[k], b[k]) for k in ("r", "R", "psi1", "psi2", "C"))
+
+
+def test_graph_replay_equals_eager_launches(wl):
+    assert _same(_run(wl, 7), _run(wl, 7, timing=True))
+
+
+def test_bitwise_repeatable(wl):
+    assert _same(_run(wl, 7), _run(wl, 7))
+    assert _same(_run(wl, 5, precision=icwf.PREC_MIXED), _run(wl, 5, precision=icwf.PREC_MIXED))
+
+
+def test_checkpoint_resume_bitwise(wl):
+    full = _run(wl, 6)
+    mid = _run(wl, 3)
+    cfg = icwf.config_from_workload(wl)
+    sim = icwf.Simulation(cfg, mid["r"], mid["R"], mid["psi1"], mid["psi2"], C0=mid["C"])
+    sim.step(3)
+    sim.sync()
+    resumed = sim.state()
+    sim.close()
+    assert _same(full, resumed)
+
+
+def test_kernel_times_are_recorded(wl):
+    sim = icwf.Simulation.from_workload(wl, C0=wl.extra["C0"])
+    sim.set_timing(True)
+    sim.step(3)
+    for name in ("wc_contract", "propagate", "velocity", "zgemm", "cholesky", "rk4", "assemble"):
+        n, ms = sim.kernel_time(name)
+        assert n == 3 and ms > 0, name
+    sim.close()
+
+
+def test_singular_overlap_without_regularisation_is_esolve(wl):
+    """A zero CWF gives S a zero row and column; with eps = 0 its pivot is
+    exactly zero and the factorisation must refuse it."""
+    cfg = icwf.config_from_workload(wl, eps=0.0)
+    p1 = wl.psi1.copy()
+    p1[3] = 0.0
+    with pytest.raises(icwf.ICWFError) as e:
+        icwf.Simulation(cfg, wl.r0, wl.R0, p1, wl.psi2, C0=wl.extra["C0"])
+    assert e.value.status == icwf.ESOLVE
+
+
+def test_node_is_reported_and_stops_the_run(wl):
+    cfg = icwf.config_from_workload(wl)
+    zero2 = np.zeros_like(wl.psi2)
+    sim = icwf.Simulation(cfg, wl.r0, wl.R0, wl.psi1, zero2, C0=wl.extra["C0"])
+    sim.step(1)
+    with pytest.raises(icwf.ICWFError) as e:
+        sim.sync()
+    assert e.value.status == icwf.ENODE
+    with pytest.raises(icwf.ICWFError) as e:
+        sim.step(1)
+    assert e.value.status == icwf.ESTATE
+    sim.close()
+
+
+def test_observables_skip_null_arrays_and_report_box_exits(wl):
+    sim = icwf.Simulation.from_workload(wl, C0=wl.extra["C0"])
+    sim.step(2)
+    o = sim.observables()
+    assert o["step"] == 2 and abs(o["t"] - 2 * wl.dt) < 1e-15
+    assert np.isfinite(o["min_abs_psi"]) and o["min_abs_psi"] > 0
+    assert 0 <= o["n_out_of_box"] <= wl.n_traj
+    sim.close()

@@ -150,9 +150,19 @@ __device__ inline void triangle_tile(int t, int *tb, int *ta) {
 // Block = 4 waves on a 16 (b) x 16 (a) tile of the upper triangle (tile
 // index tb <= ta); wave w owns b = b_tile + 4w .. 4w + 3 against all 16 a.
 // MFMA rows are a, columns are j, k is i; lane l supplies A = P1(b, a0 + l%16,
-// i) and B = W_c(i, j0 + l%16) with i in the quarter l/16 of the i range.
-// The operands of k-step s + 1 are loaded while the 16 products of step s
-// issue; the j-sums of the epilogue go to LDS once per j tile.
+// i) and B = W_c(i, j0 + l%16) with i in the quarter l/16 of the current i
+// chunk.  Each (j tile, i chunk) step stages the 32 psi1 rows of the tile and
+// the W_c chunk in LDS (two buffers): the coalesced global loads of step s + 1
+// are in flight while the matrix cores work on step s.  The j-sums of the
+// epilogue go to LDS once per j tile.
+template <typename T>
+struct WcChunk {
+    static constexpr int KC = sizeof(T) == 8 ? 32 : 64;   // i per chunk (LDS budget: 2 blocks / CU)
+    static constexpr int LDA = KC + 1;                    // padded psi1 row (complex entries)
+    static constexpr int LDW = 32 + 1;                    // padded W_c chunk row
+    static constexpr int PER = KC / 8;                    // elements each thread stages per array
+};
+
 template <typename T>
 __global__ void __launch_bounds__(256, 2) k_wc(const typename WcTraits<T>::cplx *__restrict__ psi1,
                                                const double2 *__restrict__ psi2,
@@ -161,100 +171,127 @@ __global__ void __launch_bounds__(256, 2) k_wc(const typename WcTraits<T>::cplx 
                                                const int32_t *__restrict__ flags) {
     typedef typename WcTraits<T>::acc4 acc4;
     typedef typename WcTraits<T>::cplx C2;
+    typedef WcChunk<T> CK;
+    constexpr int KC = CK::KC, LDA = CK::LDA, LDW = CK::LDW, PER = CK::PER, QS = KC / 4;
     if (flags[kFlagHalt]) return;
+    __shared__ C2 sA[2][32][LDA];      // rows 0..15: a rows, 16..31: b rows of the tile
+    __shared__ T sW[2][KC][LDW];
     __shared__ double2 wl[4][4][16];   // [wave][b][a] block partial of Wc
     int tb, ta;
     triangle_tile(blockIdx.x, &tb, &ta);
 
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int t = threadIdx.x;
+    const int lane = t & 63, wave = t >> 6;
     const int row = lane & 15, quarter = lane >> 4;
     const int a_base = ta * 16;
-    const int b_base = tb * 16 + 4 * wave;
-    const int q = nr >> 2;
+    const int b_tile = tb * 16;
+    const int b_base = b_tile + 4 * wave;
 
     for (int e = lane; e < 64; e += 64) wl[wave][e >> 4][e & 15] = make_double2(0, 0);
 
-    const C2 *pa = psi1 + (size_t)(a_base + row) * nr + quarter * q;
-    const C2 *pb = psi1 + (size_t)b_base * nr + quarter * q;
+    const int nchunk = nr / KC, ntj = nR / 32, nsteps = nchunk * ntj;
+    // staging registers for one (j tile, i chunk) step
+    C2 ra[PER];
+    T rw[PER];
+    auto fetch = [&](int step) {
+        const int jt = step / nchunk, ch = step - jt * nchunk;
+        const int i0 = ch * KC, j0 = jt * 32;
+#pragma unroll
+        for (int m = 0; m < PER; ++m) {
+            const int e = t + 256 * m;
+            const int rr = e / KC, cc = e - rr * KC;
+            const int grow = rr < 16 ? a_base + rr : b_tile + rr - 16;
+            ra[m] = psi1[(size_t)grow * nr + i0 + cc];
+            const int ii = e >> 5, jj = e & 31;
+            rw[m] = wtab[(size_t)(i0 + ii) * nR + j0 + jj];
+        }
+    };
+    auto stash = [&](int buf) {
+#pragma unroll
+        for (int m = 0; m < PER; ++m) {
+            const int e = t + 256 * m;
+            const int rr = e / KC, cc = e - rr * KC;
+            sA[buf][rr][cc] = ra[m];
+            sW[buf][e >> 5][e & 31] = rw[m];
+        }
+    };
 
-    for (int j0 = 0; j0 < nR; j0 += 32) {
-        acc4 acc[4][2][2];   // [b][re/im][j fragment]
+    acc4 acc[4][2][2];   // [b][re/im][j fragment]
+    fetch(0);
+    stash(0);
+    __syncthreads();
+    for (int step = 0; step < nsteps; ++step) {
+        const int buf = step & 1;
+        const int jt = step / nchunk, ch = step - jt * nchunk;
+        if (ch == 0) {
 #pragma unroll
-        for (int bb = 0; bb < 4; ++bb)
+            for (int bb = 0; bb < 4; ++bb)
 #pragma unroll
-            for (int c = 0; c < 2; ++c)
+                for (int c = 0; c < 2; ++c)
 #pragma unroll
-                for (int jf = 0; jf < 2; ++jf) acc[bb][c][jf] = acc4{0, 0, 0, 0};
-        const T *wrow = wtab + (size_t)(quarter * q) * nR + j0 + row;
-        C2 xa = pa[0];
-        C2 xb[4];
-#pragma unroll
-        for (int bb = 0; bb < 4; ++bb) xb[bb] = pb[(size_t)bb * nr];
-        T w0 = wrow[0], w1 = wrow[16];
-        for (int s = 0; s < q; ++s) {
-            const int sn = (s + 1 < q) ? s + 1 : s;
-            const C2 xa_n = pa[sn];
-            C2 xb_n[4];
-#pragma unroll
-            for (int bb = 0; bb < 4; ++bb) xb_n[bb] = pb[(size_t)bb * nr + sn];
-            const T w0_n = wrow[(size_t)sn * nR];
-            const T w1_n = wrow[(size_t)sn * nR + 16];
+                    for (int jf = 0; jf < 2; ++jf) acc[bb][c][jf] = acc4{0, 0, 0, 0};
+        }
+        if (step + 1 < nsteps) fetch(step + 1);
+#pragma unroll 4
+        for (int s = 0; s < QS; ++s) {
+            const int col = quarter * QS + s;
+            const C2 xa = sA[buf][row][col];
+            const T w0 = sW[buf][col][row];
+            const T w1 = sW[buf][col][row + 16];
 #pragma unroll
             for (int bb = 0; bb < 4; ++bb) {
-                const C2 p = cmulc(xb[bb], xa);   // conj(psi1^b_i) psi1^a_i
+                const C2 p = cmulc(sA[buf][16 + 4 * wave + bb][col], xa);   // conj(psi1^b_i) psi1^a_i
                 const T pr = (T)p.x, pi = (T)p.y;
                 acc[bb][0][0] = mfma(pr, w0, acc[bb][0][0]);
                 acc[bb][1][0] = mfma(pi, w0, acc[bb][1][0]);
                 acc[bb][0][1] = mfma(pr, w1, acc[bb][0][1]);
                 acc[bb][1][1] = mfma(pi, w1, acc[bb][1][1]);
             }
-            xa = xa_n;
-#pragma unroll
-            for (int bb = 0; bb < 4; ++bb) xb[bb] = xb_n[bb];
-            w0 = w0_n;
-            w1 = w1_n;
         }
-        // epilogue: lane holds T(b, a = a_base + mfma_row(T, lane, v), j = j0 + 16 jf + row);
-        // multiply by P2 = conj(psi2^b_j) psi2^a_j and sum over the 16 j of the fragment
-        double2 ws[4][4];
+        if (step + 1 < nsteps) stash(buf ^ 1);
+        if (ch == nchunk - 1) {
+            // epilogue: lane holds T(b, a = a_base + mfma_row(T, lane, v), j = j0 + 16 jf + row);
+            // multiply by P2 = conj(psi2^b_j) psi2^a_j and sum over the 16 j of the fragment
+            const int j0 = jt * 32;
+            double2 p2a[2][4];
 #pragma unroll
-        for (int bb = 0; bb < 4; ++bb)
+            for (int jf = 0; jf < 2; ++jf)
 #pragma unroll
-            for (int v = 0; v < 4; ++v) ws[bb][v] = make_double2(0, 0);
-#pragma unroll
-        for (int jf = 0; jf < 2; ++jf) {
-            const int j = j0 + 16 * jf + row;
-            double2 p2a[4];
-#pragma unroll
-            for (int v = 0; v < 4; ++v) p2a[v] = psi2[(size_t)(a_base + mfma_row(T(0), lane, v)) * nR + j];
+                for (int v = 0; v < 4; ++v)
+                    p2a[jf][v] = psi2[(size_t)(a_base + mfma_row(T(0), lane, v)) * nR + j0 + 16 * jf + row];
+            // one b at a time keeps the live registers low
 #pragma unroll
             for (int bb = 0; bb < 4; ++bb) {
-                const double2 p2b = psi2[(size_t)(b_base + bb) * nR + j];
+                double2 ws[4];
+#pragma unroll
+                for (int v = 0; v < 4; ++v) ws[v] = make_double2(0, 0);
+#pragma unroll
+                for (int jf = 0; jf < 2; ++jf) {
+                    const double2 p2b = psi2[(size_t)(b_base + bb) * nR + j0 + 16 * jf + row];
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const double2 P2 = cmulc(p2b, p2a[jf][v]);
+                        const double2 Tv = make_double2((double)acc[bb][0][jf][v], (double)acc[bb][1][jf][v]);
+                        ws[v] = cadd(ws[v], cmul(P2, Tv));
+                    }
+                }
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
-                    const double2 P2 = cmulc(p2b, p2a[v]);
-                    const double2 Tv = make_double2((double)acc[bb][0][jf][v], (double)acc[bb][1][jf][v]);
-                    ws[bb][v] = cadd(ws[bb][v], cmul(P2, Tv));
+                    double2 x = ws[v];
+#pragma unroll
+                    for (int off = 8; off > 0; off >>= 1) {
+                        x.x += __shfl_xor(x.x, off, 16);
+                        x.y += __shfl_xor(x.y, off, 16);
+                    }
+                    if (row == 0) {
+                        double2 &dst = wl[wave][bb][mfma_row(T(0), lane, v)];
+                        dst = cadd(dst, x);
+                    }
                 }
             }
         }
-#pragma unroll
-        for (int bb = 0; bb < 4; ++bb)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                double2 x = ws[bb][v];
-#pragma unroll
-                for (int off = 8; off > 0; off >>= 1) {
-                    x.x += __shfl_xor(x.x, off, 16);
-                    x.y += __shfl_xor(x.y, off, 16);
-                }
-                if (row == 0) {
-                    double2 &dst = wl[wave][bb][mfma_row(T(0), lane, v)];
-                    dst = cadd(dst, x);
-                }
-            }
+        __syncthreads();
     }
-    __syncthreads();
     // write the 4 x 16 partials of this wave
     {
         const int bb = lane >> 4, a = lane & 15;

@@ -1,6 +1,7 @@
 """ICWF throughput benchmark on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp64|mixed] [--no-cpu-baseline]
+                    [--no-serving] [--serve-sims S] [--serve-steps T]
 
 One step = one full pass of the ICWF hot path (Bohmian velocities and
 trajectory update, split-operator propagation of all 2N conditional
@@ -11,8 +12,10 @@ grid.  Inputs are seeded and synthetic and resident in HBM before timing.
 
 Prints one JSON line: traj-steps/s over exactly K timed steps, the roofline
 of the dominant kernel (the two-body contraction, timed live with HIP events
-on the stream it runs on), and the FP64 oracle timed on a bounded sample on the
-host cores.
+on the stream it runs on), the serving mix (served sims/s, p50 / p99
+time-to-result under Poisson arrivals, the speedup over running the same
+simulations one by one in FP64), and the FP64 oracle timed on a bounded sample
+on the host cores.
 """
 
 import argparse
@@ -65,6 +68,9 @@ def parse():
     p.add_argument("--workload", default="sm_n1024")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-steps", type=int, default=2)
+    p.add_argument("--no-serving", action="store_true", help="skip the serving-mix leg")
+    p.add_argument("--serve-sims", type=int, default=32)
+    p.add_argument("--serve-steps", type=int, default=100)
     p.add_argument("--copy-calibration-bytes", type=int, default=0,
                    help="first run a plain device copy of this many bytes three times (the reference kernel "
                         "that scales the HBM traffic counters)")
@@ -176,6 +182,10 @@ def main():
         "kernel_ms_per_step": {k: (ms / n if n else None) for k, (n, ms) in kt.items()},
         "final_norm": obs["norm"],
     }
+    if not args.no_serving:
+        from paper_1805_11169_amd import serving
+        line["serving"] = serving.measure(n_sims=args.serve_sims, n_steps=args.serve_steps,
+                                          log=lambda m: print(m, file=sys.stderr, flush=True))
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(wl, args.cpu_steps)
     print(json.dumps(line), flush=True)

@@ -59,7 +59,8 @@ typedef enum {
     ICWF_ENONFINITE = -4, /* a non-finite value in the inputs or the state           */
     ICWF_ENODE = -5,      /* |Psi| < 1e-300 at a trajectory: velocity undefined      */
     ICWF_ESOLVE = -6,     /* S + eps I not numerically positive definite             */
-    ICWF_ESTATE = -7      /* call not valid in the handle's state (e.g. after error) */
+    ICWF_ESTATE = -7,     /* call not valid in the handle's state (e.g. after error) */
+    ICWF_ETIMEDOUT = -8   /* a bounded wait ended before its condition held          */
 } icwf_status;
 
 typedef enum {

@@ -259,8 +259,8 @@ void enqueue_step(icwf_sim *s, int parity, hipStream_t st) {
 
 icwf_status device_status(icwf_sim *s) {
     int32_t flags[icwf::kNumFlags];
+    HIP_OK(hipMemcpyAsync(flags, s->b.flags, sizeof(flags), hipMemcpyDeviceToHost, s->stream), s);
     HIP_OK(hipStreamSynchronize(s->stream), s);
-    HIP_OK(hipMemcpy(flags, s->b.flags, sizeof(flags), hipMemcpyDeviceToHost), s);
     if (flags[icwf::kFlagNode]) {
         s->status = ICWF_ENODE;
         return fail(s, ICWF_ENODE, "a trajectory sits at a node of the ansatz wavefunction (|Psi| < 1e-300)");
@@ -295,9 +295,10 @@ icwf_status capture_graphs(icwf_sim *s) {
 // strided copy of the leading N x N block of an Np x Np complex matrix
 icwf_status copy_matrix_out(icwf_sim *s, const double2 *dev, double *host) {
     const int N = s->cfg.n_traj;
-    HIP_OK(hipMemcpy2D(host, sizeof(double2) * N, dev, sizeof(double2) * s->Np, sizeof(double2) * N, N,
-                       hipMemcpyDeviceToHost),
+    HIP_OK(hipMemcpy2DAsync(host, sizeof(double2) * N, dev, sizeof(double2) * s->Np, sizeof(double2) * N, N,
+                            hipMemcpyDeviceToHost, s->stream),
            s);
+    HIP_OK(hipStreamSynchronize(s->stream), s);
     return ICWF_OK;
 }
 
@@ -517,9 +518,10 @@ icwf_status icwf_observables(icwf_sim *s, icwf_obs *o) {
     const size_t po = 1 + d.nr + d.nR;
     if (o->pop && d.n_bo) std::copy(buf.begin() + po, buf.begin() + po + d.n_bo, o->pop);
     if (o->D && d.n_bo) std::copy(buf.begin() + po + d.n_bo, buf.begin() + po + d.n_bo + d.n_bo * d.n_bo, o->D);
-    if (o->r) HIP_OK(hipMemcpy(o->r, s->b.r, sizeof(double) * d.N, hipMemcpyDeviceToHost), s);
-    if (o->R) HIP_OK(hipMemcpy(o->R, s->b.R, sizeof(double) * d.N, hipMemcpyDeviceToHost), s);
-    if (o->C) HIP_OK(hipMemcpy(o->C, s->b.C, sizeof(double2) * d.N, hipMemcpyDeviceToHost), s);
+    if (o->r) HIP_OK(hipMemcpyAsync(o->r, s->b.r, sizeof(double) * d.N, hipMemcpyDeviceToHost, s->stream), s);
+    if (o->R) HIP_OK(hipMemcpyAsync(o->R, s->b.R, sizeof(double) * d.N, hipMemcpyDeviceToHost, s->stream), s);
+    if (o->C) HIP_OK(hipMemcpyAsync(o->C, s->b.C, sizeof(double2) * d.N, hipMemcpyDeviceToHost, s->stream), s);
+    HIP_OK(hipStreamSynchronize(s->stream), s);
     o->n_out_of_box = flags[icwf::kFlagOut];
     uint64_t bits;
     std::memcpy(&bits, &scal[0], sizeof(bits));
@@ -533,11 +535,12 @@ icwf_status icwf_get_state(icwf_sim *s, double *r, double *R, double *psi1, doub
     if (!s) return fail(nullptr, ICWF_EINVAL, "sim is NULL");
     HIP_OK(hipStreamSynchronize(s->stream), s);
     const Dims &d = s->d;
-    if (r) HIP_OK(hipMemcpy(r, s->b.r, sizeof(double) * d.N, hipMemcpyDeviceToHost), s);
-    if (R) HIP_OK(hipMemcpy(R, s->b.R, sizeof(double) * d.N, hipMemcpyDeviceToHost), s);
-    if (psi1) HIP_OK(hipMemcpy(psi1, s->b.psi1, sizeof(double2) * (size_t)d.N * d.nr, hipMemcpyDeviceToHost), s);
-    if (psi2) HIP_OK(hipMemcpy(psi2, s->b.psi2, sizeof(double2) * (size_t)d.N * d.nR, hipMemcpyDeviceToHost), s);
-    if (C) HIP_OK(hipMemcpy(C, s->b.C, sizeof(double2) * d.N, hipMemcpyDeviceToHost), s);
+    if (r) HIP_OK(hipMemcpyAsync(r, s->b.r, sizeof(double) * d.N, hipMemcpyDeviceToHost, s->stream), s);
+    if (R) HIP_OK(hipMemcpyAsync(R, s->b.R, sizeof(double) * d.N, hipMemcpyDeviceToHost, s->stream), s);
+    if (psi1) HIP_OK(hipMemcpyAsync(psi1, s->b.psi1, sizeof(double2) * (size_t)d.N * d.nr, hipMemcpyDeviceToHost, s->stream), s);
+    if (psi2) HIP_OK(hipMemcpyAsync(psi2, s->b.psi2, sizeof(double2) * (size_t)d.N * d.nR, hipMemcpyDeviceToHost, s->stream), s);
+    if (C) HIP_OK(hipMemcpyAsync(C, s->b.C, sizeof(double2) * d.N, hipMemcpyDeviceToHost, s->stream), s);
+    HIP_OK(hipStreamSynchronize(s->stream), s);
     return static_cast<icwf_status>(s->status);
 }
 
@@ -565,9 +568,10 @@ icwf_status icwf_velocities(icwf_sim *s, double *v_r, double *v_R, double *psi_a
     HIP_OK(hipGetLastError(), s);
     icwf_status st = device_status(s);
     const Dims &d = s->d;
-    if (v_r) HIP_OK(hipMemcpy(v_r, s->b.v_r, sizeof(double) * d.N, hipMemcpyDeviceToHost), s);
-    if (v_R) HIP_OK(hipMemcpy(v_R, s->b.v_R, sizeof(double) * d.N, hipMemcpyDeviceToHost), s);
-    if (psi_at) HIP_OK(hipMemcpy(psi_at, s->b.psi_at, sizeof(double2) * d.N, hipMemcpyDeviceToHost), s);
+    if (v_r) HIP_OK(hipMemcpyAsync(v_r, s->b.v_r, sizeof(double) * d.N, hipMemcpyDeviceToHost, s->stream), s);
+    if (v_R) HIP_OK(hipMemcpyAsync(v_R, s->b.v_R, sizeof(double) * d.N, hipMemcpyDeviceToHost, s->stream), s);
+    if (psi_at) HIP_OK(hipMemcpyAsync(psi_at, s->b.psi_at, sizeof(double2) * d.N, hipMemcpyDeviceToHost, s->stream), s);
+    HIP_OK(hipStreamSynchronize(s->stream), s);
     return st;
 }
 
@@ -629,6 +633,7 @@ const char *icwf_status_string(int32_t st) {
         case ICWF_ENODE: return "ICWF_ENODE";
         case ICWF_ESOLVE: return "ICWF_ESOLVE";
         case ICWF_ESTATE: return "ICWF_ESTATE";
+        case ICWF_ETIMEDOUT: return "ICWF_ETIMEDOUT";
         default: return "unknown";
     }
 }

@@ -15,7 +15,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libicwf.so")
 
-OK, EINVAL, ENOMEM, EDEVICE, ENONFINITE, ENODE, ESOLVE, ESTATE = 0, -1, -2, -3, -4, -5, -6, -7
+OK, EINVAL, ENOMEM, EDEVICE, ENONFINITE, ENODE, ESOLVE, ESTATE, ETIMEDOUT = 0, -1, -2, -3, -4, -5, -6, -7, -8
 MODEL_SHIN_METIU, MODEL_CAVITY = 1, 2
 PREC_FP64, PREC_MIXED = 0, 1
 
@@ -23,6 +23,9 @@ PREC_FP64, PREC_MIXED = 0, 1
 EXPORTS = ("icwf_workspace_bytes", "icwf_create", "icwf_step", "icwf_sync", "icwf_observables",
            "icwf_get_state", "icwf_get_matrices", "icwf_velocities", "icwf_set_timing", "icwf_kernel_time",
            "icwf_destroy", "icwf_last_error", "icwf_status_string")
+# the entry points include/icwf_serve.h declares
+SERVE_EXPORTS = ("icwf_server_create", "icwf_server_submit", "icwf_server_wait", "icwf_server_result",
+                 "icwf_server_get_stats", "icwf_server_clock", "icwf_server_destroy")
 
 
 class Config(ctypes.Structure):
@@ -43,6 +46,23 @@ class Obs(ctypes.Structure):
                 ("n_out_of_box", c_int32), ("min_abs_psi", c_double)]
 
 
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("max_active", c_int32), ("steps_per_turn", c_int32), ("turns_ahead", c_int32),
+                ("device", c_int32)]
+
+
+class RequestInfo(ctypes.Structure):
+    _fields_ = [("id", c_int64), ("status", c_int32), ("slot", c_int32), ("steps", c_int64),
+                ("t_submit", c_double), ("t_admit", c_double), ("t_done", c_double),
+                ("workspace_bytes", c_size_t), ("message", ctypes.c_char * 192)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", c_int64), ("admitted", c_int64), ("completed", c_int64), ("failed", c_int64),
+                ("active", c_int32), ("pending", c_int32), ("arena_bytes", c_size_t),
+                ("arena_in_use", c_size_t), ("arena_peak", c_size_t), ("peak_active", c_int32)]
+
+
 class ICWFError(RuntimeError):
     def __init__(self, status, message):
         super().__init__(f"{status_string(status)}: {message}")
@@ -58,6 +78,9 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is not built; run `python -m paper_1805_11169_amd.build`")
+        # torch first: its HIP runtime (same soname) then also serves libicwf.so, so the
+        # workspace, the streams and the kernels live in one runtime instance
+        import torch  # noqa: F401
         L = ctypes.CDLL(LIB_PATH)
         L.icwf_workspace_bytes.argtypes = [POINTER(Config)]
         L.icwf_workspace_bytes.restype = c_size_t
@@ -86,6 +109,21 @@ def lib():
         L.icwf_last_error.restype = c_char_p
         L.icwf_status_string.argtypes = [c_int32]
         L.icwf_status_string.restype = c_char_p
+        L.icwf_server_create.argtypes = [POINTER(ServerConfig), c_void_p, c_size_t, POINTER(c_void_p)]
+        L.icwf_server_create.restype = c_int32
+        L.icwf_server_submit.argtypes = [c_void_p, POINTER(Config), _DP, _DP, _DP, _DP, _DP, _DP, _DP, c_int32,
+                                         POINTER(c_int64)]
+        L.icwf_server_submit.restype = c_int32
+        L.icwf_server_wait.argtypes = [c_void_p, c_int64, c_double]
+        L.icwf_server_wait.restype = c_int32
+        L.icwf_server_result.argtypes = [c_void_p, c_int64, POINTER(Obs), POINTER(RequestInfo)]
+        L.icwf_server_result.restype = c_int32
+        L.icwf_server_get_stats.argtypes = [c_void_p, POINTER(ServerStats)]
+        L.icwf_server_get_stats.restype = c_int32
+        L.icwf_server_clock.argtypes = [c_void_p]
+        L.icwf_server_clock.restype = c_double
+        L.icwf_server_destroy.argtypes = [c_void_p]
+        L.icwf_server_destroy.restype = None
         _lib = L
     return _lib
 
@@ -231,6 +269,92 @@ class Simulation:
     def close(self):
         if getattr(self, "h", None):
             lib().icwf_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Continuous batching of independent simulations (include/icwf_serve.h).
+
+    The arena is one torch uint8 tensor of ``arena_bytes`` on the device; the
+    library's scheduler thread admits submitted simulations into it as slots
+    and memory free up and steps them concurrently."""
+
+    def __init__(self, arena_bytes, max_active=8, steps_per_turn=10, turns_ahead=2, device=0):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("the ICWF library needs a GPU; none is visible")
+        L = lib()
+        dev = torch.device("cuda", device) if isinstance(device, int) else torch.device(device)
+        self.arena = torch.empty(int(arena_bytes) + 256, dtype=torch.uint8, device=dev)
+        torch.cuda.synchronize(dev)
+        aligned = (self.arena.data_ptr() + 255) & ~255
+        cfg = ServerConfig(int(max_active), int(steps_per_turn), int(turns_ahead), dev.index or 0)
+        h = c_void_p()
+        st = L.icwf_server_create(byref(cfg), c_void_p(aligned), c_size_t(int(arena_bytes)), byref(h))
+        if st != OK:
+            raise ICWFError(st, "icwf_server_create failed")
+        self.h = h
+        self._cfgs = {}
+
+    def submit(self, cfg, r0, R0, psi1, psi2, C0=None, b0=None, bo=None, n_steps=1):
+        keep = [_f64(r0), _f64(R0), _f64(psi1), _f64(psi2), _f64(C0), _f64(b0), _f64(bo)]
+        rid = c_int64()
+        st = lib().icwf_server_submit(self.h, byref(cfg), *[_ptr(a) for a in keep], int(n_steps), byref(rid))
+        if st != OK:
+            raise ICWFError(st, "icwf_server_submit refused the request")
+        self._cfgs[rid.value] = (cfg.n_traj, cfg.n_r, cfg.n_R, cfg.n_bo)
+        return rid.value
+
+    def submit_workload(self, wl, n_steps, precision=PREC_FP64, C0=None):
+        cfg = config_from_workload(wl, precision)
+        return self.submit(cfg, wl.r0, wl.R0, wl.psi1, wl.psi2, C0=C0, b0=None if C0 is not None else wl.b0,
+                           bo=wl.bo, n_steps=n_steps)
+
+    def wait(self, rid, timeout=-1.0):
+        st = lib().icwf_server_wait(self.h, int(rid), float(timeout))
+        if st == ETIMEDOUT:
+            return False
+        if st != OK:
+            raise ICWFError(st, f"unknown request {rid}")
+        return True
+
+    def result(self, rid):
+        """Final observables and timing of a finished request (then forgotten)."""
+        N, nr, nR, nb = self._cfgs.pop(rid)
+        out = dict(rho_r=np.zeros(nr), rho_R=np.zeros(nR), pop=np.zeros(max(nb, 1)),
+                   D=np.zeros(max(nb * nb, 1)), r=np.zeros(N), R=np.zeros(N), C=np.zeros(2 * N))
+        o = Obs()
+        for k, v in out.items():
+            setattr(o, k, _ptr(v))
+        info = RequestInfo()
+        st = lib().icwf_server_result(self.h, int(rid), byref(o), byref(info))
+        res = dict(t=o.t, step=o.step, norm=o.norm, rho_r=out["rho_r"], rho_R=out["rho_R"], r=out["r"],
+                   R=out["R"], C=out["C"].view(np.complex128), n_out_of_box=o.n_out_of_box,
+                   min_abs_psi=o.min_abs_psi, status=st, slot=info.slot, t_submit=info.t_submit,
+                   t_admit=info.t_admit, t_done=info.t_done, workspace_bytes=info.workspace_bytes,
+                   message=info.message.decode(errors="replace"))
+        if nb:
+            res["pop"] = out["pop"][:nb]
+            res["D"] = out["D"][:nb * nb].reshape(nb, nb)
+        return res
+
+    def stats(self):
+        s = ServerStats()
+        lib().icwf_server_get_stats(self.h, byref(s))
+        return {k: getattr(s, k) for k, _ in ServerStats._fields_}
+
+    def clock(self):
+        return lib().icwf_server_clock(self.h)
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().icwf_server_destroy(self.h)
             self.h = None
 
     def __del__(self):

@@ -13,14 +13,19 @@ from paper_1805_11169_amd import icwf
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-def declared_entry_points():
-    text = open(os.path.join(ROOT, "include", "icwf.h")).read()
-    decl = r"^(?:size_t|icwf_status|void|const char \*)\s*(icwf_[a-z_]+)\s*\("
-    return sorted(set(re.findall(decl, text, flags=re.MULTILINE)))
+def declared_entry_points(header=None):
+    """Functions declared in one header, or in every header under include/."""
+    names = [header] if header else sorted(f for f in os.listdir(os.path.join(ROOT, "include")) if f.endswith(".h"))
+    decl = r"^(?:size_t|icwf_status|void|double|const char \*)\s*(icwf_[a-z_]+)\s*\("
+    found = set()
+    for h in names:
+        found |= set(re.findall(decl, open(os.path.join(ROOT, "include", h)).read(), flags=re.MULTILINE))
+    return sorted(found)
 
 
 def test_header_and_binding_agree():
-    assert declared_entry_points() == sorted(icwf.EXPORTS)
+    assert declared_entry_points("icwf.h") == sorted(icwf.EXPORTS)
+    assert declared_entry_points("icwf_serve.h") == sorted(icwf.SERVE_EXPORTS)
 
 
 def test_library_exports_every_declared_symbol():

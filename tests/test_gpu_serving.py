@@ -1,0 +1,121 @@
+"""The continuous-batching server on the GPU (include/icwf_serve.h): each
+simulation's result in the mix is bitwise its result alone; admission never
+exceeds the arena; a failing simulation does not disturb the others; requests
+that can never fit are refused at submission."""
+
+import numpy as np
+import pytest
+
+from paper_1805_11169_amd import icwf, inputs, serving
+
+pytestmark = pytest.mark.gpu
+
+
+def _requests():
+    """Uneven sizes, grids, models and precisions (small, so the oracle-free
+    alone runs are quick)."""
+    wls = [
+        (inputs.gaussian_basis(37, n_r=128, n_R=64, seed=31), icwf.PREC_FP64, 12),
+        (inputs.gaussian_basis(100, n_r=256, n_R=64, seed=32), icwf.PREC_MIXED, 9),
+        (inputs.shin_metiu(64, n_r=256, n_R=128, n_bo=2, seed=33), icwf.PREC_FP64, 15),
+        (inputs.gaussian_basis(130, n_r=128, n_R=128, seed=34, model=inputs.MODEL_CAVITY), icwf.PREC_FP64, 7),
+        (inputs.shin_metiu(80, n_r=256, n_R=128, params=[19.0, 4.5, 3.1, 4.0], R_center=-3.5, seed=35),
+         icwf.PREC_MIXED, 11),
+        (inputs.gaussian_basis(16, n_r=64, n_R=32, seed=36), icwf.PREC_FP64, 20),
+    ]
+    return wls
+
+
+def _c0(wl):
+    return wl.extra.get("C0") if wl.name.startswith("gaussians") else None
+
+
+def _alone(wl, prec, steps):
+    sim = icwf.Simulation.from_workload(wl, precision=prec, C0=_c0(wl))
+    sim.step(steps)
+    out = sim.observables(check=False)
+    sim.close()
+    return out
+
+
+def _submit(srv, wl, prec, steps):
+    c0 = _c0(wl)
+    return srv.submit(icwf.config_from_workload(wl, prec), wl.r0, wl.R0, wl.psi1, wl.psi2, C0=c0,
+                      b0=None if c0 is not None else wl.b0, bo=wl.bo, n_steps=steps)
+
+
+def _same(a, b):
+    keys = ["norm", "rho_r", "rho_R", "r", "R", "C", "step", "n_out_of_box"]
+    if "pop" in a:
+        keys += ["pop", "D"]
+    return all(np.array_equal(np.asarray(a[k]), np.asarray(b[k])) for k in keys)
+
+
+def test_results_in_the_mix_equal_results_alone():
+    reqs = _requests()
+    print("[case] serving mix of", [(w.name, p, s) for w, p, s in reqs], flush=True)
+    alone = [_alone(*r) for r in reqs]
+    need = [icwf.workspace_bytes(icwf.config_from_workload(w, p)) for w, p, _ in reqs]
+    srv = icwf.Server(2 * sum(need), max_active=4, steps_per_turn=3, turns_ahead=2)
+    ids = [_submit(srv, *r) for r in reqs]
+    got = []
+    for i in ids:
+        assert srv.wait(i, timeout=120.0)
+        got.append(srv.result(i))
+    st = srv.stats()
+    srv.close()
+    for (wl, _, steps), a, g in zip(reqs, alone, got):
+        assert g["status"] == icwf.OK, (wl.name, g["message"])
+        assert g["step"] == steps
+        assert _same(a, g), wl.name
+    assert st["completed"] == len(reqs) and st["failed"] == 0
+    assert st["peak_active"] >= 2          # they did overlap
+
+
+def test_admission_is_bounded_by_the_arena():
+    wls = serving.mix(n_sims=8, n_steps=6, n_choices=(64, 128), seed=5)
+    need = serving.footprints(wls, icwf.PREC_MIXED)
+    arena = 2 * max(need) + 1024            # at most two of the largest fit at once
+    print(f"[case] 8 sims through an arena of {arena} bytes", flush=True)
+    srv = icwf.Server(arena, max_active=8, steps_per_turn=2)
+    ids = [srv.submit_workload(wl, wl.n_steps, icwf.PREC_MIXED) for wl in wls]
+    res = []
+    for i in ids:
+        assert srv.wait(i, timeout=120.0)
+        res.append(srv.result(i))
+    st = srv.stats()
+    srv.close()
+    assert all(r["status"] == icwf.OK for r in res)
+    assert st["arena_peak"] <= arena
+    assert st["completed"] == 8
+    # admitted in arrival order
+    admits = [r["t_admit"] for r in res]
+    assert admits == sorted(admits)
+
+
+def test_a_failing_simulation_leaves_the_others_intact():
+    good = inputs.gaussian_basis(50, n_r=128, n_R=64, seed=41)
+    bad = inputs.gaussian_basis(40, n_r=128, n_R=64, seed=42)
+    bad.psi2[:] = 0.0                       # Psi vanishes everywhere: a node at every trajectory
+    print("[case] node in one of two served simulations", flush=True)
+    alone = _alone(good, icwf.PREC_FP64, 8)
+    srv = icwf.Server(64 << 20, max_active=2, steps_per_turn=2)
+    ib = _submit(srv, bad, icwf.PREC_FP64, 8)
+    ig = _submit(srv, good, icwf.PREC_FP64, 8)
+    assert srv.wait(ib, 120.0) and srv.wait(ig, 120.0)
+    rb, rg = srv.result(ib), srv.result(ig)
+    srv.close()
+    assert rb["status"] == icwf.ENODE and rb["message"]
+    assert rg["status"] == icwf.OK and _same(alone, rg)
+
+
+def test_requests_that_can_never_fit_are_refused():
+    wl = inputs.gaussian_basis(256, n_r=128, n_R=64, seed=43)
+    srv = icwf.Server(1 << 20, max_active=2)
+    with pytest.raises(icwf.ICWFError) as e:
+        _submit(srv, wl, icwf.PREC_FP64, 1)
+    assert e.value.status == icwf.ENOMEM
+    with pytest.raises(icwf.ICWFError) as e:
+        srv.wait(12345, 0.0)
+    assert e.value.status == icwf.ESTATE
+    srv.close()

@@ -98,110 +98,104 @@ __host__ __device__ constexpr int colofs(int j) { return j * NB - j * (j - 1) / 
 __host__ __device__ constexpr int rowofs(int j) { return j * (j + 1) / 2; }
 constexpr int kPacked = NB * (NB + 1) / 2;
 
-// 256 threads: thread t owns row i = t / 4, columns 16 q .. 16 q + 15 with
-// q = t % 4 (the four lanes of a row are adjacent in one wave).
+// Broadcast lane `src` (wave-uniform) of a double to the whole wave.
+__device__ inline double bcast(double v, int src) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), src);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), src);
+    return __hiloint2double(hi, lo);
+}
+
+// The panel: the 64 x 64 diagonal block stacked on this work-group's 64 rows
+// below it (a 128 x 64 slab), eliminated column by column (right-looking):
+// step j takes the pivot d = sqrt(a_jj), scales column j below it by 1/d and
+// subtracts l_rj conj(l_cj) = a_rj conj(a_cj) / d^2 from every later column c.
+// On the diagonal rows this is the Cholesky factor L11; on the rows below it
+// is x L11^H = a.
+// 512 threads: wave g owns slab rows 16 g .. 16 g + 15 (g < 4: diagonal-block
+// rows; g >= 4: 16 of the rows below), lane c owns column c; 16 entries per
+// thread in registers with static indices.  At step j a wave takes its rows'
+// column-j entries from lane j by readlane; the column-j entries of the
+// diagonal rows (the pivot and every lane's a_cj) come through LDS, written by
+// lane j of the diagonal waves as soon as their step j - 1 update is done, so
+// one barrier per step publishes them.  The update runs on every entry of a
+// lane's column, branch-free: entries above the diagonal of the block are
+// updated too but never read (the factor is written from the lower part only).
 //
 // The factored diagonal block goes to a scratch tile, not into A: other
 // work-groups of the same launch may still be reading the unfactored block.
 // Work-group 0 of the next launch (or k_chol_flush after the last panel) copies
 // it into place.
-__global__ void __launch_bounds__(256) k_chol_panel(double2 *A0, double2 *A1, int Np, int kb,
+__global__ void __launch_bounds__(512) k_chol_panel(double2 *A0, double2 *A1, int Np, int kb,
                                                     double2 *__restrict__ diag, int32_t *__restrict__ flags) {
     if (flags[kFlagHalt]) return;
-    __shared__ double2 LP[kPacked];      // the factored block, packed lower, column-major
-    __shared__ double2 colbuf[2][NB];    // pivot columns, alternating with j so that
-                                         // writing column j + 1 never races with reads of column j
-    __shared__ double rdiag[NB];
+    __shared__ double2 lcol[2][NB];      // column j over the diagonal rows, unscaled, alternating with j
+    __shared__ double dpiv[NB];
     double2 *A = blockIdx.y ? A1 : A0;
     double2 *D = diag + (size_t)blockIdx.y * NB * NB;
-    const int t = threadIdx.x, i = t >> 2, q = t & 3, k0 = 16 * q;
+    const int t = threadIdx.x, c = t & 63, g = t >> 6;
     if (blockIdx.x == 0 && kb > 0) {
         const int pb = kb - NB;
-        for (int e = t; e < NB * NB; e += 256) {
+        for (int e = t; e < NB * NB; e += 512) {
             const int rr = e / NB, cc = e % NB;
             if (cc <= rr) A[(size_t)(pb + rr) * Np + pb + cc] = D[e];
         }
     }
-    for (int e = t; e < 2 * NB; e += 256) colbuf[e / NB][e % NB] = make_double2(0.0, 0.0);
+    const bool below = kb + NB < Np;
+    const bool mine = g < 4 || below;                 // rows below exist for this wave
+    const int srow = 16 * g;                          // first slab row of this wave
+    const int grow = g < 4 ? kb + srow : kb + NB + blockIdx.x * NB + 16 * (g - 4);
     double2 a[16];
 #pragma unroll
-    for (int c = 0; c < 16; ++c) a[c] = A[(size_t)(kb + i) * Np + kb + k0 + c];
+    for (int v = 0; v < 16; ++v) a[v] = mine ? A[(size_t)(grow + v) * Np + kb + c] : make_double2(0.0, 0.0);
+    if (c == 0 && g < 4) {
+#pragma unroll
+        for (int v = 0; v < 16; ++v) lcol[0][srow + v] = a[v];
+    }
+    __syncthreads();
     bool bad = false;
-    // j = 16 qj + cj; the quarter loop stays rolled (code size), the column
-    // loop is unrolled so that a[cj] is a register.
 #pragma unroll 1
-    for (int qj = 0; qj < 4; ++qj)
+    for (int j = 0; j < NB; ++j) {
+        const double2 *lj = lcol[j & 1];
+        double piv = lj[j].x;
+        const double2 lcj = lj[c];
+        double2 lr[16];
 #pragma unroll
-    for (int cj = 0; cj < 16; ++cj) {
-        const int j = 16 * qj + cj;
-        double2 *col = colbuf[cj & 1];
-        if (q == qj && i == j) {
-            double dd = a[cj].x;
-            if (!(dd > 0.0)) {
-                bad = true;
-                dd = 1.0;
+        for (int v = 0; v < 16; ++v) lr[v] = make_double2(bcast(a[v].x, j), bcast(a[v].y, j));
+        if (!(piv > 0.0)) {
+            bad = true;
+            piv = 1.0;
+        }
+        const double d = sqrt(piv), dinv = 1.0 / d;
+        if (c > j) {
+            const double2 lc = cscale(cconj(lcj), dinv * dinv);
+#pragma unroll
+            for (int v = 0; v < 16; ++v) a[v] = csub(a[v], cmul(lr[v], lc));
+            if (c == j + 1 && g < 4) {
+                double2 *ln = lcol[(j + 1) & 1];
+#pragma unroll
+                for (int v = 0; v < 16; ++v) ln[srow + v] = a[v];
             }
-            col[j] = make_double2(sqrt(dd), 0.0);
+        } else if (c == j) {
+#pragma unroll
+            for (int v = 0; v < 16; ++v) a[v] = cscale(a[v], dinv);
+            if (t == j) dpiv[j] = d;
         }
         __syncthreads();
-        const double dj = col[j].x;
-        if (q == qj) {
-            if (i > j) {
-                const double2 l = cscale(a[cj], 1.0 / dj);
-                a[cj] = l;
-                col[i] = l;
-            } else if (i == j) {
-                a[cj] = make_double2(dj, 0.0);
+    }
+    if (bad && t == 0 && blockIdx.x == 0) raise_solve(flags);
+    if (g < 4) {
+        if (blockIdx.x == 0) {
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                const int r = srow + v;
+                if (r > c) D[r * NB + c] = a[v];
+                else if (r == c) D[r * NB + c] = make_double2(dpiv[c], 0.0);
             }
         }
-        __syncthreads();
-        if (i > j) {
-            const double2 li = col[i];
+    } else if (below) {
 #pragma unroll
-            for (int c = 0; c < 16; ++c) {
-                const int k = k0 + c;
-                if (k > j && k <= i) a[c] = csub(a[c], cmul(li, cconj(col[k])));
-            }
-        }
+        for (int v = 0; v < 16; ++v) A[(size_t)(grow + v) * Np + kb + c] = a[v];
     }
-    if (bad) raise_solve(flags);
-#pragma unroll
-    for (int c = 0; c < 16; ++c) {
-        const int k = k0 + c;
-        if (k <= i) {
-            LP[colofs(k) + i - k] = a[c];
-            if (blockIdx.x == 0) D[i * NB + k] = a[c];
-        }
-    }
-    __syncthreads();
-    if (t < NB) rdiag[t] = 1.0 / LP[colofs(t)].x;
-    __syncthreads();
-    // rows of the panel below the block: x L11^H = a, column by column
-    // (right-looking): x_j = a_j / L11[j][j], then a_k -= x_j conj(L11[k][j]) for k > j.
-    const int row = kb + NB + blockIdx.x * 64 + i;
-    if (row >= Np) return;
-    double2 *arow = A + (size_t)row * Np + kb + k0;
-#pragma unroll
-    for (int c = 0; c < 16; ++c) a[c] = arow[c];
-    const int lane = t & 63;
-#pragma unroll 1
-    for (int qj = 0; qj < 4; ++qj)
-#pragma unroll
-    for (int cj = 0; cj < 16; ++cj) {
-        const int j = 16 * qj + cj;
-        double2 x = make_double2(0, 0);
-        if (q == qj) x = cscale(a[cj], rdiag[j]);
-        x.x = __shfl(x.x, (lane & ~3) | qj);
-        x.y = __shfl(x.y, (lane & ~3) | qj);
-        if (q == qj) a[cj] = x;
-#pragma unroll
-        for (int c = 0; c < 16; ++c) {
-            const int k = k0 + c;
-            if (k > j) a[c] = csub(a[c], cmul(x, cconj(LP[colofs(j) + k - j])));
-        }
-    }
-#pragma unroll
-    for (int c = 0; c < 16; ++c) arow[c] = a[c];
 }
 
 __global__ void __launch_bounds__(256) k_chol_flush(double2 *A0, double2 *A1, int Np, int kb,
@@ -306,12 +300,6 @@ __device__ inline void publish_block(int32_t *flag) {
     }
 }
 
-// Broadcast lane `src` (wave-uniform) of a double to the whole wave.
-__device__ inline double bcast(double v, int src) {
-    const int lo = __builtin_amdgcn_readlane(__double2loint(v), src);
-    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), src);
-    return __hiloint2double(hi, lo);
-}
 
 // y = M v, one wave per row, four rows per work-group.
 __global__ void __launch_bounds__(256) k_matvec(const double2 *__restrict__ M, const double2 *__restrict__ v,
@@ -358,12 +346,16 @@ __global__ void __launch_bounds__(256) k_rk_fwd(const double2 *__restrict__ rhs,
     // contributions of the blocks above, as they complete
     double2 part = make_double2(0, 0);
     for (int C = 0; C < B; ++C) {
+        // L is an input of the launch: its slice is loaded before the wait
+        double2 lv[16];
+        const double2 *lrow = L + (size_t)(r0 + i) * Np + C * NB + 16 * q;
+#pragma unroll
+        for (int c = 0; c < 16; ++c) lv[c] = halted ? make_double2(0, 0) : lrow[c];
         wait_block(&sync[kSyncFwd + C], flags);
         if (halted) continue;
-        const double2 *lrow = L + (size_t)(r0 + i) * Np + C * NB + 16 * q;
         const double2 *yc = ybuf + C * NB + 16 * q;
 #pragma unroll
-        for (int c = 0; c < 16; ++c) part = cadd(part, cmul(lrow[c], yc[c]));
+        for (int c = 0; c < 16; ++c) part = cadd(part, cmul(lv[c], yc[c]));
     }
     part.x += __shfl_xor(part.x, 1);
     part.y += __shfl_xor(part.y, 1);
@@ -417,12 +409,15 @@ __global__ void __launch_bounds__(256) k_rk_bwd(const double2 *__restrict__ L, c
     // contributions of the blocks below (already solved): sum_k conj(L[C64+k][B64+i]) x[C64+k]
     double2 part = make_double2(0, 0);
     for (int Cb = nblk - 1; Cb > B; --Cb) {
+        double2 lv[16];
+        const double2 *lcol = L + (size_t)(Cb * NB + 16 * q) * Np + r0 + i;
+#pragma unroll
+        for (int c = 0; c < 16; ++c) lv[c] = halted ? make_double2(0, 0) : lcol[(size_t)c * Np];
         wait_block(&sync[kSyncBwd + Cb], flags);
         if (halted) continue;
-        const double2 *lcol = L + (size_t)(Cb * NB + 16 * q) * Np + r0 + i;
         const double2 *xc = xbuf + Cb * NB + 16 * q;
 #pragma unroll
-        for (int c = 0; c < 16; ++c) part = cadd(part, cmul(cconj(lcol[(size_t)c * Np]), xc[c]));
+        for (int c = 0; c < 16; ++c) part = cadd(part, cmul(cconj(lv[c]), xc[c]));
     }
     part.x += __shfl_xor(part.x, 1);
     part.y += __shfl_xor(part.y, 1);
@@ -499,7 +494,7 @@ void launch_cholesky(const Dims &d, const Bufs &b, double2 *A0, double2 *A1, int
     for (int kb = 0; kb < Np; kb += NB) {
         const int below = Np - kb - NB;
         const int gx = below > 0 ? below / 64 : 1;
-        hipLaunchKernelGGL(k_chol_panel, dim3(gx, count), dim3(256), 0, s, A0, A1, Np, kb, b.chol_diag, b.flags);
+        hipLaunchKernelGGL(k_chol_panel, dim3(gx, count), dim3(512), 0, s, A0, A1, Np, kb, b.chol_diag, b.flags);
         if (below > 0) {
             const int mt = below / 32;
             hipLaunchKernelGGL(k_chol_update, dim3(mt * (mt + 1) / 2, count), dim3(64), 0, s, A0, A1, Np, kb,

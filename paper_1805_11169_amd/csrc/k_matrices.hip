@@ -65,20 +65,44 @@ struct ZBatch {
     double scale[6];
 };
 
-// One wave per 32 x 32 output tile (2 x 2 MFMA fragments).  Lane l holds
-// A = X[b0 + 16 f + l%16][k], B = Y[a0 + 16 g + l%16][k], k split in four
-// contiguous quarters by l/16; accumulator register v of lane l is row
-// mfma_row_f64(l, v), column l%16 of its fragment.
-__global__ void __launch_bounds__(64) k_zgemm(ZBatch zb, int Np, const int32_t *__restrict__ flags) {
+// Work-group of 4 waves per 64 x 64 output tile, wave w on the 32 x 32
+// quarter (rows 32 (w / 2), columns 32 (w % 2)) as 2 x 2 MFMA fragments with
+// rows = b, columns = a, k the reduction index; lane l supplies
+// A = X[b][k] and B = Y[a][k] with b, a = l % 16 of the fragment and
+// k = l / 16 of the k step.  The 64 rows of X and of Y of a 16-wide k chunk are
+// staged in LDS (two buffers: the coalesced global loads of chunk c + 1 are in
+// flight while the matrix cores work on chunk c).  Hermitian outputs compute
+// the upper tiles and write the lower ones as their conjugates.
+constexpr int kZT = 64, kZKC = 16, kZLD = kZKC + 1;
+
+// Entry z (wave-uniform) of a kernel-argument array, by selects: an indexed
+// access would copy the whole argument struct to scratch.
+template <typename T>
+__device__ inline T zpick(const T (&a)[6], int z) {
+    T r = a[0];
+    r = z == 1 ? a[1] : r;
+    r = z == 2 ? a[2] : r;
+    r = z == 3 ? a[3] : r;
+    r = z == 4 ? a[4] : r;
+    r = z == 5 ? a[5] : r;
+    return r;
+}
+
+__global__ void __launch_bounds__(256, 2) k_zgemm(ZBatch zb, int Np, const int32_t *__restrict__ flags) {
     if (flags[kFlagHalt]) return;
     const int z = blockIdx.z;
-    const double2 *__restrict__ X = zb.X[z];
-    const double2 *__restrict__ Y = zb.Y[z];
-    const int K = zb.K[z];
-    const int lane = threadIdx.x;
+    const int bt = blockIdx.y, at = blockIdx.x;
+    const double2 *__restrict__ X = zpick(zb.X, z);
+    const double2 *__restrict__ Y = zpick(zb.Y, z);
+    const bool herm = X == Y;   // the output is Hermitian: upper tiles only
+    if (herm && bt > at) return;
+    __shared__ double2 sX[2][kZT][kZLD];
+    __shared__ double2 sY[2][kZT][kZLD];
+    const int K = zpick(zb.K, z);
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int row = lane & 15, quarter = lane >> 4;
-    const int b0 = blockIdx.y * 32, a0 = blockIdx.x * 32;
-    const int q = K >> 2;
+    const int b0 = bt * kZT, a0 = at * kZT;
+    const int wb = 32 * (wave >> 1), wa = 32 * (wave & 1);
     dbl4 re[2][2], im[2][2];
 #pragma unroll
     for (int f = 0; f < 2; ++f)
@@ -87,41 +111,84 @@ __global__ void __launch_bounds__(64) k_zgemm(ZBatch zb, int Np, const int32_t *
             re[f][g] = dbl4{0, 0, 0, 0};
             im[f][g] = dbl4{0, 0, 0, 0};
         }
-    const double2 *xp[2], *yp[2];
-#pragma unroll
-    for (int f = 0; f < 2; ++f) {
-        xp[f] = X + (size_t)(b0 + 16 * f + row) * K + quarter * q;
-        yp[f] = Y + (size_t)(a0 + 16 * f + row) * K + quarter * q;
-    }
-    for (int s = 0; s < q; ++s) {
-        double2 xv[2], yv[2];
-#pragma unroll
-        for (int f = 0; f < 2; ++f) {
-            xv[f] = xp[f][s];
-            yv[f] = yp[f][s];
+    // staging: element e = t + 256 m of a chunk is row e / 16, k e % 16
+    const int srow = t >> 4, sk = t & 15;
+    const double2 *xs = X + (size_t)(b0 + srow) * K + sk;   // rows srow + 16 m
+    const double2 *ys = Y + (size_t)(a0 + srow) * K + sk;
+    const size_t rstep = (size_t)16 * K;
+    double2 rx0 = xs[0], rx1 = xs[rstep], rx2 = xs[2 * rstep], rx3 = xs[3 * rstep];
+    double2 ry0 = ys[0], ry1 = ys[rstep], ry2 = ys[2 * rstep], ry3 = ys[3 * rstep];
+    sX[0][srow][sk] = rx0;
+    sX[0][srow + 16][sk] = rx1;
+    sX[0][srow + 32][sk] = rx2;
+    sX[0][srow + 48][sk] = rx3;
+    sY[0][srow][sk] = ry0;
+    sY[0][srow + 16][sk] = ry1;
+    sY[0][srow + 32][sk] = ry2;
+    sY[0][srow + 48][sk] = ry3;
+    __syncthreads();
+    const int nch = K / kZKC;
+    for (int ch = 0; ch < nch; ++ch) {
+        const int buf = ch & 1;
+        const bool more = ch + 1 < nch;
+        if (more) {
+            const int k0 = (ch + 1) * kZKC;
+            rx0 = xs[k0];
+            rx1 = xs[rstep + k0];
+            rx2 = xs[2 * rstep + k0];
+            rx3 = xs[3 * rstep + k0];
+            ry0 = ys[k0];
+            ry1 = ys[rstep + k0];
+            ry2 = ys[2 * rstep + k0];
+            ry3 = ys[3 * rstep + k0];
         }
 #pragma unroll
-        for (int f = 0; f < 2; ++f)
+        for (int s4 = 0; s4 < kZKC / 4; ++s4) {
+            const int kk = 4 * s4 + quarter;
+            double2 xv[2], yv[2];
 #pragma unroll
-            for (int g = 0; g < 2; ++g) {
-                // conj(x) y = (xr yr + xi yi) + i (xr yi - xi yr)
-                re[f][g] = mfma(xv[f].x, yv[g].x, re[f][g]);
-                re[f][g] = mfma(xv[f].y, yv[g].y, re[f][g]);
-                im[f][g] = mfma(xv[f].x, yv[g].y, im[f][g]);
-                im[f][g] = mfma(-xv[f].y, yv[g].x, im[f][g]);
+            for (int f = 0; f < 2; ++f) {
+                xv[f] = sX[buf][wb + 16 * f + row][kk];
+                yv[f] = sY[buf][wa + 16 * f + row][kk];
             }
+#pragma unroll
+            for (int f = 0; f < 2; ++f)
+#pragma unroll
+                for (int g = 0; g < 2; ++g) {
+                    // conj(x) y = (xr yr + xi yi) + i (xr yi - xi yr)
+                    re[f][g] = mfma(xv[f].x, yv[g].x, re[f][g]);
+                    re[f][g] = mfma(xv[f].y, yv[g].y, re[f][g]);
+                    im[f][g] = mfma(xv[f].x, yv[g].y, im[f][g]);
+                    im[f][g] = mfma(-xv[f].y, yv[g].x, im[f][g]);
+                }
+        }
+        if (more) {
+            const int nb = buf ^ 1;
+            sX[nb][srow][sk] = rx0;
+            sX[nb][srow + 16][sk] = rx1;
+            sX[nb][srow + 32][sk] = rx2;
+            sX[nb][srow + 48][sk] = rx3;
+            sY[nb][srow][sk] = ry0;
+            sY[nb][srow + 16][sk] = ry1;
+            sY[nb][srow + 32][sk] = ry2;
+            sY[nb][srow + 48][sk] = ry3;
+        }
+        __syncthreads();
     }
-    const double sc = zb.scale[z];
-    double2 *out = zb.out[z];
+    const double sc = zpick(zb.scale, z);
+    double2 *out = zpick(zb.out, z);
+    const bool mirror = herm && bt < at;
 #pragma unroll
     for (int f = 0; f < 2; ++f)
 #pragma unroll
         for (int g = 0; g < 2; ++g)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int b = b0 + 16 * f + mfma_row_f64(lane, v);
-                const int a = a0 + 16 * g + row;
-                out[(size_t)b * Np + a] = make_double2(sc * re[f][g][v], sc * im[f][g][v]);
+                const int b = b0 + wb + 16 * f + mfma_row_f64(lane, v);
+                const int a = a0 + wa + 16 * g + row;
+                const double2 o = make_double2(sc * re[f][g][v], sc * im[f][g][v]);
+                out[(size_t)b * Np + a] = o;
+                if (mirror) out[(size_t)a * Np + b] = cconj(o);
             }
 }
 
@@ -442,7 +509,7 @@ void launch_single_species(const Dims &d, const Bufs &b, bool both, hipStream_t 
         add(b.psi1, b.G1b, b.E1b, d.nr, d.hr);
         add(b.psi2, b.G2b, b.E2b, d.nR, d.hR);
     }
-    hipLaunchKernelGGL(k_zgemm, dim3(Np / 32, Np / 32, c), dim3(64), 0, s, zb, Np, b.flags);
+    hipLaunchKernelGGL(k_zgemm, dim3(Np / kZT, Np / kZT, c), dim3(256), 0, s, zb, Np, b.flags);
 }
 
 void launch_wc(const Dims &d, const Bufs &b, hipStream_t s) {

@@ -44,6 +44,7 @@ Bufs carve(const icwf_config &c, char *base, size_t *total) {
     const size_t Np = icwf::padded(c.n_traj), nr = c.n_r, nR = c.n_R, nbo = c.n_bo;
     Bufs b{};
     b.flags = L.take<int32_t>(icwf::kNumFlags);
+    b.wc_queue = L.take<int32_t>(1);
     b.scal = L.take<double>(8);
     b.psi1 = L.take<double2>(Np * nr);
     b.psi2 = L.take<double2>(Np * nR);
@@ -189,6 +190,8 @@ struct icwf_sim {
     int Np = 0;
     hipStream_t stream = nullptr;
     hipStream_t capture_stream = nullptr;
+    hipStream_t side_stream = nullptr;        // the S assembly and the factorisations, beside the contraction
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     hipGraphExec_t exec[2] = {nullptr, nullptr};
     int parity = 0;
     int64_t step = 0;
@@ -239,7 +242,13 @@ void timed(icwf_sim *s, const char *name, hipStream_t st, F fn) {
     s->timers[name].recs.emplace_back(a, b);
 }
 
-void enqueue_step(icwf_sim *s, int parity, hipStream_t st) {
+// One step on stream st.  The two Cholesky factorisations need only S (from
+// the single-species overlaps), not the two-body contraction: after the
+// single-species kernels the step forks, the side stream assembles S and
+// factors S + eps I while st contracts W_c and assembles K, and st waits for
+// the side stream before the RK4 stages.  The persistent contraction leaves CU
+// slots free for the side stream's latency-bound kernels.
+void enqueue_step(icwf_sim *s, int parity, hipStream_t st, hipStream_t side) {
     const Dims &d = s->d;
     const Bufs &b = s->b;
     timed(s, "velocity", st, [&] { icwf::launch_velocity(d, b, true, st); });
@@ -251,9 +260,16 @@ void enqueue_step(icwf_sim *s, int parity, hipStream_t st) {
         icwf::launch_cond_kets(d, b, st);
         icwf::launch_single_species(d, b, true, st);
     });
+    (void)hipEventRecord(s->ev_fork, st);
+    (void)hipStreamWaitEvent(side, s->ev_fork, 0);
+    timed(s, "cholesky", side, [&] {
+        icwf::launch_assemble(d, b, parity, icwf::kAssembleS, side);
+        icwf::launch_cholesky(d, b, b.Lmid, b.L[1 - parity], 2, side);
+    });
+    (void)hipEventRecord(s->ev_join, side);
     timed(s, "wc_contract", st, [&] { icwf::launch_wc(d, b, st); });
-    timed(s, "assemble", st, [&] { icwf::launch_assemble(d, b, parity, false, st); });
-    timed(s, "cholesky", st, [&] { icwf::launch_cholesky(d, b, b.Lmid, b.L[1 - parity], 2, st); });
+    timed(s, "assemble", st, [&] { icwf::launch_assemble(d, b, parity, icwf::kAssembleK, st); });
+    (void)hipStreamWaitEvent(st, s->ev_join, 0);
     timed(s, "rk4", st, [&] { icwf::launch_rk4(d, b, parity, st); });
 }
 
@@ -284,7 +300,7 @@ icwf_status capture_graphs(icwf_sim *s) {
     for (int p = 0; p < 2; ++p) {
         hipGraph_t g = nullptr;
         HIP_OK(hipStreamBeginCapture(s->capture_stream, hipStreamCaptureModeThreadLocal), s);
-        enqueue_step(s, p, s->capture_stream);
+        enqueue_step(s, p, s->capture_stream, s->side_stream);
         HIP_OK(hipStreamEndCapture(s->capture_stream, &g), s);
         HIP_OK(hipGraphInstantiate(&s->exec[p], g, nullptr, nullptr, 0), s);
         HIP_OK(hipGraphDestroy(g), s);
@@ -400,6 +416,13 @@ icwf_status icwf_create(const icwf_config *cfg, const double *r0, const double *
     // mixed form: W_c = (rank-K part, FP64) + (residual, FP32 matrix cores)
     std::vector<double> lr_u, lr_v;
     d.lr_rank = 0;
+    {
+        int dev = 0, ncu = 0;
+        if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu <= 0)
+            ncu = 256;
+        // two contraction work-groups fit a CU; kWcReserve of those slots stay free
+        d.wc_grid = std::max(2 * ncu - icwf::kWcReserve, ncu);
+    }
     if (cfg->precision == ICWF_PREC_MIXED) {
         std::vector<double> res = wc;
         d.lr_rank = cross_approximation(res, nr, nR, kMixedSplitTol, icwf::kLowRankMax, lr_u, lr_v);
@@ -454,7 +477,7 @@ icwf_status icwf_create(const icwf_config *cfg, const double *r0, const double *
     icwf::launch_cond_kets(d, b, st);
     icwf::launch_single_species(d, b, false, st);
     icwf::launch_wc(d, b, st);
-    icwf::launch_assemble(d, b, 0, true, st);
+    icwf::launch_assemble(d, b, 0, icwf::kAssembleInitial, st);
     icwf::launch_cholesky(d, b, b.L[0], b.L[0], 1, st);
     if (!C0) icwf::launch_solve_initial(d, b, 0, b.Cstage, st);
     CREATE_HIP(hipGetLastError());
@@ -464,6 +487,9 @@ icwf_status icwf_create(const icwf_config *cfg, const double *r0, const double *
         return cleanup_fail(ds, m);
     }
     CREATE_HIP(hipStreamCreateWithFlags(&s->capture_stream, hipStreamNonBlocking));
+    CREATE_HIP(hipStreamCreateWithFlags(&s->side_stream, hipStreamNonBlocking));
+    CREATE_HIP(hipEventCreateWithFlags(&s->ev_fork, hipEventDisableTiming));
+    CREATE_HIP(hipEventCreateWithFlags(&s->ev_join, hipEventDisableTiming));
     if (capture_graphs(s) != ICWF_OK) {
         std::string m = s->err;
         return cleanup_fail(ICWF_EDEVICE, m);
@@ -479,7 +505,7 @@ icwf_status icwf_step(icwf_sim *s, int32_t n_steps) {
     if (s->status != ICWF_OK) return fail(s, ICWF_ESTATE, "the simulation stopped on an earlier error");
     for (int k = 0; k < n_steps; ++k) {
         if (s->timing) {
-            enqueue_step(s, s->parity, s->stream);
+            enqueue_step(s, s->parity, s->stream, s->side_stream);
             HIP_OK(hipGetLastError(), s);
         } else {
             HIP_OK(hipGraphLaunch(s->exec[s->parity], s->stream), s);
@@ -611,7 +637,11 @@ void icwf_destroy(icwf_sim *s) {
     if (s->stream || s->capture_stream) (void)hipStreamSynchronize(s->stream);
     for (auto &e : s->exec)
         if (e) (void)hipGraphExecDestroy(e);
+    if (s->side_stream) (void)hipStreamSynchronize(s->side_stream);
     if (s->capture_stream) (void)hipStreamDestroy(s->capture_stream);
+    if (s->side_stream) (void)hipStreamDestroy(s->side_stream);
+    if (s->ev_fork) (void)hipEventDestroy(s->ev_fork);
+    if (s->ev_join) (void)hipEventDestroy(s->ev_join);
     for (auto &kv : s->timers)
         for (auto &pr : kv.second.recs) {
             (void)hipEventDestroy(pr.first);

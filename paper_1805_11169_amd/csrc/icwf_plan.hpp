@@ -13,6 +13,7 @@ namespace icwf {
 struct Dims {
     int N, nr, nR, n_bo, prec;
     int lr_rank;                          // rank of the FP64 part of the mixed contraction
+    int wc_grid;                          // work-groups of the persistent two-body contraction
     double r_min, hr, R_min, hR, m_r, m_R, dt, eps;
     ModelParams mp;
 };
@@ -24,6 +25,7 @@ constexpr int kPad = 64;
 inline int padded(int N) { return (N + kPad - 1) / kPad * kPad; }
 constexpr int kCholNb = 64;      // Cholesky panel width
 constexpr int kLowRankMax = 32;  // largest rank of the FP64 part of the mixed contraction
+constexpr int kWcReserve = 32;   // CU slots the persistent contraction leaves to the other stream
 
 struct Bufs {
     double2 *psi1, *psi2;                 // [N][nr], [N][nR] CWFs (Eq. 7)
@@ -60,6 +62,7 @@ struct Bufs {
     double2 *obs_chi;                     // [n_bo][nR]
     double *obs_out;                      // packed observables
     int32_t *flags;                       // kNumFlags status flags
+    int32_t *wc_queue;                    // tile counter of the persistent two-body contraction
     double *scal;                         // small device scalars (min |Psi|, ...)
 };
 
@@ -82,8 +85,12 @@ void launch_single_species(const Dims &d, const Bufs &b, bool both_conditionings
 // Two-body contraction Wc (upper pair tiles), FP64 or FP32 matrix cores.
 void launch_wc(const Dims &d, const Bufs &b, hipStream_t s);
 
-// S_next, K_minus, K_next, and the midpoint / regularised matrices.
-void launch_assemble(const Dims &d, const Bufs &b, int parity, bool initial, hipStream_t s);
+// The step's matrices from the single-species and two-body blocks:
+//   kAssembleS: S_next and the regularised midpoint / endpoint S + eps I;
+//   kAssembleK: K_minus, K_next and the midpoint K;
+//   kAssembleInitial: S_0, K_0 and S_0 + eps I (start of the run).
+enum AssemblePart { kAssembleS = 1, kAssembleK = 2, kAssembleInitial = 3 };
+void launch_assemble(const Dims &d, const Bufs &b, int parity, AssemblePart part, hipStream_t s);
 
 // In-place lower Cholesky of `count` matrices (pointers in A), each N x N.
 void launch_cholesky(const Dims &d, const Bufs &b, double2 *A0, double2 *A1, int count, hipStream_t s);

@@ -16,6 +16,8 @@
 // tile.  FP64: v_mfma_f64_16x16x4 throughout.  Mixed: P1 and the table in
 // FP32 on v_mfma_f32_16x16x4 with FP32 accumulation over i inside a j tile,
 // the epilogue and the sum over j tiles in FP64.
+#include <algorithm>
+
 #include "icwf_plan.hpp"
 
 namespace icwf {
@@ -235,6 +237,7 @@ __global__ void __launch_bounds__(256, 2) k_wc(const typename WcTraits<T>::cplx 
                                                const double2 *__restrict__ psi2,
                                                const T *__restrict__ wtab, int nr, int nR, double scale,
                                                double2 *__restrict__ Wc, int Np, int accumulate,
+                                               int ntiles, int32_t *__restrict__ queue,
                                                const int32_t *__restrict__ flags) {
     typedef typename WcTraits<T>::acc4 acc4;
     typedef typename WcTraits<T>::cplx C2;
@@ -244,127 +247,138 @@ __global__ void __launch_bounds__(256, 2) k_wc(const typename WcTraits<T>::cplx 
     __shared__ C2 sA[2][32][LDA];      // rows 0..15: a rows, 16..31: b rows of the tile
     __shared__ T sW[2][KC][LDW];
     __shared__ double2 wl[4][4][16];   // [wave][b][a] block partial of Wc
-    int tb, ta;
-    triangle_tile(blockIdx.x, &tb, &ta);
-
-    const int t = threadIdx.x;
-    const int lane = t & 63, wave = t >> 6;
-    const int row = lane & 15, quarter = lane >> 4;
-    const int a_base = ta * 16;
-    const int b_tile = tb * 16;
-    const int b_base = b_tile + 4 * wave;
-
-    for (int e = lane; e < 64; e += 64) wl[wave][e >> 4][e & 15] = make_double2(0, 0);
-
-    const int nchunk = nr / KC, ntj = nR / 32, nsteps = nchunk * ntj;
-    // staging registers for one (j tile, i chunk) step
-    C2 ra[PER];
-    T rw[PER];
-    auto fetch = [&](int step) {
-        const int jt = step / nchunk, ch = step - jt * nchunk;
-        const int i0 = ch * KC, j0 = jt * 32;
-#pragma unroll
-        for (int m = 0; m < PER; ++m) {
-            const int e = t + 256 * m;
-            const int rr = e / KC, cc = e - rr * KC;
-            const int grow = rr < 16 ? a_base + rr : b_tile + rr - 16;
-            ra[m] = psi1[(size_t)grow * nr + i0 + cc];
-            const int ii = e >> 5, jj = e & 31;
-            rw[m] = wtab[(size_t)(i0 + ii) * nR + j0 + jj];
-        }
-    };
-    auto stash = [&](int buf) {
-#pragma unroll
-        for (int m = 0; m < PER; ++m) {
-            const int e = t + 256 * m;
-            const int rr = e / KC, cc = e - rr * KC;
-            sA[buf][rr][cc] = ra[m];
-            sW[buf][e >> 5][e & 31] = rw[m];
-        }
-    };
-
-    acc4 acc[4][2][2];   // [b][re/im][j fragment]
-    fetch(0);
-    stash(0);
-    __syncthreads();
-    for (int step = 0; step < nsteps; ++step) {
-        const int buf = step & 1;
-        const int jt = step / nchunk, ch = step - jt * nchunk;
-        if (ch == 0) {
-#pragma unroll
-            for (int bb = 0; bb < 4; ++bb)
-#pragma unroll
-                for (int c = 0; c < 2; ++c)
-#pragma unroll
-                    for (int jf = 0; jf < 2; ++jf) acc[bb][c][jf] = acc4{0, 0, 0, 0};
-        }
-        if (step + 1 < nsteps) fetch(step + 1);
-#pragma unroll 4
-        for (int s = 0; s < QS; ++s) {
-            const int col = quarter * QS + s;
-            const C2 xa = sA[buf][row][col];
-            const T w0 = sW[buf][col][row];
-            const T w1 = sW[buf][col][row + 16];
-#pragma unroll
-            for (int bb = 0; bb < 4; ++bb) {
-                const C2 p = cmulc(sA[buf][16 + 4 * wave + bb][col], xa);   // conj(psi1^b_i) psi1^a_i
-                const T pr = (T)p.x, pi = (T)p.y;
-                acc[bb][0][0] = mfma(pr, w0, acc[bb][0][0]);
-                acc[bb][1][0] = mfma(pi, w0, acc[bb][1][0]);
-                acc[bb][0][1] = mfma(pr, w1, acc[bb][0][1]);
-                acc[bb][1][1] = mfma(pi, w1, acc[bb][1][1]);
-            }
-        }
-        if (step + 1 < nsteps) stash(buf ^ 1);
-        if (ch == nchunk - 1) {
-            // epilogue: lane holds T(b, a = a_base + mfma_row(T, lane, v), j = j0 + 16 jf + row);
-            // multiply by P2 = conj(psi2^b_j) psi2^a_j and sum over the 16 j of the fragment
-            const int j0 = jt * 32;
-            double2 p2a[2][4];
-#pragma unroll
-            for (int jf = 0; jf < 2; ++jf)
-#pragma unroll
-                for (int v = 0; v < 4; ++v)
-                    p2a[jf][v] = psi2[(size_t)(a_base + mfma_row(T(0), lane, v)) * nR + j0 + 16 * jf + row];
-            // one b at a time keeps the live registers low
-#pragma unroll
-            for (int bb = 0; bb < 4; ++bb) {
-                double2 ws[4];
-#pragma unroll
-                for (int v = 0; v < 4; ++v) ws[v] = make_double2(0, 0);
-#pragma unroll
-                for (int jf = 0; jf < 2; ++jf) {
-                    const double2 p2b = psi2[(size_t)(b_base + bb) * nR + j0 + 16 * jf + row];
-#pragma unroll
-                    for (int v = 0; v < 4; ++v) {
-                        const double2 P2 = cmulc(p2b, p2a[jf][v]);
-                        const double2 Tv = make_double2((double)acc[bb][0][jf][v], (double)acc[bb][1][jf][v]);
-                        ws[v] = cadd(ws[v], cmul(P2, Tv));
-                    }
-                }
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    double2 x = ws[v];
-#pragma unroll
-                    for (int off = 8; off > 0; off >>= 1) {
-                        x.x += __shfl_xor(x.x, off, 16);
-                        x.y += __shfl_xor(x.y, off, 16);
-                    }
-                    if (row == 0) {
-                        double2 &dst = wl[wave][bb][mfma_row(T(0), lane, v)];
-                        dst = cadd(dst, x);
-                    }
-                }
-            }
-        }
+    __shared__ int s_tile;
+    // persistent: the work-group takes upper-triangle tiles from a queue until
+    // none is left (fewer work-groups than CU slots leaves room for work on
+    // another stream)
+    for (;;) {
+        if (threadIdx.x == 0) s_tile = atomicAdd(queue, 1);
         __syncthreads();
-    }
-    // write the 4 x 16 partials of this wave
-    {
-        const int bb = lane >> 4, a = lane & 15;
-        const double2 x = cscale(wl[wave][bb][a], scale);
-        double2 *dst = Wc + (size_t)(b_base + bb) * Np + a_base + a;
-        *dst = accumulate ? cadd(*dst, x) : x;
+        const int tile = s_tile;
+        __syncthreads();
+        if (tile >= ntiles) break;
+        int tb, ta;
+        triangle_tile(tile, &tb, &ta);
+
+        const int t = threadIdx.x;
+        const int lane = t & 63, wave = t >> 6;
+        const int row = lane & 15, quarter = lane >> 4;
+        const int a_base = ta * 16;
+        const int b_tile = tb * 16;
+        const int b_base = b_tile + 4 * wave;
+
+        for (int e = lane; e < 64; e += 64) wl[wave][e >> 4][e & 15] = make_double2(0, 0);
+
+        const int nchunk = nr / KC, ntj = nR / 32, nsteps = nchunk * ntj;
+        // staging registers for one (j tile, i chunk) step
+        C2 ra[PER];
+        T rw[PER];
+        auto fetch = [&](int step) {
+            const int jt = step / nchunk, ch = step - jt * nchunk;
+            const int i0 = ch * KC, j0 = jt * 32;
+    #pragma unroll
+            for (int m = 0; m < PER; ++m) {
+                const int e = t + 256 * m;
+                const int rr = e / KC, cc = e - rr * KC;
+                const int grow = rr < 16 ? a_base + rr : b_tile + rr - 16;
+                ra[m] = psi1[(size_t)grow * nr + i0 + cc];
+                const int ii = e >> 5, jj = e & 31;
+                rw[m] = wtab[(size_t)(i0 + ii) * nR + j0 + jj];
+            }
+        };
+        auto stash = [&](int buf) {
+    #pragma unroll
+            for (int m = 0; m < PER; ++m) {
+                const int e = t + 256 * m;
+                const int rr = e / KC, cc = e - rr * KC;
+                sA[buf][rr][cc] = ra[m];
+                sW[buf][e >> 5][e & 31] = rw[m];
+            }
+        };
+
+        acc4 acc[4][2][2];   // [b][re/im][j fragment]
+        fetch(0);
+        stash(0);
+        __syncthreads();
+        for (int step = 0; step < nsteps; ++step) {
+            const int buf = step & 1;
+            const int jt = step / nchunk, ch = step - jt * nchunk;
+            if (ch == 0) {
+    #pragma unroll
+                for (int bb = 0; bb < 4; ++bb)
+    #pragma unroll
+                    for (int c = 0; c < 2; ++c)
+    #pragma unroll
+                        for (int jf = 0; jf < 2; ++jf) acc[bb][c][jf] = acc4{0, 0, 0, 0};
+            }
+            if (step + 1 < nsteps) fetch(step + 1);
+    #pragma unroll 4
+            for (int s = 0; s < QS; ++s) {
+                const int col = quarter * QS + s;
+                const C2 xa = sA[buf][row][col];
+                const T w0 = sW[buf][col][row];
+                const T w1 = sW[buf][col][row + 16];
+    #pragma unroll
+                for (int bb = 0; bb < 4; ++bb) {
+                    const C2 p = cmulc(sA[buf][16 + 4 * wave + bb][col], xa);   // conj(psi1^b_i) psi1^a_i
+                    const T pr = (T)p.x, pi = (T)p.y;
+                    acc[bb][0][0] = mfma(pr, w0, acc[bb][0][0]);
+                    acc[bb][1][0] = mfma(pi, w0, acc[bb][1][0]);
+                    acc[bb][0][1] = mfma(pr, w1, acc[bb][0][1]);
+                    acc[bb][1][1] = mfma(pi, w1, acc[bb][1][1]);
+                }
+            }
+            if (step + 1 < nsteps) stash(buf ^ 1);
+            if (ch == nchunk - 1) {
+                // epilogue: lane holds T(b, a = a_base + mfma_row(T, lane, v), j = j0 + 16 jf + row);
+                // multiply by P2 = conj(psi2^b_j) psi2^a_j and sum over the 16 j of the fragment
+                const int j0 = jt * 32;
+                double2 p2a[2][4];
+    #pragma unroll
+                for (int jf = 0; jf < 2; ++jf)
+    #pragma unroll
+                    for (int v = 0; v < 4; ++v)
+                        p2a[jf][v] = psi2[(size_t)(a_base + mfma_row(T(0), lane, v)) * nR + j0 + 16 * jf + row];
+                // one b at a time keeps the live registers low
+    #pragma unroll
+                for (int bb = 0; bb < 4; ++bb) {
+                    double2 ws[4];
+    #pragma unroll
+                    for (int v = 0; v < 4; ++v) ws[v] = make_double2(0, 0);
+    #pragma unroll
+                    for (int jf = 0; jf < 2; ++jf) {
+                        const double2 p2b = psi2[(size_t)(b_base + bb) * nR + j0 + 16 * jf + row];
+    #pragma unroll
+                        for (int v = 0; v < 4; ++v) {
+                            const double2 P2 = cmulc(p2b, p2a[jf][v]);
+                            const double2 Tv = make_double2((double)acc[bb][0][jf][v], (double)acc[bb][1][jf][v]);
+                            ws[v] = cadd(ws[v], cmul(P2, Tv));
+                        }
+                    }
+    #pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        double2 x = ws[v];
+    #pragma unroll
+                        for (int off = 8; off > 0; off >>= 1) {
+                            x.x += __shfl_xor(x.x, off, 16);
+                            x.y += __shfl_xor(x.y, off, 16);
+                        }
+                        if (row == 0) {
+                            double2 &dst = wl[wave][bb][mfma_row(T(0), lane, v)];
+                            dst = cadd(dst, x);
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+        }
+        // write the 4 x 16 partials of this wave
+        {
+            const int bb = lane >> 4, a = lane & 15;
+            const double2 x = cscale(wl[wave][bb][a], scale);
+            double2 *dst = Wc + (size_t)(b_base + bb) * Np + a_base + a;
+            *dst = accumulate ? cadd(*dst, x) : x;
+        }
     }
 }
 
@@ -519,8 +533,9 @@ void launch_wc(const Dims &d, const Bufs &b, hipStream_t s) {
     const double scale = d.hr * d.hR;
     if (d.prec == 1) {
         // mixed: FP32 matrix cores on the residual of the rank-K split, FP64 rank-K part added
-        hipLaunchKernelGGL(k_wc<float>, dim3(blocks), dim3(256), 0, s, b.psi1_f32, b.psi2, b.wc32, d.nr, d.nR,
-                           scale, b.Wc, Np, 0, b.flags);
+        launch_fill_i32(b.wc_queue, 1, 0, s);
+        hipLaunchKernelGGL(k_wc<float>, dim3(std::min(blocks, d.wc_grid)), dim3(256), 0, s, b.psi1_f32, b.psi2,
+                           b.wc32, d.nr, d.nR, scale, b.Wc, Np, 0, blocks, b.wc_queue, b.flags);
         if (d.lr_rank > 0) {
             const int T32 = Np / 32;
             const int groups = d.lr_rank < kLrGroups ? d.lr_rank : kLrGroups;
@@ -531,8 +546,9 @@ void launch_wc(const Dims &d, const Bufs &b, hipStream_t s) {
                                b.Wc, Np, b.flags);
         }
     } else {
-        hipLaunchKernelGGL(k_wc<double>, dim3(blocks), dim3(256), 0, s, b.psi1, b.psi2, b.wc64, d.nr, d.nR, scale,
-                           b.Wc, Np, 0, b.flags);
+        launch_fill_i32(b.wc_queue, 1, 0, s);
+        hipLaunchKernelGGL(k_wc<double>, dim3(std::min(blocks, d.wc_grid)), dim3(256), 0, s, b.psi1, b.psi2,
+                           b.wc64, d.nr, d.nR, scale, b.Wc, Np, 0, blocks, b.wc_queue, b.flags);
     }
 }
 

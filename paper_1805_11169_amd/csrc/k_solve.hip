@@ -48,7 +48,7 @@ __global__ void k_assemble(const double2 *__restrict__ S1, const double2 *__rest
                            const double2 *__restrict__ Kcur, const double *__restrict__ r,
                            const double *__restrict__ R, const double *__restrict__ r_new,
                            const double *__restrict__ R_new, ModelParams mp, int N, int Np, double eps,
-                           int initial, double2 *__restrict__ Snext, double2 *__restrict__ Kminus,
+                           int part, double2 *__restrict__ Snext, double2 *__restrict__ Kminus,
                            double2 *__restrict__ Knext, double2 *__restrict__ Amid, double2 *__restrict__ Anext,
                            double2 *__restrict__ Kmid, const int32_t *__restrict__ flags) {
     if (flags[kFlagHalt]) return;
@@ -57,28 +57,31 @@ __global__ void k_assemble(const double2 *__restrict__ S1, const double2 *__rest
     const int b = (int)(idx / Np), a = (int)(idx - (size_t)b * Np);
     const double2 s1 = S1[idx], s2 = S2[idx];
     const double2 S = cmul(s1, s2);
+    const double reg = (a == b) ? eps : 0.0;
+    if (part & kAssembleS) {
+        Snext[idx] = S;
+        Anext[idx] = make_double2(S.x + reg, S.y);
+        if (part == kAssembleS) {
+            const double2 sc = Scur[idx];
+            Amid[idx] = make_double2(0.5 * (sc.x + S.x) + reg, 0.5 * (sc.y + S.y));
+        }
+    }
+    if (!(part & kAssembleK)) return;
     const double2 w = (b <= a) ? Wc[idx] : cconj(Wc[(size_t)a * Np + b]);
     double ca = 0.0, cn = 0.0;
     if (a < N) {
         ca = model_v1(mp, r[a]) + model_v2(mp, R[a]);
         cn = model_v1(mp, r_new[a]) + model_v2(mp, R_new[a]);
     }
-    const double reg = (a == b) ? eps : 0.0;
-    if (initial) {
-        // start of the run: S_0, K_0 = K(psi_0, x_0) -> the slots of parity 0
-        Snext[idx] = S;
-        Knext[idx] = csub(csub(csub(w, cmul(E1a[idx], s2)), cmul(s1, E2a[idx])), cscale(S, ca));
-        Anext[idx] = make_double2(S.x + reg, S.y);
+    const double2 km = csub(csub(csub(w, cmul(E1a[idx], s2)), cmul(s1, E2a[idx])), cscale(S, ca));
+    if (part == kAssembleInitial) {
+        // start of the run: K_0 = K(psi_0, x_0) -> the slot of parity 0
+        Knext[idx] = km;
         return;
     }
-    const double2 km = csub(csub(csub(w, cmul(E1a[idx], s2)), cmul(s1, E2a[idx])), cscale(S, ca));
     const double2 kn = csub(csub(csub(w, cmul(E1b[idx], s2)), cmul(s1, E2b[idx])), cscale(S, cn));
-    const double2 sc = Scur[idx];
-    Snext[idx] = S;
     Kminus[idx] = km;
     Knext[idx] = kn;
-    Anext[idx] = make_double2(S.x + reg, S.y);
-    Amid[idx] = make_double2(0.5 * (sc.x + S.x) + reg, 0.5 * (sc.y + S.y));
     const double2 kc = Kcur[idx];
     Kmid[idx] = make_double2(0.5 * (kc.x + km.x), 0.5 * (kc.y + km.y));
 }
@@ -479,14 +482,14 @@ __global__ void k_fill_i32(int32_t *p, int n, int32_t v) {
 
 }  // namespace
 
-void launch_assemble(const Dims &d, const Bufs &b, int parity, bool initial, hipStream_t s) {
+void launch_assemble(const Dims &d, const Bufs &b, int parity, AssemblePart part, hipStream_t s) {
     const int Np = padded(d.N);
     const size_t tot = (size_t)Np * Np;
+    const bool initial = part == kAssembleInitial;
     const int cur = parity, nxt = initial ? parity : 1 - parity;
     hipLaunchKernelGGL(k_assemble, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, b.S1, b.S2, b.E1a, b.E1b,
                        b.E2a, b.E2b, b.Wc, b.Smat[cur], b.Kmat[cur], b.r, b.R, b.r_new, b.R_new, d.mp, d.N, Np,
-                       d.eps, initial ? 1 : 0, b.Smat[nxt], b.Kminus, b.Kmat[nxt], b.Lmid, b.L[nxt], b.Kmid,
-                       b.flags);
+                       d.eps, (int)part, b.Smat[nxt], b.Kminus, b.Kmat[nxt], b.Lmid, b.L[nxt], b.Kmid, b.flags);
 }
 
 void launch_cholesky(const Dims &d, const Bufs &b, double2 *A0, double2 *A1, int count, hipStream_t s) {

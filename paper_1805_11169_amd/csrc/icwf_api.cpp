@@ -243,12 +243,19 @@ void timed(icwf_sim *s, const char *name, hipStream_t st, F fn) {
 }
 
 // One step on stream st.  The two Cholesky factorisations need only S (from
-// the single-species overlaps), not the two-body contraction: after the
-// single-species kernels the step forks, the side stream assembles S and
-// factors S + eps I while st contracts W_c and assembles K, and st waits for
-// the side stream before the RK4 stages.  The persistent contraction leaves CU
-// slots free for the side stream's latency-bound kernels.
+// the single-species overlaps), not the two-body contraction: from
+// kOverlapMinN padded trajectories on, after the single-species kernels the
+// step forks, the side stream assembles S and factors S + eps I while st
+// contracts W_c and assembles K, and st waits for the side stream before the
+// RK4 stages.  The persistent contraction leaves CU slots free for the side
+// stream's latency-bound kernels.  Smaller simulations (whose contraction
+// does not fill the GPU, and which a server runs many at a time) stay on one
+// stream: event waits between streams would serialise other simulations'
+// work queued behind them on the shared hardware queues.
+constexpr int kOverlapMinN = 1024;
+
 void enqueue_step(icwf_sim *s, int parity, hipStream_t st, hipStream_t side) {
+    if (s->Np < kOverlapMinN) side = st;
     const Dims &d = s->d;
     const Bufs &b = s->b;
     timed(s, "velocity", st, [&] { icwf::launch_velocity(d, b, true, st); });
@@ -260,16 +267,19 @@ void enqueue_step(icwf_sim *s, int parity, hipStream_t st, hipStream_t side) {
         icwf::launch_cond_kets(d, b, st);
         icwf::launch_single_species(d, b, true, st);
     });
-    (void)hipEventRecord(s->ev_fork, st);
-    (void)hipStreamWaitEvent(side, s->ev_fork, 0);
+    const bool fork = side != st;
+    if (fork) {
+        (void)hipEventRecord(s->ev_fork, st);
+        (void)hipStreamWaitEvent(side, s->ev_fork, 0);
+    }
     timed(s, "cholesky", side, [&] {
         icwf::launch_assemble(d, b, parity, icwf::kAssembleS, side);
         icwf::launch_cholesky(d, b, b.Lmid, b.L[1 - parity], 2, side);
     });
-    (void)hipEventRecord(s->ev_join, side);
+    if (fork) (void)hipEventRecord(s->ev_join, side);
     timed(s, "wc_contract", st, [&] { icwf::launch_wc(d, b, st); });
     timed(s, "assemble", st, [&] { icwf::launch_assemble(d, b, parity, icwf::kAssembleK, st); });
-    (void)hipStreamWaitEvent(st, s->ev_join, 0);
+    if (fork) (void)hipStreamWaitEvent(st, s->ev_join, 0);
     timed(s, "rk4", st, [&] { icwf::launch_rk4(d, b, parity, st); });
 }
 

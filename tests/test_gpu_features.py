@@ -96,3 +96,14 @@ def test_observables_skip_null_arrays_and_report_box_exits(wl):
     assert np.isfinite(o["min_abs_psi"]) and o["min_abs_psi"] > 0
     assert 0 <= o["n_out_of_box"] <= wl.n_traj
     sim.close()
+
+
+def test_forked_step_graph_equals_eager_and_repeats():
+    """From 1024 trajectories the step forks (factorisations on a second
+    stream beside the two-body contraction); replay, eager launches and a
+    second run agree bitwise."""
+    w = inputs.gaussian_basis(1024, n_r=64, n_R=32, seed=22)
+    print(f"[case] {w.name} forked step", flush=True)
+    a = _run(w, 3)
+    assert _same(a, _run(w, 3, timing=True))
+    assert _same(a, _run(w, 3))

@@ -85,6 +85,9 @@ Bufs carve(const icwf_config &c, char *base, size_t *total) {
     double2 **mats[] = {&b.S1,      &b.S2,      &b.E1a,     &b.E1b,  &b.E2a,     &b.E2b,   &b.Wc,  &b.Smat[0],
                         &b.Smat[1], &b.Kmat[0], &b.Kmat[1], &b.Kminus, &b.Kmid, &b.L[0], &b.L[1], &b.Lmid};
     for (double2 **m : mats) *m = L.take<double2>(Np * Np);
+    b.Linv[0] = L.take<double2>(Np * icwf::kCholNb);
+    b.Linv[1] = L.take<double2>(Np * icwf::kCholNb);
+    b.Linvmid = L.take<double2>(Np * icwf::kCholNb);
     b.chol_diag = L.take<double2>(2 * icwf::kCholNb * icwf::kCholNb);
     b.xsol = L.take<double2>(Np);
     b.solve_sync = L.take<int32_t>(130);
@@ -274,7 +277,7 @@ void enqueue_step(icwf_sim *s, int parity, hipStream_t st, hipStream_t side) {
     }
     timed(s, "cholesky", side, [&] {
         icwf::launch_assemble(d, b, parity, icwf::kAssembleS, side);
-        icwf::launch_cholesky(d, b, b.Lmid, b.L[1 - parity], 2, side);
+        icwf::launch_cholesky(d, b, b.Lmid, b.L[1 - parity], b.Linvmid, b.Linv[1 - parity], 2, side);
     });
     if (fork) (void)hipEventRecord(s->ev_join, side);
     timed(s, "wc_contract", st, [&] { icwf::launch_wc(d, b, st); });
@@ -488,7 +491,7 @@ icwf_status icwf_create(const icwf_config *cfg, const double *r0, const double *
     icwf::launch_single_species(d, b, false, st);
     icwf::launch_wc(d, b, st);
     icwf::launch_assemble(d, b, 0, icwf::kAssembleInitial, st);
-    icwf::launch_cholesky(d, b, b.L[0], b.L[0], 1, st);
+    icwf::launch_cholesky(d, b, b.L[0], b.L[0], b.Linv[0], b.Linv[0], 1, st);
     if (!C0) icwf::launch_solve_initial(d, b, 0, b.Cstage, st);
     CREATE_HIP(hipGetLastError());
     const icwf_status ds = device_status(s);

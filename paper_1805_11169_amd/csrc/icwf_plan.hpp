@@ -54,6 +54,7 @@ struct Bufs {
     double2 *Smat[2], *Kmat[2];           // S_k, K_k (current / next by step parity)
     double2 *Kminus, *Kmid;               // K(psi_k+1, x_k) and the midpoint K
     double2 *L[2], *Lmid;                 // Cholesky factors of S + eps I (lower)
+    double2 *Linv[2], *Linvmid;           // [Np][64] inverses of their 64 x 64 diagonal blocks
     double2 *chol_diag;                   // [2][64][64] factored diagonal blocks in flight
     double2 *xsol;                        // [Np] back-substitution result of an RK stage
     int32_t *solve_sync;                  // [130] block flags and tickets of the stage solves
@@ -92,8 +93,10 @@ void launch_wc(const Dims &d, const Bufs &b, hipStream_t s);
 enum AssemblePart { kAssembleS = 1, kAssembleK = 2, kAssembleInitial = 3 };
 void launch_assemble(const Dims &d, const Bufs &b, int parity, AssemblePart part, hipStream_t s);
 
-// In-place lower Cholesky of `count` matrices (pointers in A), each N x N.
-void launch_cholesky(const Dims &d, const Bufs &b, double2 *A0, double2 *A1, int count, hipStream_t s);
+// In-place lower Cholesky of `count` matrices (A0, A1), each Np x Np, and the
+// inverses of their 64 x 64 diagonal blocks into X0, X1 ([Np][64]).
+void launch_cholesky(const Dims &d, const Bufs &b, double2 *A0, double2 *A1, double2 *X0, double2 *X1, int count,
+                     hipStream_t s);
 
 // One RK4 step of Eq. 8 with the factors / matrices of the given parity.
 void launch_rk4(const Dims &d, const Bufs &b, int parity, hipStream_t s);

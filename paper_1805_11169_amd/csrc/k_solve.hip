@@ -23,7 +23,8 @@
 // work-groups and two launches over the 64-row blocks of the factor.
 // k_rk_fwd: a work-group solves L y = K v for its block after the blocks
 // above it are done (it waits on their flags and subtracts their
-// contributions as they arrive).
+// contributions as they arrive), then applies the inverse of its diagonal
+// block (from k_tri_inv, computed beside the two-body contraction).
 // k_rk_bwd: the same for L^H x = y from the bottom up, then the stage update
 // k = -i x of its rows.  Work-groups take blocks in ticket order, so a
 // work-group only ever waits on work-groups that are already running, and
@@ -275,6 +276,54 @@ __global__ void __launch_bounds__(64) k_chol_update(double2 *A0, double2 *A1, in
             }
 }
 
+// Inverse of each 64 x 64 diagonal block of a lower Cholesky factor,
+// X_B = L_BB^-1 (lower triangular), row by row: x_rc = (delta_rc -
+// sum_{c <= k < r} L_rk x_kc) / L_rr.  One work-group per block; thread t
+// owns column c = t / 4 of X and the quarter q = t % 4 of the k range, the
+// four partial sums meet by shuffles (the quarters of a column are adjacent
+// lanes of one wave, so no barrier is needed between rows).  The stage
+// solves apply X_B and X_B^H as matrix-vector products instead of a 64-step
+// substitution on their critical path.  Output: X[(B 64 + r) 64 + c].
+__global__ void __launch_bounds__(256) k_tri_inv(const double2 *__restrict__ A0, const double2 *__restrict__ A1,
+                                                 double2 *__restrict__ X0, double2 *__restrict__ X1, int Np,
+                                                 const int32_t *__restrict__ flags) {
+    if (flags[kFlagHalt]) return;
+    // packed lower triangles (66 KB together, so the kernel fits beside a
+    // two-body contraction work-group on one CU): L row-major, X column-major
+    __shared__ double2 sL[kPacked];
+    __shared__ double2 sX[kPacked];
+    const double2 *A = blockIdx.y ? A1 : A0;
+    double2 *X = blockIdx.y ? X1 : X0;
+    const int r0 = blockIdx.x * NB;
+    const int t = threadIdx.x, c = t >> 2, q = t & 3;
+    for (int e = t; e < NB * NB; e += 256) {
+        const int rr = e / NB, cc = e % NB;
+        if (cc <= rr) sL[rowofs(rr) + cc] = A[(size_t)(r0 + rr) * Np + r0 + cc];
+    }
+    __syncthreads();
+#pragma unroll 1
+    for (int r = 0; r < NB; ++r) {
+        double2 acc = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int kk = 0; kk < 16; ++kk) {
+            const int k = 16 * q + kk;
+            if (k >= c && k < r) acc = cadd(acc, cmul(sL[rowofs(r) + k], sX[colofs(c) + k - c]));
+        }
+        acc.x += __shfl_xor(acc.x, 1);
+        acc.y += __shfl_xor(acc.y, 1);
+        acc.x += __shfl_xor(acc.x, 2);
+        acc.y += __shfl_xor(acc.y, 2);
+        if (q == 0 && r >= c)
+            sX[colofs(c) + r - c] =
+                cscale(make_double2((r == c ? 1.0 : 0.0) - acc.x, -acc.y), 1.0 / sL[rowofs(r) + r].x);
+    }
+    __syncthreads();
+    for (int e = t; e < NB * NB; e += 256) {
+        const int rr = e / NB, cc = e % NB;
+        X[(size_t)(r0 + rr) * NB + cc] = cc <= rr ? sX[colofs(cc) + rr - cc] : make_double2(0.0, 0.0);
+    }
+}
+
 // ------------------------------------------------------------------ RK4 stage solves
 // Synchronisation words in the workspace (int32): [0, 64) forward block
 // flags, [64, 128) backward block flags, [128] forward ticket, [129] backward
@@ -322,15 +371,15 @@ __global__ void __launch_bounds__(256) k_matvec(const double2 *__restrict__ M, c
     if (lane == 0) y[rowi] = acc;
 }
 
-// Forward stage kernel: y_B = L_BB^-1 (rhs_B - sum_{C<B} L_BC y_C).
-// 256 threads; thread t: row i = t / 4 of the block, quarter q = t % 4.  The
-// 64-step substitution inside the diagonal block runs in one wave with the
-// solved entry broadcast by readlane and the pivots' reciprocals precomputed.
+// Forward stage kernel: y_B = L_BB^-1 (rhs_B - sum_{C<B} L_BC y_C), with
+// L_BB^-1 from k_tri_inv.  256 threads; thread t: row i = t / 4 of the block,
+// quarter q = t % 4 of the columns.  Everything that does not depend on the
+// blocks above (the block's slices of L and of L_BB^-1) is loaded before the
+// waits.
 __global__ void __launch_bounds__(256) k_rk_fwd(const double2 *__restrict__ rhs, const double2 *__restrict__ L,
-                                                double2 *__restrict__ ybuf, int Np, int32_t *__restrict__ sync,
-                                                int32_t *__restrict__ flags) {
-    __shared__ double2 LPk[kPacked];  // diagonal block L[B64 + i][B64 + j], i >= j, packed column-major
-    __shared__ double2 pr[NB];
+                                                const double2 *__restrict__ Linv, double2 *__restrict__ ybuf,
+                                                int Np, int32_t *__restrict__ sync, int32_t *__restrict__ flags) {
+    __shared__ double2 uvec[NB];
     __shared__ int slot;
     const int B = take_ticket(&sync[kSyncTicketF], &slot);
     if (B == 0) {
@@ -338,18 +387,14 @@ __global__ void __launch_bounds__(256) k_rk_fwd(const double2 *__restrict__ rhs,
         if (threadIdx.x == 0) sync[kSyncTicketB] = 0;
     }
     const bool halted = flags[kFlagHalt] != 0;
-    const int t = threadIdx.x, i = t >> 2, q = t & 3, lane = t & 63, wave = t >> 6;
+    const int t = threadIdx.x, i = t >> 2, q = t & 3;
     const int r0 = B * NB;
-    if (!halted) {
-        for (int e = t; e < NB * NB; e += 256) {
-            const int rr = e / NB, cc = e % NB;
-            if (cc <= rr) LPk[colofs(cc) + rr - cc] = L[(size_t)(r0 + rr) * Np + r0 + cc];
-        }
-    }
+    double2 iv[16];   // row i of L_BB^-1, columns 16 q ..
+#pragma unroll
+    for (int c = 0; c < 16; ++c) iv[c] = halted ? make_double2(0, 0) : Linv[(size_t)(r0 + i) * NB + 16 * q + c];
     // contributions of the blocks above, as they complete
     double2 part = make_double2(0, 0);
     for (int C = 0; C < B; ++C) {
-        // L is an input of the launch: its slice is loaded before the wait
         double2 lv[16];
         const double2 *lrow = L + (size_t)(r0 + i) * Np + C * NB + 16 * q;
 #pragma unroll
@@ -364,35 +409,30 @@ __global__ void __launch_bounds__(256) k_rk_fwd(const double2 *__restrict__ rhs,
     part.y += __shfl_xor(part.y, 1);
     part.x += __shfl_xor(part.x, 2);
     part.y += __shfl_xor(part.y, 2);
-    if (q == 0) pr[i] = part;
+    if (q == 0) uvec[i] = halted ? make_double2(0, 0) : csub(rhs[r0 + i], part);
     __syncthreads();
-    if (!halted && wave == 0) {
-        double2 u = csub(rhs[r0 + lane], pr[lane]);
-        const double inv = 1.0 / LPk[colofs(lane)].x;
-        for (int j = 0; j < NB; ++j) {
-            const double xr = bcast(u.x * inv, j), xi = bcast(u.y * inv, j);
-            // lanes <= j read an earlier column's entry (in bounds, finite), masked out
-            const double m = (lane > j) ? 1.0 : 0.0;
-            u = csub(u, cmul(LPk[colofs(j) + lane - j], make_double2(m * xr, m * xi)));
-            if (lane == j) u = make_double2(xr, xi);
-        }
-        ybuf[r0 + lane] = u;
-    }
+    double2 y = make_double2(0, 0);
+#pragma unroll
+    for (int c = 0; c < 16; ++c) y = cadd(y, cmul(iv[c], uvec[16 * q + c]));
+    y.x += __shfl_xor(y.x, 1);
+    y.y += __shfl_xor(y.y, 1);
+    y.x += __shfl_xor(y.x, 2);
+    y.y += __shfl_xor(y.y, 2);
+    if (!halted && q == 0) ybuf[r0 + i] = y;
     publish_block(&sync[kSyncFwd + B]);
 }
 
 // Backward stage kernel: x_B = L_BB^-H (y_B - sum_{C>B} L_CB^H x_C), blocks
 // from the bottom up; then the RK4 stage update of the block's rows.
 // stage: 1..4; 0 = initial coefficients (C = x).
-__global__ void __launch_bounds__(256) k_rk_bwd(const double2 *__restrict__ L, const double2 *__restrict__ ybuf,
-                                                double2 *__restrict__ xbuf, int Np, int nblk, int stage, double dt,
-                                                int N, double2 *__restrict__ C, double2 *__restrict__ Cacc,
-                                                double2 *__restrict__ Cstage, double *__restrict__ r,
-                                                double *__restrict__ R, const double *__restrict__ r_new,
-                                                const double *__restrict__ R_new, int32_t *__restrict__ sync,
-                                                int32_t *__restrict__ flags) {
-    __shared__ double2 LPr[kPacked];  // diagonal block L[B64 + j][B64 + i], i <= j, packed row-major
-    __shared__ double2 pr[NB];
+__global__ void __launch_bounds__(256) k_rk_bwd(const double2 *__restrict__ L, const double2 *__restrict__ Linv,
+                                                const double2 *__restrict__ ybuf, double2 *__restrict__ xbuf, int Np,
+                                                int nblk, int stage, double dt, int N, double2 *__restrict__ C,
+                                                double2 *__restrict__ Cacc, double2 *__restrict__ Cstage,
+                                                double *__restrict__ r, double *__restrict__ R,
+                                                const double *__restrict__ r_new, const double *__restrict__ R_new,
+                                                int32_t *__restrict__ sync, int32_t *__restrict__ flags) {
+    __shared__ double2 uvec[NB];
     __shared__ int slot;
     const int ticket = take_ticket(&sync[kSyncTicketB], &slot);
     const int B = nblk - 1 - ticket;
@@ -401,14 +441,11 @@ __global__ void __launch_bounds__(256) k_rk_bwd(const double2 *__restrict__ L, c
         if (threadIdx.x == 0) sync[kSyncTicketF] = 0;
     }
     const bool halted = flags[kFlagHalt] != 0;
-    const int t = threadIdx.x, i = t >> 2, q = t & 3, lane = t & 63, wave = t >> 6;
+    const int t = threadIdx.x, i = t >> 2, q = t & 3;
     const int r0 = B * NB;
-    if (!halted) {
-        for (int e = t; e < NB * NB; e += 256) {
-            const int rr = e / NB, cc = e % NB;
-            if (cc <= rr) LPr[rowofs(rr) + cc] = L[(size_t)(r0 + rr) * Np + r0 + cc];
-        }
-    }
+    double2 iv[16];   // column i of L_BB^-1, rows 16 q ..
+#pragma unroll
+    for (int c = 0; c < 16; ++c) iv[c] = halted ? make_double2(0, 0) : Linv[(size_t)(r0 + 16 * q + c) * NB + i];
     // contributions of the blocks below (already solved): sum_k conj(L[C64+k][B64+i]) x[C64+k]
     double2 part = make_double2(0, 0);
     for (int Cb = nblk - 1; Cb > B; --Cb) {
@@ -426,21 +463,19 @@ __global__ void __launch_bounds__(256) k_rk_bwd(const double2 *__restrict__ L, c
     part.y += __shfl_xor(part.y, 1);
     part.x += __shfl_xor(part.x, 2);
     part.y += __shfl_xor(part.y, 2);
-    if (q == 0) pr[i] = part;
+    if (q == 0) uvec[i] = halted ? make_double2(0, 0) : csub(ybuf[r0 + i], part);
     __syncthreads();
-    if (!halted && wave == 0) {
-        double2 u = csub(ybuf[r0 + lane], pr[lane]);
-        const double inv = 1.0 / LPr[rowofs(lane) + lane].x;
-        for (int j = NB - 1; j >= 0; --j) {
-            const double xr = bcast(u.x * inv, j), xi = bcast(u.y * inv, j);
-            // lanes >= j read a later row's entry (in bounds, finite), masked out
-            const double m = (lane < j) ? 1.0 : 0.0;
-            u = csub(u, cmul(cconj(LPr[rowofs(j) + lane]), make_double2(m * xr, m * xi)));
-            if (lane == j) u = make_double2(xr, xi);
-        }
-        xbuf[r0 + lane] = u;
+    double2 u = make_double2(0, 0);
+#pragma unroll
+    for (int c = 0; c < 16; ++c) u = cadd(u, cmul(cconj(iv[c]), uvec[16 * q + c]));
+    u.x += __shfl_xor(u.x, 1);
+    u.y += __shfl_xor(u.y, 1);
+    u.x += __shfl_xor(u.x, 2);
+    u.y += __shfl_xor(u.y, 2);
+    if (!halted && q == 0) {
+        xbuf[r0 + i] = u;
         // stage update of this block's rows
-        const int ii = r0 + lane;
+        const int ii = r0 + i;
         bool bad = false;
         if (stage == 0) {
             C[ii] = (ii < N) ? u : make_double2(0, 0);
@@ -492,7 +527,8 @@ void launch_assemble(const Dims &d, const Bufs &b, int parity, AssemblePart part
                        d.eps, (int)part, b.Smat[nxt], b.Kminus, b.Kmat[nxt], b.Lmid, b.L[nxt], b.Kmid, b.flags);
 }
 
-void launch_cholesky(const Dims &d, const Bufs &b, double2 *A0, double2 *A1, int count, hipStream_t s) {
+void launch_cholesky(const Dims &d, const Bufs &b, double2 *A0, double2 *A1, double2 *X0, double2 *X1, int count,
+                     hipStream_t s) {
     const int Np = padded(d.N);
     for (int kb = 0; kb < Np; kb += NB) {
         const int below = Np - kb - NB;
@@ -505,6 +541,7 @@ void launch_cholesky(const Dims &d, const Bufs &b, double2 *A0, double2 *A1, int
         }
     }
     hipLaunchKernelGGL(k_chol_flush, dim3(1, count), dim3(256), 0, s, A0, A1, Np, Np - NB, b.chol_diag, b.flags);
+    hipLaunchKernelGGL(k_tri_inv, dim3(Np / NB, count), dim3(256), 0, s, A0, A1, X0, X1, Np, b.flags);
 }
 
 void launch_rk4(const Dims &d, const Bufs &b, int parity, hipStream_t s) {
@@ -512,20 +549,23 @@ void launch_rk4(const Dims &d, const Bufs &b, int parity, hipStream_t s) {
     const int cur = parity, nxt = 1 - parity;
     const double2 *Ks[4] = {b.Kmat[cur], b.Kmid, b.Kmid, b.Kminus};
     const double2 *Ls[4] = {b.L[cur], b.Lmid, b.Lmid, b.L[nxt]};
+    const double2 *Xs[4] = {b.Linv[cur], b.Linvmid, b.Linvmid, b.Linv[nxt]};
     for (int st = 1; st <= 4; ++st) {
         const double2 *v = (st == 1) ? b.C : b.Cstage;
         hipLaunchKernelGGL(k_matvec, dim3(Np / 4), dim3(256), 0, s, Ks[st - 1], v, b.rhs, Np, b.flags);
-        hipLaunchKernelGGL(k_rk_fwd, dim3(nblk), dim3(256), 0, s, b.rhs, Ls[st - 1], b.y, Np, b.solve_sync, b.flags);
-        hipLaunchKernelGGL(k_rk_bwd, dim3(nblk), dim3(256), 0, s, Ls[st - 1], b.y, b.xsol, Np, nblk, st, d.dt, d.N,
-                           b.C, b.Cacc, b.Cstage, b.r, b.R, b.r_new, b.R_new, b.solve_sync, b.flags);
+        hipLaunchKernelGGL(k_rk_fwd, dim3(nblk), dim3(256), 0, s, b.rhs, Ls[st - 1], Xs[st - 1], b.y, Np,
+                           b.solve_sync, b.flags);
+        hipLaunchKernelGGL(k_rk_bwd, dim3(nblk), dim3(256), 0, s, Ls[st - 1], Xs[st - 1], b.y, b.xsol, Np, nblk, st,
+                           d.dt, d.N, b.C, b.Cacc, b.Cstage, b.r, b.R, b.r_new, b.R_new, b.solve_sync, b.flags);
     }
 }
 
 void launch_solve_initial(const Dims &d, const Bufs &b, int parity, double2 *rhs, hipStream_t s) {
     const int Np = padded(d.N), nblk = Np / NB;
-    hipLaunchKernelGGL(k_rk_fwd, dim3(nblk), dim3(256), 0, s, rhs, b.L[parity], b.y, Np, b.solve_sync, b.flags);
-    hipLaunchKernelGGL(k_rk_bwd, dim3(nblk), dim3(256), 0, s, b.L[parity], b.y, b.xsol, Np, nblk, 0, d.dt, d.N,
-                       b.C, b.Cacc, b.Cstage, b.r, b.R, b.r_new, b.R_new, b.solve_sync, b.flags);
+    hipLaunchKernelGGL(k_rk_fwd, dim3(nblk), dim3(256), 0, s, rhs, b.L[parity], b.Linv[parity], b.y, Np,
+                       b.solve_sync, b.flags);
+    hipLaunchKernelGGL(k_rk_bwd, dim3(nblk), dim3(256), 0, s, b.L[parity], b.Linv[parity], b.y, b.xsol, Np, nblk, 0,
+                       d.dt, d.N, b.C, b.Cacc, b.Cstage, b.r, b.R, b.r_new, b.R_new, b.solve_sync, b.flags);
 }
 
 void launch_fill_i32(int32_t *p, int n, int32_t v, hipStream_t s) {

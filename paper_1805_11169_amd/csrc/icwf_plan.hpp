@@ -25,7 +25,7 @@ constexpr int kPad = 64;
 inline int padded(int N) { return (N + kPad - 1) / kPad * kPad; }
 constexpr int kCholNb = 64;      // Cholesky panel width
 constexpr int kLowRankMax = 32;  // largest rank of the FP64 part of the mixed contraction
-constexpr int kWcReserve = 32;   // CU slots the persistent contraction leaves to the other stream
+constexpr int kWcReserve = 64;   // CU slots the persistent contraction leaves to the other stream
 
 struct Bufs {
     double2 *psi1, *psi2;                 // [N][nr], [N][nR] CWFs (Eq. 7)

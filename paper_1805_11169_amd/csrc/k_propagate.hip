@@ -10,7 +10,7 @@
 // Stockham FFT reads and the set its last pass writes, so the potential phase
 // and the first forward pass, the last forward pass, the kinetic phase and the
 // first inverse pass, and the last inverse pass and the store all run in
-// registers.  The passes between them go through LDS (radix 8, with one radix
+// registers.  The passes between them go through two LDS buffers (radix 8, with one radix
 // 2 or 4 pass first when log2 n is not a multiple of 3; twiddles from a
 // table).  The CWF is read once from HBM and written once, both coalesced.
 // The potential phase is evaluated once per point (one erf, one sincos) and
@@ -23,6 +23,12 @@ namespace icwf {
 namespace {
 
 constexpr int kPts = 8;   // points per thread
+
+// LDS position of FFT element i: one pad slot after every 8 elements.  The
+// early Stockham passes write with strides 8 and 64 (element 8 t + r, and
+// 64 u + k + 8 r); padded, every 16 consecutive lanes hit 16 different
+// 16-byte bank groups instead of a handful.
+__device__ inline int lp(int i) { return i + (i >> 3); }
 
 __device__ inline void dft2(double2 &a, double2 &b) {
     const double2 t = a;
@@ -63,12 +69,13 @@ __device__ inline void dft8(double2 (&u)[8]) {
 // One Stockham pass of radix R, Ns = size of the sub-transforms already done.
 // The thread's 8 values are 8/R butterflies; butterfly b (index
 // j = t + b n/8 among the n/R of the pass) takes v[b + r 8/R], r = 0..R-1,
-// read from sh[j + r n/R], twiddled by exp(-2 pi i r k / (Ns R)) with
-// k = j mod Ns, and its outputs go to sh[(j - k) R + k + r Ns].  The first
+// read from src[j + r n/R], twiddled by exp(-2 pi i r k / (Ns R)) with
+// k = j mod Ns, and its outputs go to dst[(j - k) R + k + r Ns].  The first
 // pass takes its inputs from registers and the last keeps its outputs there;
-// on both ends v[m] is the point t + m n/8.
+// on both ends v[m] is the point t + m n/8.  src and dst are different LDS
+// buffers, so one barrier per pass (after the writes) orders everything.
 template <int R>
-__device__ inline void fft_pass(double2 (&v)[kPts], double2 *sh, int n, int Ns, int t,
+__device__ inline void fft_pass(double2 (&v)[kPts], const double2 *src, double2 *dst, int n, int Ns, int t,
                                 const double2 *__restrict__ tw, bool first, bool last) {
     constexpr int S = kPts / R;
     const int q = n / kPts;
@@ -77,15 +84,23 @@ __device__ inline void fft_pass(double2 (&v)[kPts], double2 *sh, int n, int Ns, 
 #pragma unroll
         for (int b = 0; b < S; ++b)
 #pragma unroll
-            for (int r = 0; r < R; ++r) v[b + r * S] = sh[t + b * q + r * nR];
+            for (int r = 0; r < R; ++r) v[b + r * S] = src[lp(t + b * q + r * nR)];
     }
     if (Ns > 1) {
         const int st = n / (Ns * R);
 #pragma unroll
         for (int b = 0; b < S; ++b) {
             const int k = (t + b * q) & (Ns - 1);
+            // w^r from one table entry w = exp(-2 pi i k / (Ns R)) by products
+            // (a few ulp, far below the FFT's own rounding): one load instead
+            // of R - 1 in flight per butterfly
+            const double2 w = tw[(k * st) & (n - 1)];
+            double2 wr = w;
 #pragma unroll
-            for (int r = 1; r < R; ++r) v[b + r * S] = cmul(v[b + r * S], tw[(r * k * st) & (n - 1)]);
+            for (int r = 1; r < R; ++r) {
+                v[b + r * S] = cmul(v[b + r * S], wr);
+                if (r + 1 < R) wr = cmul(wr, w);
+            }
         }
     }
 #pragma unroll
@@ -104,34 +119,41 @@ __device__ inline void fft_pass(double2 (&v)[kPts], double2 *sh, int n, int Ns, 
         }
     }
     if (!last) {
-        __syncthreads();   // every read of sh in this pass is done
 #pragma unroll
         for (int b = 0; b < S; ++b) {
             const int j = t + b * q, k = j & (Ns - 1);
 #pragma unroll
-            for (int r = 0; r < R; ++r) sh[(j - k) * R + k + r * Ns] = v[b + r * S];
+            for (int r = 0; r < R; ++r) dst[lp((j - k) * R + k + r * Ns)] = v[b + r * S];
         }
         __syncthreads();
     }
 }
 
 // Forward DFT (unnormalised) of the CWF held as v[m] = x[t + m n/8]; returns
-// X[t + m n/8] in v[m].
-__device__ inline void fft8(double2 (&v)[kPts], double2 *sh, int n, int log2n, int t,
+// X[t + m n/8] in v[m].  sh holds two buffers of stride ld; par is the buffer
+// the next pass writes, kept across calls so that the first pass of one
+// transform never writes the buffer the last pass of the previous one reads.
+__device__ inline void fft8(double2 (&v)[kPts], double2 *sh, int ld, int &par, int n, int log2n, int t,
                             const double2 *__restrict__ tw) {
     const int rem = log2n % 3;
     const int npass = (log2n + 2) / 3;
     int Ns = 1, pass = 0;
     if (rem == 1) {
-        fft_pass<2>(v, sh, n, Ns, t, tw, true, npass == 1);
+        fft_pass<2>(v, sh + (par ^ 1) * ld, sh + par * ld, n, Ns, t, tw, true, npass == 1);
+        par ^= 1;
         Ns = 2;
         pass = 1;
     } else if (rem == 2) {
-        fft_pass<4>(v, sh, n, Ns, t, tw, true, npass == 1);
+        fft_pass<4>(v, sh + (par ^ 1) * ld, sh + par * ld, n, Ns, t, tw, true, npass == 1);
+        par ^= 1;
         Ns = 4;
         pass = 1;
     }
-    for (; Ns < n; Ns *= 8, ++pass) fft_pass<8>(v, sh, n, Ns, t, tw, pass == 0, pass == npass - 1);
+    for (; Ns < n; Ns *= 8, ++pass) {
+        const bool last = pass == npass - 1;
+        fft_pass<8>(v, sh + (par ^ 1) * ld, sh + par * ld, n, Ns, t, tw, pass == 0, last);
+        if (!last) par ^= 1;
+    }
 }
 
 // blockDim.x = max(64, n/8) threads: n/8 per CWF, blockDim.x / (n/8) CWFs.
@@ -148,13 +170,19 @@ __global__ void __launch_bounds__(512) k_propagate(double2 *__restrict__ psi, in
     const int cpb = blockDim.x / q;
     const int lc = threadIdx.x / q, t = threadIdx.x - lc * q;
     const int cw = blockIdx.x * cpb + lc;
-    double2 *sh = sh_all + lc * n;
+    const int ld = n + n / 8;                // one padded buffer; two per CWF
+    double2 *sh = sh_all + lc * 2 * ld;
+    int par = 0;
     double2 *p = psi + (size_t)cw * n;
     const double c = cond[cw];
     // part of the conditioned potential that is constant on this CWF's grid
     const double vconst = (species == 1) ? model_v2(mp, c) : model_v1(mp, c);
 
     double2 ph[kPts], v[kPts];
+    // the CWF's loads first: they are in flight while the phases (which do not
+    // depend on them) are evaluated
+#pragma unroll
+    for (int m = 0; m < kPts; ++m) v[m] = p[t + m * q];
 #pragma unroll
     for (int m = 0; m < kPts; ++m) {
         const int i = t + m * q;
@@ -163,15 +191,13 @@ __global__ void __launch_bounds__(512) k_propagate(double2 *__restrict__ psi, in
         double s, co;
         sincos(-0.5 * dt * V, &s, &co);
         ph[m] = make_double2(co, s);
-        v[m] = cmul(ph[m], p[i]);
-        // one point's erf and sincos at a time: interleaving all eight would
-        // need more registers than two work-groups per CU leave
-        __builtin_amdgcn_sched_barrier(0);
     }
-    fft8(v, sh, n, log2n, t, tw);
+#pragma unroll
+    for (int m = 0; m < kPts; ++m) v[m] = cmul(ph[m], v[m]);
+    fft8(v, sh, ld, par, n, log2n, t, tw);
 #pragma unroll
     for (int m = 0; m < kPts; ++m) v[m] = cconj(cmul(kin[t + m * q], v[m]));
-    fft8(v, sh, n, log2n, t, tw);
+    fft8(v, sh, ld, par, n, log2n, t, tw);
     const double inv_n = 1.0 / n;
 #pragma unroll
     for (int m = 0; m < kPts; ++m) {
@@ -197,7 +223,7 @@ void launch_propagate(const Dims &d, const Bufs &b, int species, hipStream_t s) 
     const int T = q < 64 ? 64 : q;           // 64 / q CWFs per work-group below n = 512
     const int cpb = T / q;
     const int grid = padded(d.N) / cpb;      // padded rows hold zero CWFs
-    const size_t lds = sizeof(double2) * (size_t)n * cpb;
+    const size_t lds = sizeof(double2) * (size_t)2 * (n + n / 8) * cpb;
     if (species == 1) {
         hipLaunchKernelGGL(k_propagate, dim3(grid), dim3(T), lds, s, b.psi1, n, ilog2(n), b.vstat_r, d.r_min,
                            d.hr, b.R, 1, d.mp, b.kin_r, b.tw_r, d.dt, d.prec == 1 ? b.psi1_f32 : nullptr,

@@ -277,50 +277,118 @@ __global__ void __launch_bounds__(64) k_chol_update(double2 *A0, double2 *A1, in
 }
 
 // Inverse of each 64 x 64 diagonal block of a lower Cholesky factor,
-// X_B = L_BB^-1 (lower triangular), row by row: x_rc = (delta_rc -
-// sum_{c <= k < r} L_rk x_kc) / L_rr.  One work-group per block; thread t
-// owns column c = t / 4 of X and the quarter q = t % 4 of the k range, the
-// four partial sums meet by shuffles (the quarters of a column are adjacent
-// lanes of one wave, so no barrier is needed between rows).  The stage
-// solves apply X_B and X_B^H as matrix-vector products instead of a 64-step
-// substitution on their critical path.  Output: X[(B 64 + r) 64 + c].
+// X_B = L_BB^-1 (lower triangular), by block recursion:
+//     [[A, 0], [C, D]]^-1 = [[A^-1, 0], [-D^-1 C A^-1, D^-1]].
+// The four 16 x 16 diagonal blocks are inverted by the four waves at once
+// (lane c of wave w substitutes column c of its block in registers:
+// x_rc = (delta_rc - sum_{k<r} L_rk x_kc) / L_rr); the off-diagonal blocks of
+// the two 32 x 32 inverses, then the one of the 64 x 64 inverse, are the
+// products -D^-1 (C A^-1).  One work-group per block, a handful of barriers.
+// The stage solves apply X_B and X_B^H as matrix-vector products instead of a
+// 64-step substitution on their critical path.  Output: X[(B 64 + r) 64 + c].
 __global__ void __launch_bounds__(256) k_tri_inv(const double2 *__restrict__ A0, const double2 *__restrict__ A1,
                                                  double2 *__restrict__ X0, double2 *__restrict__ X1, int Np,
                                                  const int32_t *__restrict__ flags) {
     if (flags[kFlagHalt]) return;
-    // packed lower triangles (66 KB together, so the kernel fits beside a
-    // two-body contraction work-group on one CU): L row-major, X column-major
-    __shared__ double2 sL[kPacked];
-    __shared__ double2 sX[kPacked];
+    // 84 KB of LDS: fits beside a two-body contraction work-group on one CU
+    __shared__ double2 sX[NB][NB + 1];        // the inverse (lower; zero above)
+    __shared__ double2 sD[4][16][17];         // the four 16 x 16 diagonal blocks of L
     const double2 *A = blockIdx.y ? A1 : A0;
     double2 *X = blockIdx.y ? X1 : X0;
     const int r0 = blockIdx.x * NB;
-    const int t = threadIdx.x, c = t >> 2, q = t & 3;
-    for (int e = t; e < NB * NB; e += 256) {
-        const int rr = e / NB, cc = e % NB;
-        if (cc <= rr) sL[rowofs(rr) + cc] = A[(size_t)(r0 + rr) * Np + r0 + cc];
+    const double2 *Lb = A + (size_t)r0 * Np + r0;   // L_BB(r, k) = Lb[r Np + k]
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    for (int e = t; e < NB * (NB + 1); e += 256) sX[e / (NB + 1)][e % (NB + 1)] = make_double2(0.0, 0.0);
+    for (int e = t; e < 4 * 256; e += 256) {
+        const int w = e >> 8, rr = (e >> 4) & 15, cc = e & 15;
+        sD[w][rr][cc] = cc <= rr ? Lb[(size_t)(16 * w + rr) * Np + 16 * w + cc] : make_double2(0.0, 0.0);
     }
     __syncthreads();
-#pragma unroll 1
-    for (int r = 0; r < NB; ++r) {
-        double2 acc = make_double2(0.0, 0.0);
+    // 16 x 16 diagonal blocks
+    if (lane < 16) {
+        const int c = lane, o = 16 * wave;
+        double2 x[16];
 #pragma unroll
-        for (int kk = 0; kk < 16; ++kk) {
-            const int k = 16 * q + kk;
-            if (k >= c && k < r) acc = cadd(acc, cmul(sL[rowofs(r) + k], sX[colofs(c) + k - c]));
+        for (int r = 0; r < 16; ++r) {
+            double2 acc = make_double2(r == c ? 1.0 : 0.0, 0.0);
+#pragma unroll
+            for (int k = 0; k < r; ++k) acc = csub(acc, cmul(sD[wave][r][k], x[k]));
+            x[r] = cscale(acc, 1.0 / sD[wave][r][r].x);
         }
-        acc.x += __shfl_xor(acc.x, 1);
-        acc.y += __shfl_xor(acc.y, 1);
-        acc.x += __shfl_xor(acc.x, 2);
-        acc.y += __shfl_xor(acc.y, 2);
-        if (q == 0 && r >= c)
-            sX[colofs(c) + r - c] =
-                cscale(make_double2((r == c ? 1.0 : 0.0) - acc.x, -acc.y), 1.0 / sL[rowofs(r) + r].x);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) sX[o + r][o + c] = x[r];
     }
     __syncthreads();
+    // level 1: blocks (1, 0) and (3, 2) of 16: T = L_ba X_aa into sX, then -X_bb T
+    {
+        const int p = t >> 7, u = t & 127;            // pair p, 128 threads per pair, 2 outputs each
+        const int a = 2 * p, bb = 2 * p + 1;
+        double2 o2[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int e = u + 128 * h, r = e >> 4, c = e & 15;
+            double2 acc = make_double2(0.0, 0.0);
+            for (int k = c; k < 16; ++k)
+                acc = cadd(acc, cmul(Lb[(size_t)(16 * bb + r) * Np + 16 * a + k], sX[16 * a + k][16 * a + c]));
+            o2[h] = acc;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int e = u + 128 * h, r = e >> 4, c = e & 15;
+            sX[16 * bb + r][16 * a + c] = o2[h];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int e = u + 128 * h, r = e >> 4, c = e & 15;
+            double2 acc = make_double2(0.0, 0.0);
+            for (int k = 0; k <= r; ++k) acc = cadd(acc, cmul(sX[16 * bb + r][16 * bb + k], sX[16 * bb + k][16 * a + c]));
+            o2[h] = make_double2(-acc.x, -acc.y);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int e = u + 128 * h, r = e >> 4, c = e & 15;
+            sX[16 * bb + r][16 * a + c] = o2[h];
+        }
+        __syncthreads();
+    }
+    // level 2: block (1, 0) of 32: T = L_BA X_AA, then -X_BB T (4 outputs per thread)
+    {
+        double2 o4[4];
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+            const int e = t + 256 * h, r = e >> 5, c = e & 31;
+            double2 acc = make_double2(0.0, 0.0);
+            for (int k = c; k < 32; ++k) acc = cadd(acc, cmul(Lb[(size_t)(32 + r) * Np + k], sX[k][c]));
+            o4[h] = acc;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+            const int e = t + 256 * h, r = e >> 5, c = e & 31;
+            sX[32 + r][c] = o4[h];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+            const int e = t + 256 * h, r = e >> 5, c = e & 31;
+            double2 acc = make_double2(0.0, 0.0);
+            for (int k = 0; k <= r; ++k) acc = cadd(acc, cmul(sX[32 + r][32 + k], sX[32 + k][c]));
+            o4[h] = make_double2(-acc.x, -acc.y);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+            const int e = t + 256 * h, r = e >> 5, c = e & 31;
+            sX[32 + r][c] = o4[h];
+        }
+        __syncthreads();
+    }
     for (int e = t; e < NB * NB; e += 256) {
         const int rr = e / NB, cc = e % NB;
-        X[(size_t)(r0 + rr) * NB + cc] = cc <= rr ? sX[colofs(cc) + rr - cc] : make_double2(0.0, 0.0);
+        X[(size_t)(r0 + rr) * NB + cc] = sX[rr][cc];
     }
 }
 

@@ -39,9 +39,9 @@ HBM_PEAK_GBS = 8000.0
 # any change the traffic is reported as null until measured again.
 TRAFFIC = {
     "sm_n1024": {
-        "sources_sha256_16": "4f4d5cbc6a5047ba",
-        "fp64": 1707920384.0,      # k_wc<double>: fetch 829785.5 KiB x2, write 8320.0 KiB
-        "mixed": 1038246502.4,     # k_wc<float> + k_wc_lowrank + k_lr_reduce
+        "sources_sha256_16": "6f9fe7b044d89196",
+        "fp64": 1330291507.2,      # k_wc<double>: fetch 644908.9 KiB x2, write 9295.0 KiB
+        "mixed": 920872140.8,     # k_wc<float> + k_wc_lowrank + k_lr_reduce
     },
 }
 TRAFFIC_SOURCES = ("paper_1805_11169_amd/csrc/k_matrices.hip", "paper_1805_11169_amd/csrc/icwf_device.hpp")

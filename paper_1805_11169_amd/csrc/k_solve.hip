@@ -290,30 +290,26 @@ __global__ void __launch_bounds__(256) k_tri_inv(const double2 *__restrict__ A0,
                                                  double2 *__restrict__ X0, double2 *__restrict__ X1, int Np,
                                                  const int32_t *__restrict__ flags) {
     if (flags[kFlagHalt]) return;
-    // 84 KB of LDS: fits beside a two-body contraction work-group on one CU
+    // 66.5 KB of LDS: fits beside a two-body contraction work-group on one CU
     __shared__ double2 sX[NB][NB + 1];        // the inverse (lower; zero above)
-    __shared__ double2 sD[4][16][17];         // the four 16 x 16 diagonal blocks of L
     const double2 *A = blockIdx.y ? A1 : A0;
     double2 *X = blockIdx.y ? X1 : X0;
     const int r0 = blockIdx.x * NB;
     const double2 *Lb = A + (size_t)r0 * Np + r0;   // L_BB(r, k) = Lb[r Np + k]
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     for (int e = t; e < NB * (NB + 1); e += 256) sX[e / (NB + 1)][e % (NB + 1)] = make_double2(0.0, 0.0);
-    for (int e = t; e < 4 * 256; e += 256) {
-        const int w = e >> 8, rr = (e >> 4) & 15, cc = e & 15;
-        sD[w][rr][cc] = cc <= rr ? Lb[(size_t)(16 * w + rr) * Np + 16 * w + cc] : make_double2(0.0, 0.0);
-    }
     __syncthreads();
-    // 16 x 16 diagonal blocks
+    // 16 x 16 diagonal blocks (their entries are the same for every lane: cached loads)
     if (lane < 16) {
         const int c = lane, o = 16 * wave;
+        const double2 *Ld = Lb + (size_t)o * Np + o;
         double2 x[16];
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
             double2 acc = make_double2(r == c ? 1.0 : 0.0, 0.0);
 #pragma unroll
-            for (int k = 0; k < r; ++k) acc = csub(acc, cmul(sD[wave][r][k], x[k]));
-            x[r] = cscale(acc, 1.0 / sD[wave][r][r].x);
+            for (int k = 0; k < r; ++k) acc = csub(acc, cmul(Ld[(size_t)r * Np + k], x[k]));
+            x[r] = cscale(acc, 1.0 / Ld[(size_t)r * Np + r].x);
         }
 #pragma unroll
         for (int r = 0; r < 16; ++r) sX[o + r][o + c] = x[r];

@@ -435,6 +435,8 @@ icwf_status icwf_create(const icwf_config *cfg, const double *r0, const double *
             ncu = 256;
         // two contraction work-groups fit a CU; kWcReserve of those slots stay free
         d.wc_grid = std::max(2 * ncu - icwf::kWcReserve, ncu);
+        d.prop_grid[0] = icwf::propagate_grid(nr, N, ncu);
+        d.prop_grid[1] = icwf::propagate_grid(nR, N, ncu);
     }
     if (cfg->precision == ICWF_PREC_MIXED) {
         std::vector<double> res = wc;

@@ -14,6 +14,7 @@ struct Dims {
     int N, nr, nR, n_bo, prec;
     int lr_rank;                          // rank of the FP64 part of the mixed contraction
     int wc_grid;                          // work-groups of the persistent two-body contraction
+    int prop_grid[2];                     // work-groups of the persistent propagation, per species
     double r_min, hr, R_min, hR, m_r, m_R, dt, eps;
     ModelParams mp;
 };
@@ -72,6 +73,10 @@ struct Bufs {
 // Split-operator step of every CWF of one species; species 1 = electronic
 // (conditioned on R^a), 2 = nuclear (conditioned on r^a).
 void launch_propagate(const Dims &d, const Bufs &b, int species, hipStream_t s);
+
+// Work-groups of the persistent propagation for grid size n and N trajectories:
+// as many as fit the device's ncu compute units at once, at most one per CWF group.
+int propagate_grid(int n, int N, int ncu);
 
 // Periodic-sinc tables at the current positions, velocity contraction and
 // reduction; writes v_r, v_R, psi_at, r_new, R_new (x + dt v) and the flags.

@@ -5,24 +5,32 @@
 //     psi <- e^{-i V dt/2} IFFT[ e^{-i k^2 dt/2m} FFT( e^{-i V dt/2} psi ) ],
 //     V_1^a(r_i) = W(r_i, R^a),   V_2^a(R_j) = W(r^a, R_j).
 //
-// One work-group per CWF (several for small grids).  Thread t of a CWF holds
-// the 8 points t + m n/8, m = 0..7: that is the set the first pass of a
-// Stockham FFT reads and the set its last pass writes, so the potential phase
-// and the first forward pass, the last forward pass, the kinetic phase and the
-// first inverse pass, and the last inverse pass and the store all run in
-// registers.  The passes between them go through two LDS buffers (radix 8, with one radix
-// 2 or 4 pass first when log2 n is not a multiple of 3; twiddles from a
-// table).  The CWF is read once from HBM and written once, both coalesced.
-// The potential phase is evaluated once per point (one erf, one sincos) and
-// kept in registers for both half steps.  The inverse FFT is the forward one
-// applied to the conjugate.  Bound: HBM (2 x 16 bytes per grid point per step).
+// Persistent work-groups: each holds one CWF at a time (several for small
+// grids) and walks the CWFs with the grid's stride, so the tables it keeps in
+// LDS are loaded once per work-group and the stores of one CWF drain while the
+// next one is read and its phases are evaluated.  Thread t of a CWF holds the
+// 8 points t + m n/8, m = 0..7: that is the set the first pass of a Stockham
+// FFT reads and the set its last pass writes, so the potential phase and the
+// first forward pass, the last forward pass, the kinetic phase and the first
+// inverse pass, and the last inverse pass and the store all run in registers.
+// The passes between them go through two LDS buffers (radix 8, with one
+// radix 2 or 4 pass first when log2 n is not a multiple of 3; twiddles from an
+// LDS table).  The CWF is read once from HBM and written once, both
+// coalesced.  The potential phase is evaluated once per point (the coupling
+// from a piecewise-polynomial erf table, e^{i theta} by a reduced Taylor
+// series) and kept in registers for both half steps.  The inverse FFT is
+// the forward one applied to the conjugate.
 #include "icwf_plan.hpp"
+
+#include "erf_table.inc"
 
 namespace icwf {
 
 namespace {
 
 constexpr int kPts = 8;   // points per thread
+// the erf(z)/z table in LDS, in 16-byte slots
+constexpr int kErfTableSlots = (kErfPieces * kErfTerms * 8 + 15) / 16;
 
 // LDS position of FFT element i: one pad slot after every 8 elements.  The
 // early Stockham passes write with strides 8 and 64 (element 8 t + r, and
@@ -76,7 +84,7 @@ __device__ inline void dft8(double2 (&u)[8]) {
 // buffers, so one barrier per pass (after the writes) orders everything.
 template <int R>
 __device__ inline void fft_pass(double2 (&v)[kPts], const double2 *src, double2 *dst, int n, int Ns, int t,
-                                const double2 *__restrict__ tw, bool first, bool last) {
+                                const double2 *tw, bool first, bool last) {
     constexpr int S = kPts / R;
     const int q = n / kPts;
     const int nR = n / R;
@@ -92,9 +100,9 @@ __device__ inline void fft_pass(double2 (&v)[kPts], const double2 *src, double2 
         for (int b = 0; b < S; ++b) {
             const int k = (t + b * q) & (Ns - 1);
             // w^r from one table entry w = exp(-2 pi i k / (Ns R)) by products
-            // (a few ulp, far below the FFT's own rounding): one load instead
-            // of R - 1 in flight per butterfly
-            const double2 w = tw[(k * st) & (n - 1)];
+            // (a few ulp, far below the FFT's own rounding); k st < n / 8, so
+            // the table holds exp(-2 pi i j / n) for j < n / 8 only
+            const double2 w = tw[k * st];
             double2 wr = w;
 #pragma unroll
             for (int r = 1; r < R; ++r) {
@@ -133,31 +141,99 @@ __device__ inline void fft_pass(double2 (&v)[kPts], const double2 *src, double2 
 // X[t + m n/8] in v[m].  sh holds two buffers of stride ld; par is the buffer
 // the next pass writes, kept across calls so that the first pass of one
 // transform never writes the buffer the last pass of the previous one reads.
-__device__ inline void fft8(double2 (&v)[kPts], double2 *sh, int ld, int &par, int n, int log2n, int t,
-                            const double2 *__restrict__ tw) {
-    const int rem = log2n % 3;
-    const int npass = (log2n + 2) / 3;
-    int Ns = 1, pass = 0;
-    if (rem == 1) {
-        fft_pass<2>(v, sh + (par ^ 1) * ld, sh + par * ld, n, Ns, t, tw, true, npass == 1);
+// n = 2^LOG2N is a compile-time constant, so the passes unroll and every LDS
+// index becomes a per-thread base plus an immediate offset.
+template <int LOG2N>
+__device__ inline void fft8(double2 (&v)[kPts], double2 *sh, int ld, int &par, int t, const double2 *tw) {
+    constexpr int n = 1 << LOG2N;
+    constexpr int rem = LOG2N % 3;
+    constexpr int npass = (LOG2N + 2) / 3;
+    constexpr int first8 = rem ? 1 : 0;      // index of the first radix-8 pass
+    if constexpr (rem == 1) {
+        fft_pass<2>(v, sh + (par ^ 1) * ld, sh + par * ld, n, 1, t, tw, true, npass == 1);
         par ^= 1;
-        Ns = 2;
-        pass = 1;
-    } else if (rem == 2) {
-        fft_pass<4>(v, sh + (par ^ 1) * ld, sh + par * ld, n, Ns, t, tw, true, npass == 1);
+    } else if constexpr (rem == 2) {
+        fft_pass<4>(v, sh + (par ^ 1) * ld, sh + par * ld, n, 1, t, tw, true, npass == 1);
         par ^= 1;
-        Ns = 4;
-        pass = 1;
     }
-    for (; Ns < n; Ns *= 8, ++pass) {
+#pragma unroll
+    for (int pass = first8; pass < npass; ++pass) {
+        const int Ns = (rem == 0 ? 1 : (1 << rem)) << (3 * (pass - first8));
         const bool last = pass == npass - 1;
         fft_pass<8>(v, sh + (par ^ 1) * ld, sh + par * ld, n, Ns, t, tw, pass == 0, last);
         if (!last) par ^= 1;
     }
 }
 
-// blockDim.x = max(64, n/8) threads: n/8 per CWF, blockDim.x / (n/8) CWFs.
-__global__ void __launch_bounds__(512) k_propagate(double2 *__restrict__ psi, int n, int log2n,
+// e^{i theta} for |theta| <= pi/4 by the Taylor series of sin and cos in
+// u = theta^2, to degrees 15 and 16: the first dropped terms are below
+// (pi/4)^17/17! = 5e-17 and (pi/4)^18/18! = 2e-18, under half an ulp of
+// the results.  Horner's rule from the highest power.
+__device__ inline double2 expi_small(double th) {
+    const double u = th * th;
+    double s = -1.0 / 1307674368000.0;   // -1/15!
+    s = fma(s, u, 1.0 / 6227020800.0);   // +1/13!
+    s = fma(s, u, -1.0 / 39916800.0);    // -1/11!
+    s = fma(s, u, 1.0 / 362880.0);       // +1/9!
+    s = fma(s, u, -1.0 / 5040.0);        // -1/7!
+    s = fma(s, u, 1.0 / 120.0);          // +1/5!
+    s = fma(s, u, -1.0 / 6.0);           // -1/3!
+    double c = 1.0 / 20922789888000.0;   // +1/16!
+    c = fma(c, u, -1.0 / 87178291200.0); // -1/14!
+    c = fma(c, u, 1.0 / 479001600.0);    // +1/12!
+    c = fma(c, u, -1.0 / 3628800.0);     // -1/10!
+    c = fma(c, u, 1.0 / 40320.0);        // +1/8!
+    c = fma(c, u, -1.0 / 720.0);         // -1/6!
+    c = fma(c, u, 1.0 / 24.0);           // +1/4!
+    c = fma(c, u, -0.5);                 // -1/2!
+    return make_double2(fma(u, c, 1.0), fma(th * u, s, th));
+}
+
+// e^{i theta} for any theta: theta = k pi/2 + r with k = rint(2 theta/pi),
+// r = theta - k pi/2 by the three-term split of pi/2 of Cody and Waite (three
+// doubles whose sum is pi/2 to 160 bits; each product is exact inside its
+// FMA), so |r| <= pi/4 up to rounding; then e^{i theta} = i^k e^{i r}.  The
+// absolute error stays at a few 1e-16 for |theta| < 2^30, far beyond any
+// phase a time step takes.
+__device__ inline double2 expi(double th) {
+    const double k = rint(th * 0.63661977236758134308);
+    double r = fma(-k, 1.5707963267948966, th);      // pi/2 rounded to a double
+    r = fma(-k, 6.123233995736766e-17, r);           // pi/2 minus that, rounded
+    r = fma(-k, -1.4973849048591698e-33, r);         // the remainder, rounded
+    const double2 e = expi_small(r);
+    const double k4 = k - 4.0 * floor(0.25 * k);     // k mod 4
+    // i^k (c + i s): k = 0: (c, s), 1: (-s, c), 2: (-c, -s), 3: (s, -c)
+    const bool odd = k4 == 1.0 || k4 == 3.0;
+    const double a = odd ? e.y : e.x, b = odd ? e.x : e.y;
+    return make_double2((k4 == 1.0 || k4 == 2.0) ? -a : a, k4 >= 2.0 ? -b : b);
+}
+
+// The Shin-Metiu coupling g(d) = erf(|d|/a)/|d| at z = |d|/a: below z = 6
+// from the piecewise polynomial table of erf(z)/z (read from LDS, where the
+// work-group keeps it; every lane takes its own piece, no branches), above it
+// 1/|d| by a reciprocal refined by two Newton steps, since erf(z) rounds to 1
+// there.  inv_a = 1/a.
+__device__ inline double erf_over_x_table(double d, double inv_a, const double *tab) {
+    const double ax = fabs(d);
+    const double z = ax * inv_a;
+    const int j = (int)fmin(z * 4.0, (double)(kErfPieces - 1));
+    const double s = z - (j + 0.5) * 0.25;
+    const double *cf = tab + j * kErfTerms;
+    double e = cf[kErfTerms - 1];
+#pragma unroll
+    for (int k = kErfTerms - 2; k >= 0; --k) e = fma(e, s, cf[k]);
+    double r = __builtin_amdgcn_rcp(ax);
+    r = fma(fma(-ax, r, 1.0), r, r);
+    r = fma(fma(-ax, r, 1.0), r, r);
+    return z < 6.0 ? e * inv_a : r;
+}
+
+// n = 2^LOG2N points; blockDim.x = max(64, n/8) threads: n/8 per CWF,
+// cpb = blockDim.x / (n/8) CWFs per work-group; work-group g takes the CWF
+// groups g, g + G, ... of the ngroups = Np / cpb (G = gridDim.x).  LDS: the
+// n/8 twiddles, the erf(z)/z table, then two padded buffers per CWF.
+template <int LOG2N>
+__global__ void __launch_bounds__(512) k_propagate(double2 *__restrict__ psi, int ngroups,
                                                    const double *__restrict__ vstat, double x_min, double h,
                                                    const double *__restrict__ cond, int species, ModelParams mp,
                                                    const double2 *__restrict__ kin,
@@ -166,46 +242,71 @@ __global__ void __launch_bounds__(512) k_propagate(double2 *__restrict__ psi, in
                                                    const int32_t *__restrict__ flags) {
     if (flags[kFlagHalt]) return;
     extern __shared__ double2 sh_all[];
-    const int q = n / kPts;
-    const int cpb = blockDim.x / q;
-    const int lc = threadIdx.x / q, t = threadIdx.x - lc * q;
-    const int cw = blockIdx.x * cpb + lc;
-    const int ld = n + n / 8;                // one padded buffer; two per CWF
-    double2 *sh = sh_all + lc * 2 * ld;
+    constexpr int n = 1 << LOG2N;
+    constexpr int q = n / kPts;
+    constexpr int cpb = q < 64 ? 64 / q : 1;
+    constexpr int ld = n + n / 8;            // one padded buffer; two per CWF
+    const int lc = threadIdx.x / q, t0 = threadIdx.x - lc * q;
+    double2 *stw = sh_all;
+    double *serf = reinterpret_cast<double *>(sh_all + q);
+    double2 *sh = sh_all + q + kErfTableSlots + lc * 2 * ld;
+    for (int j = threadIdx.x; j < q; j += blockDim.x) stw[j] = tw[j];
+    for (int j = threadIdx.x; j < kErfPieces * kErfTerms; j += blockDim.x) serf[j] = (&kErfOverZ[0][0])[j];
     int par = 0;
-    double2 *p = psi + (size_t)cw * n;
-    const double c = cond[cw];
-    // part of the conditioned potential that is constant on this CWF's grid
-    const double vconst = (species == 1) ? model_v2(mp, c) : model_v1(mp, c);
-
-    double2 ph[kPts], v[kPts];
-    // the CWF's loads first: they are in flight while the phases (which do not
-    // depend on them) are evaluated
+    __syncthreads();                         // tables in place
+    for (int g = blockIdx.x; g < ngroups; g += gridDim.x) {
+        // the thread index, opaque to the compiler within each iteration:
+        // otherwise the loads and addresses that do not change from one CWF
+        // to the next are hoisted out of the loop and held in registers
+        // across it, which spills
+        int t = t0;
+        asm volatile("" : "+v"(t));
+        const int cw = g * cpb + lc;
+        double2 *p = psi + (size_t)cw * n;
+        const double c = cond[cw];
+        double2 v[kPts];
 #pragma unroll
-    for (int m = 0; m < kPts; ++m) v[m] = p[t + m * q];
+        for (int m = 0; m < kPts; ++m) v[m] = p[t + m * q];
+        // part of the conditioned potential that is constant on this CWF's grid
+        const double vconst = (species == 1) ? model_v2(mp, c) : model_v1(mp, c);
+        double2 ph[kPts];
+        if (mp.kind == 1) {                  // Shin-Metiu: W_c = -g(r - R; R_f)
+            const double inv_a = 1.0 / mp.p[1];
 #pragma unroll
-    for (int m = 0; m < kPts; ++m) {
-        const int i = t + m * q;
-        const double x = x_min + i * h;
-        const double V = vstat[i] + vconst + ((species == 1) ? model_wc(mp, x, c) : model_wc(mp, c, x));
-        double s, co;
-        sincos(-0.5 * dt * V, &s, &co);
-        ph[m] = make_double2(co, s);
-    }
+            for (int m = 0; m < kPts; ++m) {
+                const double x = x_min + (t + m * q) * h;
+                const double V = vstat[t + m * q] + vconst - erf_over_x_table(x - c, inv_a, serf);
+                ph[m] = expi(-0.5 * dt * V);
+                // two points at a time: all eight in flight at once need more
+                // registers than the wave has
+                if (m % 2 == 1) __builtin_amdgcn_sched_barrier(0);
+            }
+        } else {
 #pragma unroll
-    for (int m = 0; m < kPts; ++m) v[m] = cmul(ph[m], v[m]);
-    fft8(v, sh, ld, par, n, log2n, t, tw);
+            for (int m = 0; m < kPts; ++m) {
+                const double x = x_min + (t + m * q) * h;
+                const double V = vstat[t + m * q] + vconst + ((species == 1) ? model_wc(mp, x, c) : model_wc(mp, c, x));
+                ph[m] = expi(-0.5 * dt * V);
+            }
+        }
 #pragma unroll
-    for (int m = 0; m < kPts; ++m) v[m] = cconj(cmul(kin[t + m * q], v[m]));
-    fft8(v, sh, ld, par, n, log2n, t, tw);
-    const double inv_n = 1.0 / n;
+        for (int m = 0; m < kPts; ++m) v[m] = cmul(ph[m], v[m]);
+        double2 kv[kPts];
 #pragma unroll
-    for (int m = 0; m < kPts; ++m) {
-        const int i = t + m * q;
-        const double2 o = cmul(ph[m], cscale(cconj(v[m]), inv_n));
-        p[i] = o;
-        // FP32 copy for the mixed form's FP32 contraction
-        if (psi_f32) psi_f32[(size_t)cw * n + i] = make_float2((float)o.x, (float)o.y);
+        for (int m = 0; m < kPts; ++m) kv[m] = kin[t + m * q];
+        fft8<LOG2N>(v, sh, ld, par, t, stw);
+#pragma unroll
+        for (int m = 0; m < kPts; ++m) v[m] = cconj(cmul(kv[m], v[m]));
+        fft8<LOG2N>(v, sh, ld, par, t, stw);
+        const double inv_n = 1.0 / n;
+#pragma unroll
+        for (int m = 0; m < kPts; ++m) {
+            const int i = t + m * q;
+            const double2 o = cmul(ph[m], cscale(cconj(v[m]), inv_n));
+            p[i] = o;
+            // FP32 copy for the mixed form's FP32 contraction
+            if (psi_f32) psi_f32[(size_t)cw * n + i] = make_float2((float)o.x, (float)o.y);
+        }
     }
 }
 
@@ -217,20 +318,61 @@ int ilog2(int n) {
 
 }  // namespace
 
+namespace {
+int threads_for(int n) {
+    const int q = n / kPts;
+    return q < 64 ? 64 : q;                  // 64 / q CWFs per work-group below n = 512
+}
+size_t lds_for(int n) {
+    const int q = n / kPts;
+    const int cpb = threads_for(n) / q;
+    return sizeof(double2) * ((size_t)q + kErfTableSlots + (size_t)2 * (n + n / 8) * cpb);
+}
+}  // namespace
+
+namespace {
+// The instantiation for n = 2^l, 32 <= n <= 4096.
+using PropKernel = void (*)(double2 *, int, const double *, double, double, const double *, int, ModelParams,
+                            const double2 *, const double2 *, double, float2 *, const int32_t *);
+PropKernel kernel_for(int n) {
+    switch (ilog2(n)) {
+    case 5: return k_propagate<5>;
+    case 6: return k_propagate<6>;
+    case 7: return k_propagate<7>;
+    case 8: return k_propagate<8>;
+    case 9: return k_propagate<9>;
+    case 10: return k_propagate<10>;
+    case 11: return k_propagate<11>;
+    case 12: return k_propagate<12>;
+    default: return nullptr;
+    }
+}
+}  // namespace
+
+int propagate_grid(int n, int N, int ncu) {
+    const int T = threads_for(n);
+    const int ngroups = padded(N) / (T / (n / kPts));
+    int per_cu = 0;
+    const PropKernel k = kernel_for(n);
+    if (!k || hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, T, lds_for(n)) != hipSuccess || per_cu < 1)
+        per_cu = 1;
+    const long long full = (long long)per_cu * (ncu > 0 ? ncu : 1);
+    return (int)(ngroups < full ? ngroups : full);
+}
+
 void launch_propagate(const Dims &d, const Bufs &b, int species, hipStream_t s) {
     const int n = species == 1 ? d.nr : d.nR;
-    const int q = n / kPts;
-    const int T = q < 64 ? 64 : q;           // 64 / q CWFs per work-group below n = 512
-    const int cpb = T / q;
-    const int grid = padded(d.N) / cpb;      // padded rows hold zero CWFs
-    const size_t lds = sizeof(double2) * (size_t)2 * (n + n / 8) * cpb;
+    const int T = threads_for(n);
+    const int ngroups = padded(d.N) / (T / (n / kPts));   // padded rows hold zero CWFs
+    const int grid = d.prop_grid[species - 1];
+    const size_t lds = lds_for(n);
+    const PropKernel k = kernel_for(n);      // n is validated at creation (a power of two in [32, 4096])
     if (species == 1) {
-        hipLaunchKernelGGL(k_propagate, dim3(grid), dim3(T), lds, s, b.psi1, n, ilog2(n), b.vstat_r, d.r_min,
-                           d.hr, b.R, 1, d.mp, b.kin_r, b.tw_r, d.dt, d.prec == 1 ? b.psi1_f32 : nullptr,
-                           b.flags);
+        hipLaunchKernelGGL(k, dim3(grid), dim3(T), lds, s, b.psi1, ngroups, b.vstat_r, d.r_min, d.hr, b.R, 1, d.mp,
+                           b.kin_r, b.tw_r, d.dt, d.prec == 1 ? b.psi1_f32 : nullptr, b.flags);
     } else {
-        hipLaunchKernelGGL(k_propagate, dim3(grid), dim3(T), lds, s, b.psi2, n, ilog2(n), b.vstat_R, d.R_min,
-                           d.hR, b.r, 2, d.mp, b.kin_R, b.tw_R, d.dt, nullptr, b.flags);
+        hipLaunchKernelGGL(k, dim3(grid), dim3(T), lds, s, b.psi2, ngroups, b.vstat_R, d.R_min, d.hR, b.r, 2, d.mp,
+                           b.kin_R, b.tw_R, d.dt, nullptr, b.flags);
     }
 }
 

@@ -96,3 +96,26 @@ def test_ten_steps_observables(case):
     assert np.max(np.abs(o["r"] - ref["r"])) < 1e-10 * max(1.0, np.max(np.abs(ref["r"])))
     assert np.max(np.abs(o["R"] - ref["R"])) < 1e-10 * max(1.0, np.max(np.abs(ref["R"])))
     sim.close()
+
+
+@pytest.mark.parametrize("dt", [10.0, 40.0])
+def test_one_step_phases_beyond_a_quarter_turn(dt):
+    """Long time steps make the potential phase V dt/2 run over several
+    quarter turns (up to 6.7 rad at dt = 40), which the propagation
+    reduces by multiples of pi/2 before its series: the CWFs after one step
+    still match the oracle's e^{-i V dt/2} to 1e-12."""
+    wl = inputs.gaussian_basis(40, n_r=128, n_R=64, dt=dt, seed=11)
+    _print_case(f"dt={dt}", wl)
+    setup = setup_for(wl)
+    st0 = init_for(setup, wl)
+    sim = icwf.Simulation.from_workload(wl, C0=wl.extra["C0"])
+    sim.step(1)
+    sim.sync()
+    got = sim.state()
+    ref = oicwf.step(setup, st0)
+    # the electronic phases at the trajectories' nuclear positions pass pi/4
+    W = setup.model.W(setup.r[:, None], st0.R_traj[None, :])
+    assert 0.5 * dt * np.max(np.abs(W)) > 1.0
+    assert np.max(np.abs(got["psi1"] - ref.psi1)) < 1e-12
+    assert np.max(np.abs(got["psi2"] - ref.psi2)) < 1e-12
+    sim.close()

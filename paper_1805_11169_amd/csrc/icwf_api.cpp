@@ -57,8 +57,8 @@ Bufs carve(const icwf_config &c, char *base, size_t *total) {
     b.Cstage = L.take<double2>(Np);
     b.y = L.take<double2>(Np);
     b.rhs = L.take<double2>(Np);
-    b.vstat_r = L.take<double>(nr);
-    b.vstat_R = L.take<double>(nR);
+    b.vphase_r = L.take<double2>(nr);
+    b.vphase_R = L.take<double2>(nR);
     b.kin_r = L.take<double2>(nr);
     b.kin_R = L.take<double2>(nR);
     b.tw_r = L.take<double2>(nr);
@@ -455,6 +455,10 @@ icwf_status icwf_create(const icwf_config *cfg, const double *r0, const double *
     };
     fill_k(kin_r, tw_r, nr, d.hr, d.m_r);
     fill_k(kin_R, tw_R, nR, d.hR, d.m_R);
+    // half-step phases of the one-coordinate parts V_1(r_i), V_2(R_j)
+    std::vector<double2> vph_r(nr), vph_R(nR);
+    for (int i = 0; i < nr; ++i) vph_r[i] = make_double2(std::cos(-0.5 * d.dt * vr[i]), std::sin(-0.5 * d.dt * vr[i]));
+    for (int j = 0; j < nR; ++j) vph_R[j] = make_double2(std::cos(-0.5 * d.dt * vR[j]), std::sin(-0.5 * d.dt * vR[j]));
 
     // ---- padded state
     std::vector<double> rp(Np, cfg->r_min), Rp(Np, cfg->R_min);
@@ -470,8 +474,8 @@ icwf_status icwf_create(const icwf_config *cfg, const double *r0, const double *
     CREATE_HIP(hipMemcpyAsync(b.R, Rp.data(), sizeof(double) * Np, hipMemcpyHostToDevice, st));
     CREATE_HIP(hipMemcpyAsync(b.r_new, rp.data(), sizeof(double) * Np, hipMemcpyHostToDevice, st));
     CREATE_HIP(hipMemcpyAsync(b.R_new, Rp.data(), sizeof(double) * Np, hipMemcpyHostToDevice, st));
-    CREATE_HIP(hipMemcpyAsync(b.vstat_r, vr.data(), sizeof(double) * nr, hipMemcpyHostToDevice, st));
-    CREATE_HIP(hipMemcpyAsync(b.vstat_R, vR.data(), sizeof(double) * nR, hipMemcpyHostToDevice, st));
+    CREATE_HIP(hipMemcpyAsync(b.vphase_r, vph_r.data(), sizeof(double2) * nr, hipMemcpyHostToDevice, st));
+    CREATE_HIP(hipMemcpyAsync(b.vphase_R, vph_R.data(), sizeof(double2) * nR, hipMemcpyHostToDevice, st));
     CREATE_HIP(hipMemcpyAsync(b.kin_r, kin_r.data(), sizeof(double2) * nr, hipMemcpyHostToDevice, st));
     CREATE_HIP(hipMemcpyAsync(b.kin_R, kin_R.data(), sizeof(double2) * nR, hipMemcpyHostToDevice, st));
     CREATE_HIP(hipMemcpyAsync(b.tw_r, tw_r.data(), sizeof(double2) * nr, hipMemcpyHostToDevice, st));

@@ -16,10 +16,14 @@
 // The passes between them go through two LDS buffers (radix 8, with one
 // radix 2 or 4 pass first when log2 n is not a multiple of 3; twiddles from an
 // LDS table).  The CWF is read once from HBM and written once, both
-// coalesced.  The potential phase is evaluated once per point (the coupling
-// from a piecewise-polynomial erf table, e^{i theta} by a reduced Taylor
-// series) and kept in registers for both half steps.  The inverse FFT is
-// the forward one applied to the conjugate.
+// coalesced.  The potential phase is evaluated once per point and kept in
+// registers for both half steps, as the product of a table of the
+// one-coordinate part's phase, the constant part's phase, and the coupling's
+// (from a piecewise-polynomial erf table, e^{i theta} by a Taylor series,
+// reduced when needed).  The inverse FFT is the forward one applied to the
+// conjugate.
+#include <cmath>
+
 #include "icwf_plan.hpp"
 
 #include "erf_table.inc"
@@ -208,6 +212,23 @@ __device__ inline double2 expi(double th) {
     return make_double2((k4 == 1.0 || k4 == 2.0) ? -a : a, k4 >= 2.0 ? -b : b);
 }
 
+// e^{i theta} for |theta| <= 0.05: the Taylor series of sin and cos to
+// degrees 9 and 8, whose first dropped terms, below 0.05^10/11! = 2.5e-21
+// (relative to theta) and 0.05^10/10! = 2.7e-20, are far under an ulp.
+constexpr double kTinyPhase = 0.05;
+__device__ inline double2 expi_tiny(double th) {
+    const double u = th * th;
+    double s = 1.0 / 362880.0;                    // +1/9!
+    s = fma(s, u, -1.0 / 5040.0);                 // -1/7!
+    s = fma(s, u, 1.0 / 120.0);                   // +1/5!
+    s = fma(s, u, -1.0 / 6.0);                    // -1/3!
+    double c = 1.0 / 40320.0;                     // +1/8!
+    c = fma(c, u, -1.0 / 720.0);                  // -1/6!
+    c = fma(c, u, 1.0 / 24.0);                    // +1/4!
+    c = fma(c, u, -0.5);                          // -1/2!
+    return make_double2(fma(u, c, 1.0), fma(th * u, s, th));
+}
+
 // The Shin-Metiu coupling g(d) = erf(|d|/a)/|d| at z = |d|/a: below z = 6
 // from the piecewise polynomial table of erf(z)/z (read from LDS, where the
 // work-group keeps it; every lane takes its own piece, no branches), above it
@@ -234,10 +255,10 @@ __device__ inline double erf_over_x_table(double d, double inv_a, const double *
 // n/8 twiddles, the erf(z)/z table, then two padded buffers per CWF.
 template <int LOG2N>
 __global__ void __launch_bounds__(512) k_propagate(double2 *__restrict__ psi, int ngroups,
-                                                   const double *__restrict__ vstat, double x_min, double h,
+                                                   const double2 *__restrict__ vphase, double x_min, double h,
                                                    const double *__restrict__ cond, int species, ModelParams mp,
                                                    const double2 *__restrict__ kin,
-                                                   const double2 *__restrict__ tw, double dt,
+                                                   const double2 *__restrict__ tw, double dt, int tiny,
                                                    float2 *__restrict__ psi_f32,
                                                    const int32_t *__restrict__ flags) {
     if (flags[kFlagHalt]) return;
@@ -267,26 +288,40 @@ __global__ void __launch_bounds__(512) k_propagate(double2 *__restrict__ psi, in
         double2 v[kPts];
 #pragma unroll
         for (int m = 0; m < kPts; ++m) v[m] = p[t + m * q];
-        // part of the conditioned potential that is constant on this CWF's grid
+        // e^{-i V dt/2} = e^{-i V_s(x) dt/2} (table) x e^{-i V_c dt/2} (the part
+        // of the conditioned potential constant on this CWF's grid) x
+        // e^{-i W_c(x) dt/2} (the coupling, evaluated per point)
         const double vconst = (species == 1) ? model_v2(mp, c) : model_v1(mp, c);
+        const double2 pc = expi(-0.5 * dt * vconst);
         double2 ph[kPts];
-        if (mp.kind == 1) {                  // Shin-Metiu: W_c = -g(r - R; R_f)
+        if (mp.kind == 1) {                  // Shin-Metiu: W_c = -g(r - R; R_f), 0 <= g <= 2/(sqrt(pi) R_f)
             const double inv_a = 1.0 / mp.p[1];
+            if (tiny) {                      // dt/(sqrt(pi) R_f) <= kTinyPhase
 #pragma unroll
-            for (int m = 0; m < kPts; ++m) {
-                const double x = x_min + (t + m * q) * h;
-                const double V = vstat[t + m * q] + vconst - erf_over_x_table(x - c, inv_a, serf);
-                ph[m] = expi(-0.5 * dt * V);
-                // two points at a time: all eight in flight at once need more
-                // registers than the wave has
-                if (m % 2 == 1) __builtin_amdgcn_sched_barrier(0);
+                for (int m = 0; m < kPts; ++m) {
+                    const double x = x_min + (t + m * q) * h;
+                    const double2 e = expi_tiny(0.5 * dt * erf_over_x_table(x - c, inv_a, serf));
+                    ph[m] = cmul(cmul(vphase[t + m * q], pc), e);
+                    // two points at a time: all eight in flight at once need
+                    // more registers than the wave has
+                    if (m % 2 == 1) __builtin_amdgcn_sched_barrier(0);
+                }
+            } else {
+#pragma unroll
+                for (int m = 0; m < kPts; ++m) {
+                    const double x = x_min + (t + m * q) * h;
+                    const double2 e = expi(0.5 * dt * erf_over_x_table(x - c, inv_a, serf));
+                    ph[m] = cmul(cmul(vphase[t + m * q], pc), e);
+                    if (m % 2 == 1) __builtin_amdgcn_sched_barrier(0);
+                }
             }
         } else {
 #pragma unroll
             for (int m = 0; m < kPts; ++m) {
                 const double x = x_min + (t + m * q) * h;
-                const double V = vstat[t + m * q] + vconst + ((species == 1) ? model_wc(mp, x, c) : model_wc(mp, c, x));
-                ph[m] = expi(-0.5 * dt * V);
+                const double wcv = (species == 1) ? model_wc(mp, x, c) : model_wc(mp, c, x);
+                ph[m] = cmul(cmul(vphase[t + m * q], pc), expi(-0.5 * dt * wcv));
+                if (m % 2 == 1) __builtin_amdgcn_sched_barrier(0);
             }
         }
 #pragma unroll
@@ -332,8 +367,8 @@ size_t lds_for(int n) {
 
 namespace {
 // The instantiation for n = 2^l, 32 <= n <= 4096.
-using PropKernel = void (*)(double2 *, int, const double *, double, double, const double *, int, ModelParams,
-                            const double2 *, const double2 *, double, float2 *, const int32_t *);
+using PropKernel = void (*)(double2 *, int, const double2 *, double, double, const double *, int, ModelParams,
+                            const double2 *, const double2 *, double, int, float2 *, const int32_t *);
 PropKernel kernel_for(int n) {
     switch (ilog2(n)) {
     case 5: return k_propagate<5>;
@@ -367,12 +402,14 @@ void launch_propagate(const Dims &d, const Bufs &b, int species, hipStream_t s) 
     const int grid = d.prop_grid[species - 1];
     const size_t lds = lds_for(n);
     const PropKernel k = kernel_for(n);      // n is validated at creation (a power of two in [32, 4096])
+    // the Shin-Metiu coupling phase stays within the short series' range
+    const int tiny = d.mp.kind == 1 && 0.5 * std::fabs(d.dt) * 2.0 / (std::sqrt(M_PI) * d.mp.p[1]) <= kTinyPhase;
     if (species == 1) {
-        hipLaunchKernelGGL(k, dim3(grid), dim3(T), lds, s, b.psi1, ngroups, b.vstat_r, d.r_min, d.hr, b.R, 1, d.mp,
-                           b.kin_r, b.tw_r, d.dt, d.prec == 1 ? b.psi1_f32 : nullptr, b.flags);
+        hipLaunchKernelGGL(k, dim3(grid), dim3(T), lds, s, b.psi1, ngroups, b.vphase_r, d.r_min, d.hr, b.R, 1, d.mp,
+                           b.kin_r, b.tw_r, d.dt, tiny, d.prec == 1 ? b.psi1_f32 : nullptr, b.flags);
     } else {
-        hipLaunchKernelGGL(k, dim3(grid), dim3(T), lds, s, b.psi2, ngroups, b.vstat_R, d.R_min, d.hR, b.r, 2, d.mp,
-                           b.kin_R, b.tw_R, d.dt, nullptr, b.flags);
+        hipLaunchKernelGGL(k, dim3(grid), dim3(T), lds, s, b.psi2, ngroups, b.vphase_R, d.R_min, d.hR, b.r, 2, d.mp,
+                           b.kin_R, b.tw_R, d.dt, tiny, nullptr, b.flags);
     }
 }
 

@@ -169,6 +169,121 @@ __device__ inline void fft8(double2 (&v)[kPts], double2 *sh, int ld, int &par, i
     }
 }
 
+// ---- n = 4096: four-step transform, two barriers per CWF ---------------------
+//
+// 4096 = 64 x 64 with i = i1 + 64 i2 and k = k2 + 64 k1: a 64-point DFT over
+// i2 for each i1, the twiddle w4096^(i1 k2), a 64-point DFT over i1 for each
+// k2.  Each 64-point DFT is 8 x 8: an in-register radix-8 DFT, a w64 twiddle,
+// an 8 x 8 exchange among 8 lanes of one wave and a second radix-8 DFT.  With
+// wave w, lane l = lo + 8 hi (lo = l & 7, hi = l >> 3) and register m, the
+// thread holds x[lo + 8 w + 64 hi + 512 m] on entry (i1 = lo + 8 w) and returns
+// X[hi + 8 w + 64 lo + 512 m].  Only the exchange between the two halves
+// crosses waves (one barrier); the 8-lane exchanges go through the wave's own
+// 512-slot slice of an LDS buffer and need no barrier, LDS operations of one
+// wave being executed in order.  Slot maps are XOR-swizzled so that every 16
+// consecutive lanes touch 16 different 16-byte bank groups on both the write
+// and the read side.
+//
+// The same stages in reverse order (the DFT matrix and each stage matrix being
+// symmetric, up to the inverse permutations) compute the DFT from the output
+// layout back to the input layout; the inverse transform is that sequence
+// applied to the conjugate.  Buffer use: the forward exchange writes B0 and
+// the reverse one B1; the 8-lane exchanges use the wave's slice of the buffer
+// whose last cross-wave exchange it has already read.  Every cross-wave write
+// into a buffer is separated by a barrier from the last use of that buffer by
+// any wave.
+
+constexpr int kFourStepLog2 = 12;
+
+__device__ inline void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// element (lo, a, b) of the first 8 x 8 exchange (lanes (lo, a) -> (lo, b))
+__device__ inline int slot_a(int lo, int a, int b) { return 64 * a + 8 * (b ^ (a & 1)) + lo; }
+// element (b, p, e) of the second one (lanes (p, b) -> (e, b))
+__device__ inline int slot_c(int b, int p, int e) { return 64 * b + 8 * (e ^ (b & 1)) + (p ^ e); }
+
+// v[r] *= w^r, r = 1..7 (powers by products, a few ulp)
+__device__ inline void twiddle_powers(double2 (&v)[kPts], double2 w) {
+    double2 wr = w;
+#pragma unroll
+    for (int r = 1; r < kPts; ++r) {
+        v[r] = cmul(v[r], wr);
+        if (r + 1 < kPts) wr = cmul(wr, w);
+    }
+}
+
+// v[c] *= w4096^(i1 (hi + 8 c)), c = 0..7
+__device__ inline void twiddle_middle(double2 (&v)[kPts], int i1, int hi, const double2 *tw) {
+    double2 t = tw[i1 * hi];
+    const double2 r = tw[8 * i1];
+#pragma unroll
+    for (int c = 0; c < kPts; ++c) {
+        v[c] = cmul(v[c], t);
+        if (c + 1 < kPts) t = cmul(t, r);
+    }
+}
+
+// all eight values to dest wave j = 0..7, then the eight from source waves
+__device__ inline void cross_wave(double2 (&v)[kPts], double2 *B, int w, int l) {
+#pragma unroll
+    for (int j = 0; j < kPts; ++j) B[j * 512 + w * 64 + l] = v[j];
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kPts; ++j) v[j] = B[w * 512 + j * 64 + l];
+}
+
+// forward, input layout -> output layout
+__device__ inline void fft4096_fwd(double2 (&v)[kPts], double2 *B0, double2 *B1, int w, int l, const double2 *tw) {
+    const int lo = l & 7, hi = l >> 3;
+    double2 *R0 = B0 + w * 512, *R1 = B1 + w * 512;
+    dft8(v);                                              // over i2's high part
+    twiddle_powers(v, tw[64 * hi]);                       // w64^(a b), a = hi
+#pragma unroll
+    for (int b = 0; b < kPts; ++b) R1[slot_a(lo, hi, b)] = v[b];
+    wave_sync();
+#pragma unroll
+    for (int a = 0; a < kPts; ++a) v[a] = R1[slot_a(lo, a, hi)];
+    dft8(v);                                              // over i2's low part
+    twiddle_middle(v, lo + 8 * w, hi, tw);
+    cross_wave(v, B0, w, l);
+    dft8(v);                                              // over i1's high part
+    twiddle_powers(v, tw[64 * lo]);                       // w64^(p e), p = lo
+#pragma unroll
+    for (int e = 0; e < kPts; ++e) R0[slot_c(hi, lo, e)] = v[e];
+    wave_sync();
+#pragma unroll
+    for (int p = 0; p < kPts; ++p) v[p] = R0[slot_c(hi, p, lo)];
+    dft8(v);                                              // over i1's low part
+}
+
+// the same stages in reverse: output layout -> input layout
+__device__ inline void fft4096_rev(double2 (&v)[kPts], double2 *B0, double2 *B1, int w, int l, const double2 *tw) {
+    const int lo = l & 7, hi = l >> 3;
+    double2 *R0 = B0 + w * 512, *R1 = B1 + w * 512;
+    dft8(v);
+#pragma unroll
+    for (int p = 0; p < kPts; ++p) R0[slot_c(hi, p, lo)] = v[p];
+    wave_sync();
+#pragma unroll
+    for (int e = 0; e < kPts; ++e) v[e] = R0[slot_c(hi, lo, e)];
+    twiddle_powers(v, tw[64 * lo]);
+    dft8(v);
+    cross_wave(v, B1, w, l);
+    twiddle_middle(v, lo + 8 * w, hi, tw);
+    dft8(v);
+#pragma unroll
+    for (int a = 0; a < kPts; ++a) R1[slot_a(lo, a, hi)] = v[a];
+    wave_sync();
+#pragma unroll
+    for (int b = 0; b < kPts; ++b) v[b] = R1[slot_a(lo, hi, b)];
+    twiddle_powers(v, tw[64 * hi]);
+    dft8(v);
+}
+
 // e^{i theta} for |theta| <= pi/4 by the Taylor series of sin and cos in
 // u = theta^2, to degrees 15 and 16: the first dropped terms are below
 // (pi/4)^17/17! = 5e-17 and (pi/4)^18/18! = 2e-18, under half an ulp of
@@ -266,7 +381,8 @@ __global__ void __launch_bounds__(512) k_propagate(double2 *__restrict__ psi, in
     constexpr int n = 1 << LOG2N;
     constexpr int q = n / kPts;
     constexpr int cpb = q < 64 ? 64 / q : 1;
-    constexpr int ld = n + n / 8;            // one padded buffer; two per CWF
+    constexpr bool four_step = LOG2N == kFourStepLog2;
+    constexpr int ld = four_step ? n : n + n / 8;   // one (padded) buffer; two per CWF
     const int lc = threadIdx.x / q, t0 = threadIdx.x - lc * q;
     double2 *stw = sh_all;
     double *serf = reinterpret_cast<double *>(sh_all + q);
@@ -274,20 +390,31 @@ __global__ void __launch_bounds__(512) k_propagate(double2 *__restrict__ psi, in
     for (int j = threadIdx.x; j < q; j += blockDim.x) stw[j] = tw[j];
     for (int j = threadIdx.x; j < kErfPieces * kErfTerms; j += blockDim.x) serf[j] = (&kErfOverZ[0][0])[j];
     int par = 0;
+    // this thread's points: x index xi + m q, FFT-order k index ki + m q
+    int xi0 = t0, ki0 = t0;
+    if constexpr (four_step) {
+        const int w = t0 >> 6, lo = t0 & 7, hi = (t0 >> 3) & 7;
+        xi0 = lo + 8 * w + 64 * hi;
+        ki0 = hi + 8 * w + 64 * lo;
+    }
+    // the conditioning coordinate is read one CWF ahead: the phases of a CWF
+    // cannot start before it arrives
+    double c_next = blockIdx.x < (unsigned)ngroups ? cond[blockIdx.x * cpb + lc] : 0.0;
     __syncthreads();                         // tables in place
     for (int g = blockIdx.x; g < ngroups; g += gridDim.x) {
         // the thread index, opaque to the compiler within each iteration:
         // otherwise the loads and addresses that do not change from one CWF
         // to the next are hoisted out of the loop and held in registers
         // across it, which spills
-        int t = t0;
-        asm volatile("" : "+v"(t));
+        int t = t0, xi = xi0, ki = ki0;
+        asm volatile("" : "+v"(t), "+v"(xi), "+v"(ki));
         const int cw = g * cpb + lc;
         double2 *p = psi + (size_t)cw * n;
-        const double c = cond[cw];
+        const double c = c_next;
+        if (g + (int)gridDim.x < ngroups) c_next = cond[(g + gridDim.x) * cpb + lc];
         double2 v[kPts];
 #pragma unroll
-        for (int m = 0; m < kPts; ++m) v[m] = p[t + m * q];
+        for (int m = 0; m < kPts; ++m) v[m] = p[xi + m * q];
         // e^{-i V dt/2} = e^{-i V_s(x) dt/2} (table) x e^{-i V_c dt/2} (the part
         // of the conditioned potential constant on this CWF's grid) x
         // e^{-i W_c(x) dt/2} (the coupling, evaluated per point)
@@ -299,9 +426,9 @@ __global__ void __launch_bounds__(512) k_propagate(double2 *__restrict__ psi, in
             if (tiny) {                      // dt/(sqrt(pi) R_f) <= kTinyPhase
 #pragma unroll
                 for (int m = 0; m < kPts; ++m) {
-                    const double x = x_min + (t + m * q) * h;
+                    const double x = x_min + (xi + m * q) * h;
                     const double2 e = expi_tiny(0.5 * dt * erf_over_x_table(x - c, inv_a, serf));
-                    ph[m] = cmul(cmul(vphase[t + m * q], pc), e);
+                    ph[m] = cmul(cmul(vphase[xi + m * q], pc), e);
                     // two points at a time: all eight in flight at once need
                     // more registers than the wave has
                     if (m % 2 == 1) __builtin_amdgcn_sched_barrier(0);
@@ -309,18 +436,18 @@ __global__ void __launch_bounds__(512) k_propagate(double2 *__restrict__ psi, in
             } else {
 #pragma unroll
                 for (int m = 0; m < kPts; ++m) {
-                    const double x = x_min + (t + m * q) * h;
+                    const double x = x_min + (xi + m * q) * h;
                     const double2 e = expi(0.5 * dt * erf_over_x_table(x - c, inv_a, serf));
-                    ph[m] = cmul(cmul(vphase[t + m * q], pc), e);
+                    ph[m] = cmul(cmul(vphase[xi + m * q], pc), e);
                     if (m % 2 == 1) __builtin_amdgcn_sched_barrier(0);
                 }
             }
         } else {
 #pragma unroll
             for (int m = 0; m < kPts; ++m) {
-                const double x = x_min + (t + m * q) * h;
+                const double x = x_min + (xi + m * q) * h;
                 const double wcv = (species == 1) ? model_wc(mp, x, c) : model_wc(mp, c, x);
-                ph[m] = cmul(cmul(vphase[t + m * q], pc), expi(-0.5 * dt * wcv));
+                ph[m] = cmul(cmul(vphase[xi + m * q], pc), expi(-0.5 * dt * wcv));
                 if (m % 2 == 1) __builtin_amdgcn_sched_barrier(0);
             }
         }
@@ -328,15 +455,17 @@ __global__ void __launch_bounds__(512) k_propagate(double2 *__restrict__ psi, in
         for (int m = 0; m < kPts; ++m) v[m] = cmul(ph[m], v[m]);
         double2 kv[kPts];
 #pragma unroll
-        for (int m = 0; m < kPts; ++m) kv[m] = kin[t + m * q];
-        fft8<LOG2N>(v, sh, ld, par, t, stw);
+        for (int m = 0; m < kPts; ++m) kv[m] = kin[ki + m * q];
+        if constexpr (four_step) fft4096_fwd(v, sh, sh + n, t >> 6, t & 63, stw);
+        else fft8<LOG2N>(v, sh, ld, par, t, stw);
 #pragma unroll
         for (int m = 0; m < kPts; ++m) v[m] = cconj(cmul(kv[m], v[m]));
-        fft8<LOG2N>(v, sh, ld, par, t, stw);
+        if constexpr (four_step) fft4096_rev(v, sh, sh + n, t >> 6, t & 63, stw);
+        else fft8<LOG2N>(v, sh, ld, par, t, stw);
         const double inv_n = 1.0 / n;
 #pragma unroll
         for (int m = 0; m < kPts; ++m) {
-            const int i = t + m * q;
+            const int i = xi + m * q;
             const double2 o = cmul(ph[m], cscale(cconj(v[m]), inv_n));
             p[i] = o;
             // FP32 copy for the mixed form's FP32 contraction
@@ -361,7 +490,8 @@ int threads_for(int n) {
 size_t lds_for(int n) {
     const int q = n / kPts;
     const int cpb = threads_for(n) / q;
-    return sizeof(double2) * ((size_t)q + kErfTableSlots + (size_t)2 * (n + n / 8) * cpb);
+    const size_t ld = ilog2(n) == kFourStepLog2 ? n : n + n / 8;
+    return sizeof(double2) * ((size_t)q + kErfTableSlots + 2 * ld * cpb);
 }
 }  // namespace
 

@@ -128,3 +128,25 @@ def test_cavity_2048_sampled(rng):
     assert np.max(np.abs(got["psi1"][idx] - p1)) < 1e-12
     assert np.max(np.abs(got["psi2"][idx] - p2)) < 1e-12
     assert omat is not None
+
+
+@pytest.mark.parametrize("model", [inputs.MODEL_SHIN_METIU, inputs.MODEL_CAVITY])
+def test_one_step_on_the_4096_point_grid(model):
+    """The 4096-point electronic grid takes the four-step transform (64 x 64,
+    one cross-wave exchange per transform): all CWFs after one step against the
+    oracle's split-operator step, both models (N = 70: two tiles, ragged)."""
+    if model == inputs.MODEL_SHIN_METIU:
+        wl = inputs.gaussian_basis(70, n_r=4096, n_R=512, r_box=(-75.0, 75.0), R_box=(-9.0, 9.0), dt=0.1, seed=13)
+    else:
+        wl = inputs.gaussian_basis(70, n_r=4096, n_R=512, model=model, r_box=(-50.0, 50.0), R_box=(-20.0, 20.0),
+                                   dt=0.1, seed=14)
+    print(f"[case] {wl.name} one step", flush=True)
+    setup = setup_for(wl)
+    sim = icwf.Simulation.from_workload(wl, C0=wl.extra["C0"])
+    sim.step(1)
+    got = sim.state()
+    sim.close()
+    p1, p2 = oprop.propagate_cwfs(wl.psi1, wl.psi2, setup.model, setup.r, setup.R, setup.hr, setup.hR,
+                                  setup.m_r, setup.m_R, wl.r0, wl.R0, setup.dt)
+    assert np.max(np.abs(got["psi1"] - p1)) < 1e-12
+    assert np.max(np.abs(got["psi2"] - p2)) < 1e-12

@@ -144,6 +144,12 @@ def main():
         kt[name] = (n, ms)
     sim.set_timing(False)
     obs = sim.observables()
+    # observables on demand (norm, both densities): launches, copy-out and sync
+    torch.cuda.synchronize()
+    t_obs = time.perf_counter()
+    for _ in range(5):
+        sim.observables(check=False)
+    obs_ms = (time.perf_counter() - t_obs) / 5 * 1e3
     sim.close()
     del stream
 
@@ -180,6 +186,7 @@ def main():
         "propagation": {"achieved_gbs": prop_gbs, "peak_gbs": HBM_PEAK_GBS, "frac": prop_gbs / HBM_PEAK_GBS,
                         "avg_launch_ms": ms_pr / n_pr},
         "kernel_ms_per_step": {k: (ms / n if n else None) for k, (n, ms) in kt.items()},
+        "observables_ms": obs_ms,
         "final_norm": obs["norm"],
     }
     if not args.no_serving:

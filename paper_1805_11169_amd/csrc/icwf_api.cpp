@@ -92,7 +92,7 @@ Bufs carve(const icwf_config &c, char *base, size_t *total) {
     b.xsol = L.take<double2>(Np);
     b.solve_sync = L.take<int32_t>(130);
     b.bo = L.take<double>(std::max<size_t>(1, nR * nbo * nr));
-    b.obs_u = L.take<double2>(Np * std::max(nr, nR));
+    b.obs_psi = L.take<double2>(nr * nR);
     b.obs_chi = L.take<double2>(std::max<size_t>(1, nbo * nR));
     b.obs_out = L.take<double>(obs_len(c.n_r, c.n_R, c.n_bo));
     *total = (L.off + 255) & ~size_t(255);
@@ -546,7 +546,7 @@ icwf_status icwf_observables(icwf_sim *s, icwf_obs *o) {
     if (!s || !o) return fail(s, ICWF_EINVAL, "NULL argument");
     icwf_status st = icwf_sync(s);
     const Dims &d = s->d;
-    icwf::launch_observables(d, s->b, s->parity, s->stream);
+    icwf::launch_observables(d, s->b, s->stream);
     HIP_OK(hipGetLastError(), s);
     std::vector<double> buf(obs_len(d.nr, d.nR, d.n_bo));
     HIP_OK(hipMemcpyAsync(buf.data(), s->b.obs_out, sizeof(double) * buf.size(), hipMemcpyDeviceToHost, s->stream), s);

@@ -60,7 +60,7 @@ struct Bufs {
     double2 *xsol;                        // [Np] back-substitution result of an RK stage
     int32_t *solve_sync;                  // [130] block flags and tickets of the stage solves
     double *bo;                           // [nR][n_bo][nr] BO states
-    double2 *obs_u, *obs_v;               // observables scratch [N][max(nr,nR)]
+    double2 *obs_psi;                     // [nr][nR] Psi on the grid (observables)
     double2 *obs_chi;                     // [n_bo][nR]
     double *obs_out;                      // packed observables
     int32_t *flags;                       // kNumFlags status flags
@@ -113,7 +113,7 @@ void launch_solve_initial(const Dims &d, const Bufs &b, int parity, double2 *rhs
 void launch_commit_positions(const Dims &d, const Bufs &b, hipStream_t s);
 
 // Observables into b.obs_out (layout in icwf_api.cpp).
-void launch_observables(const Dims &d, const Bufs &b, int parity, hipStream_t s);
+void launch_observables(const Dims &d, const Bufs &b, hipStream_t s);
 
 // FP32 copy of psi1 (mixed form; the propagation keeps it current afterwards).
 void launch_psi1_f32(const Dims &d, const Bufs &b, hipStream_t s);

@@ -1,16 +1,114 @@
-// Observables of the ansatz (text around the Shin-Metiu figure): the norm
-// C^H S C, the reduced densities
-//     rho(R_j) = sum_{b,a} conj(C_b psi2^b_j) S1[b][a] C_a psi2^a_j
-//     rho(r_i) = sum_{b,a} conj(C_b psi1^b_i) S2[b][a] C_a psi1^a_i,
-// the BO projections chi^(n)(R_j) = sum_a C_a psi2^a_j <phi_n(.;R_j)|psi1^a>,
-// the populations P_n = hR sum_j |chi^(n)_j|^2 and the decoherence indicator
-// D_nm = hR sum_j |chi^(n)_j|^2 |chi^(m)_j|^2.  Computed on demand, not every step.
-// Output layout: [norm, rho_r[nr], rho_R[nR], pop[n_bo], D[n_bo][n_bo]].
+// Observables of the ansatz (text around the Shin-Metiu figure), all from the
+// wavefunction on the grid, Eq. 7 evaluated at the grid points:
+//     Psi(r_i, R_j) = sum_a C_a psi1^a_i psi2^a_j          (one complex GEMM)
+//     rho(r_i) = hR sum_j |Psi_ij|^2,   rho(R_j) = hr sum_i |Psi_ij|^2,
+//     norm = hr sum_i rho(r_i)  (= C^H S C),
+//     chi^(n)(R_j) = hr sum_i phi_n(r_i; R_j) Psi_ij  (BO projections, real phi_n),
+//     P_n = hR sum_j |chi^(n)_j|^2,  D_nm = hR sum_j |chi^(n)_j|^2 |chi^(m)_j|^2.
+// The GEMM costs N n_r n_R complex products, against N^2 (n_r + n_R) for the
+// same densities written with the single-species overlaps.  Computed on
+// demand, not every step; every sum runs in a fixed order (bitwise
+// repeatable).  Output layout: [norm, rho_r[nr], rho_R[nR], pop[n_bo], D[n_bo][n_bo]].
 #include "icwf_plan.hpp"
 
 namespace icwf {
 
 namespace {
+
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+__device__ inline dbl4 mfma(double a, double b, dbl4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// Psi = U^T V, U[a][i] = C_a psi1[a][i], V[a][j] = psi2[a][j], a < Np.  One
+// 64 x 64 tile of Psi per work-group of 4 waves, wave w on the 32 x 32
+// quarter (rows 32 (w / 2), columns 32 (w % 2)) as 2 x 2 fragments of
+// v_mfma_f64_16x16x4 with rows = i, columns = j and the trajectory a as the
+// reduction index.  16-trajectory chunks of U (times C_a) and V are staged
+// through double-buffered LDS by coalesced row loads (64 consecutive grid
+// points per row).  Rows or columns beyond the grid (n = 32) read zeros and
+// are not stored.
+constexpr int kOT = 64, kOKC = 16, kOLD = kOT + 1;
+
+__global__ void __launch_bounds__(256) k_obs_psi(const double2 *__restrict__ psi1, const double2 *__restrict__ psi2,
+                                                 const double2 *__restrict__ C, int nr, int nR, int Np,
+                                                 double2 *__restrict__ Psi) {
+    __shared__ double2 sU[2][kOKC][kOLD];
+    __shared__ double2 sV[2][kOKC][kOLD];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int row = lane & 15, quarter = lane >> 4;
+    const int i0 = blockIdx.y * kOT, j0 = blockIdx.x * kOT;
+    const int wi = 32 * (wave >> 1), wj = 32 * (wave & 1);
+    // staging: thread t loads grid point c = t % 64 of the chunk rows t / 64 + 4 m
+    const int sc = t & 63, sr = t >> 6;
+    const bool ui = i0 + sc < nr, vj = j0 + sc < nR;
+    dbl4 re[2][2], im[2][2];
+#pragma unroll
+    for (int f = 0; f < 2; ++f)
+#pragma unroll
+        for (int g = 0; g < 2; ++g) {
+            re[f][g] = dbl4{0, 0, 0, 0};
+            im[f][g] = dbl4{0, 0, 0, 0};
+        }
+    double2 ru[4], rv[4];
+    auto load = [&](int a0) {
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            const int a = a0 + sr + 4 * m;
+            ru[m] = ui ? cmul(C[a], psi1[(size_t)a * nr + i0 + sc]) : make_double2(0.0, 0.0);
+            rv[m] = vj ? psi2[(size_t)a * nR + j0 + sc] : make_double2(0.0, 0.0);
+        }
+    };
+    auto stage = [&](int buf) {
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            sU[buf][sr + 4 * m][sc] = ru[m];
+            sV[buf][sr + 4 * m][sc] = rv[m];
+        }
+    };
+    load(0);
+    stage(0);
+    __syncthreads();
+    const int nch = Np / kOKC;
+    for (int ch = 0; ch < nch; ++ch) {
+        const int buf = ch & 1;
+        const bool more = ch + 1 < nch;
+        if (more) load((ch + 1) * kOKC);
+#pragma unroll
+        for (int s4 = 0; s4 < kOKC / 4; ++s4) {
+            const int kk = 4 * s4 + quarter;
+            double2 uv[2], vv[2];
+#pragma unroll
+            for (int f = 0; f < 2; ++f) {
+                uv[f] = sU[buf][kk][wi + 16 * f + row];
+                vv[f] = sV[buf][kk][wj + 16 * f + row];
+            }
+#pragma unroll
+            for (int f = 0; f < 2; ++f)
+#pragma unroll
+                for (int g = 0; g < 2; ++g) {
+                    // u v = (ur vr - ui vi) + i (ur vi + ui vr)
+                    re[f][g] = mfma(uv[f].x, vv[g].x, re[f][g]);
+                    re[f][g] = mfma(-uv[f].y, vv[g].y, re[f][g]);
+                    im[f][g] = mfma(uv[f].x, vv[g].y, im[f][g]);
+                    im[f][g] = mfma(uv[f].y, vv[g].x, im[f][g]);
+                }
+        }
+        if (more) stage(buf ^ 1);
+        __syncthreads();
+    }
+#pragma unroll
+    for (int f = 0; f < 2; ++f)
+#pragma unroll
+        for (int g = 0; g < 2; ++g)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int i = i0 + wi + 16 * f + mfma_row_f64(lane, v);
+                const int j = j0 + wj + 16 * g + row;
+                if (i < nr && j < nR) Psi[(size_t)i * nR + j] = make_double2(re[f][g][v], im[f][g][v]);
+            }
+}
 
 __device__ inline double block_sum(double v, double *red) {
     const int t = threadIdx.x;
@@ -25,62 +123,67 @@ __device__ inline double block_sum(double v, double *red) {
     return s;
 }
 
-// out[0] = Re(C^H S C); one block of 256 threads, one thread per row strip.
-__global__ void k_obs_norm(const double2 *__restrict__ S, const double2 *__restrict__ C, int Np,
-                           double *__restrict__ out) {
-    __shared__ double red[256];
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+// rho_r[i] = hR sum_j |Psi_ij|^2: one wave per row, four rows per block.
+__global__ void k_obs_rho_r(const double2 *__restrict__ Psi, int nr, int nR, double hR, double *__restrict__ rho) {
+    const int i = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (i >= nr) return;
     double acc = 0.0;
-    for (int b = threadIdx.x; b < Np; b += blockDim.x) {
-        double2 y = make_double2(0, 0);
-        const double2 *row = S + (size_t)b * Np;
-        for (int a = 0; a < Np; ++a) y = cadd(y, cmul(row[a], C[a]));
-        acc += cmulc(C[b], y).x;
+    for (int j = lane; j < nR; j += 64) {
+        const double2 p = Psi[(size_t)i * nR + j];
+        acc += p.x * p.x + p.y * p.y;
     }
-    const double s = block_sum(acc, red);
-    if (threadIdx.x == 0) out[0] = s;
+    acc = wave_sum(acc);
+    if (lane == 0) rho[i] = hR * acc;
 }
 
-// U[a][i] = C_a psi[a][i]
-__global__ void k_obs_u(const double2 *__restrict__ psi, const double2 *__restrict__ C, int n, int Np,
-                        double2 *__restrict__ U) {
-    const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= (size_t)Np * n) return;
-    U[idx] = cmul(C[idx / n], psi[idx]);
-}
-
-// rho[j] = Re sum_b conj(U[b][j]) sum_a O[b][a] U[a][j]; one block per j.
-__global__ void k_obs_density(const double2 *__restrict__ O, const double2 *__restrict__ U, int n, int Np,
-                              double *__restrict__ rho) {
-    __shared__ double red[256];
-    const int j = blockIdx.x;
+// rho_R[j] = hr sum_i |Psi_ij|^2: 64 columns per block, four row slices
+// reduced in LDS in a fixed order.
+__global__ void k_obs_rho_R(const double2 *__restrict__ Psi, int nr, int nR, double hr, double *__restrict__ rho) {
+    __shared__ double part[4][64];
+    const int c = threadIdx.x & 63, sl = threadIdx.x >> 6;
+    const int j = blockIdx.x * 64 + c;
     double acc = 0.0;
-    for (int b = threadIdx.x; b < Np; b += blockDim.x) {
-        const double2 *row = O + (size_t)b * Np;
-        double2 v = make_double2(0, 0);
-        for (int a = 0; a < Np; ++a) v = cadd(v, cmul(row[a], U[(size_t)a * n + j]));
-        acc += cmulc(U[(size_t)b * n + j], v).x;
-    }
-    const double s = block_sum(acc, red);
-    if (threadIdx.x == 0) rho[j] = s;
+    if (j < nR)
+        for (int i = sl; i < nr; i += 4) {
+            const double2 p = Psi[(size_t)i * nR + j];
+            acc += p.x * p.x + p.y * p.y;
+        }
+    part[sl][c] = acc;
+    __syncthreads();
+    if (sl == 0 && j < nR) rho[j] = hr * (((part[0][c] + part[1][c]) + part[2][c]) + part[3][c]);
 }
 
-// chi[nb][j] = sum_a C_a psi2[a][j] hr sum_i bo[j][nb][i] psi1[a][i]; one block per (j, nb).
-__global__ void k_obs_chi(const double *__restrict__ bo, const double2 *__restrict__ psi1,
-                          const double2 *__restrict__ psi2, const double2 *__restrict__ C, int nr, int nR,
-                          int n_bo, int Np, double hr, double2 *__restrict__ chi) {
-    __shared__ double red[256];
-    const int j = blockIdx.x, nb = blockIdx.y;
+// out[0] = hr sum_i rho_r[i]; one block.
+__global__ void k_obs_norm(const double *__restrict__ rho_r, int nr, double hr, double *__restrict__ out) {
+    __shared__ double part[4];
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < nr; i += blockDim.x) acc += rho_r[i];
+    acc = wave_sum(acc);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) out[0] = hr * (((part[0] + part[1]) + part[2]) + part[3]);
+}
+
+// chi[nb][j] = hr sum_i bo[j][nb][i] Psi_ij: one wave per (j, nb).
+__global__ void k_obs_chi(const double *__restrict__ bo, const double2 *__restrict__ Psi, int nr, int nR,
+                          int n_bo, double hr, double2 *__restrict__ chi) {
+    const int j = blockIdx.x, nb = blockIdx.y, lane = threadIdx.x;
     const double *phi = bo + ((size_t)j * n_bo + nb) * nr;
-    double2 acc = make_double2(0, 0);
-    for (int a = threadIdx.x; a < Np; a += blockDim.x) {
-        const double2 *p = psi1 + (size_t)a * nr;
-        double2 pr = make_double2(0, 0);
-        for (int i = 0; i < nr; ++i) pr = cadd(pr, cscale(p[i], phi[i]));
-        acc = cadd(acc, cmul(cmul(C[a], psi2[(size_t)a * nR + j]), cscale(pr, hr)));
+    double sr = 0.0, si = 0.0;
+    for (int i = lane; i < nr; i += 64) {
+        const double2 p = Psi[(size_t)i * nR + j];
+        sr += phi[i] * p.x;
+        si += phi[i] * p.y;
     }
-    const double sr = block_sum(acc.x, red);
-    const double si = block_sum(acc.y, red);
-    if (threadIdx.x == 0) chi[(size_t)nb * nR + j] = make_double2(sr, si);
+    sr = wave_sum(sr);
+    si = wave_sum(si);
+    if (lane == 0) chi[(size_t)nb * nR + j] = make_double2(hr * sr, hr * si);
 }
 
 // pop[n] and D[n][m]; one block.
@@ -119,21 +222,18 @@ __global__ void k_obs_pop(const double2 *__restrict__ chi, int nR, int n_bo, dou
 
 }  // namespace
 
-void launch_observables(const Dims &d, const Bufs &b, int parity, hipStream_t s) {
+void launch_observables(const Dims &d, const Bufs &b, hipStream_t s) {
     const int Np = padded(d.N);
     double *out = b.obs_out;
-    hipLaunchKernelGGL(k_obs_norm, dim3(1), dim3(256), 0, s, b.Smat[parity], b.C, Np, out);
-    size_t tot = (size_t)Np * d.nR;
-    hipLaunchKernelGGL(k_obs_u, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, b.psi2, b.C, d.nR, Np,
-                       b.obs_u);
-    hipLaunchKernelGGL(k_obs_density, dim3(d.nR), dim3(256), 0, s, b.S1, b.obs_u, d.nR, Np, out + 1 + d.nr);
-    tot = (size_t)Np * d.nr;
-    hipLaunchKernelGGL(k_obs_u, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, b.psi1, b.C, d.nr, Np,
-                       b.obs_u);
-    hipLaunchKernelGGL(k_obs_density, dim3(d.nr), dim3(256), 0, s, b.S2, b.obs_u, d.nr, Np, out + 1);
+    double *rho_r = out + 1, *rho_R = out + 1 + d.nr;
+    const dim3 tiles((d.nR + kOT - 1) / kOT, (d.nr + kOT - 1) / kOT);
+    hipLaunchKernelGGL(k_obs_psi, tiles, dim3(256), 0, s, b.psi1, b.psi2, b.C, d.nr, d.nR, Np, b.obs_psi);
+    hipLaunchKernelGGL(k_obs_rho_r, dim3((d.nr + 3) / 4), dim3(256), 0, s, b.obs_psi, d.nr, d.nR, d.hR, rho_r);
+    hipLaunchKernelGGL(k_obs_rho_R, dim3((d.nR + 63) / 64), dim3(256), 0, s, b.obs_psi, d.nr, d.nR, d.hr, rho_R);
+    hipLaunchKernelGGL(k_obs_norm, dim3(1), dim3(256), 0, s, rho_r, d.nr, d.hr, out);
     if (d.n_bo > 0) {
-        hipLaunchKernelGGL(k_obs_chi, dim3(d.nR, d.n_bo), dim3(256), 0, s, b.bo, b.psi1, b.psi2, b.C, d.nr, d.nR,
-                           d.n_bo, Np, d.hr, b.obs_chi);
+        hipLaunchKernelGGL(k_obs_chi, dim3(d.nR, d.n_bo), dim3(64), 0, s, b.bo, b.obs_psi, d.nr, d.nR, d.n_bo, d.hr,
+                           b.obs_chi);
         double *pop = out + 1 + d.nr + d.nR;
         hipLaunchKernelGGL(k_obs_pop, dim3(1), dim3(256), 0, s, b.obs_chi, d.nR, d.n_bo, d.hR, pop, pop + d.n_bo);
     }

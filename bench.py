@@ -1,7 +1,7 @@
 """ICWF throughput benchmark on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp64|mixed] [--no-cpu-baseline]
-                    [--no-serving] [--serve-sims S] [--serve-steps T]
+                    [--no-serving] [--serve-sims S] [--serve-steps T] [--no-large-propagation]
 
 One step = one full pass of the ICWF hot path (Bohmian velocities and
 trajectory update, split-operator propagation of all 2N conditional
@@ -14,8 +14,9 @@ Prints one JSON line: traj-steps/s over exactly K timed steps, the roofline
 of the dominant kernel (the two-body contraction, timed live with HIP events
 on the stream it runs on), the serving mix (served sims/s, p50 / p99
 time-to-result under Poisson arrivals, the speedup over running the same
-simulations one by one in FP64), and the FP64 oracle timed on a bounded sample
-on the host cores.
+simulations one by one in FP64), the propagation's HBM rate on the
+N = 4096, 4096 x 512 workload (whose CWFs do not fit the Infinity Cache), and
+the FP64 oracle timed on a bounded sample on the host cores.
 """
 
 import argparse
@@ -69,12 +70,35 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-steps", type=int, default=2)
     p.add_argument("--no-serving", action="store_true", help="skip the serving-mix leg")
+    p.add_argument("--no-large-propagation", action="store_true",
+                   help="skip the propagation measurement on the N = 4096, 4096 x 512 workload")
     p.add_argument("--serve-sims", type=int, default=32)
     p.add_argument("--serve-steps", type=int, default=100)
     p.add_argument("--copy-calibration-bytes", type=int, default=0,
                    help="first run a plain device copy of this many bytes three times (the reference kernel "
                         "that scales the HBM traffic counters)")
     return p.parse_args()
+
+
+def large_propagation():
+    """The propagation on the working set that does not fit the 256 MB
+    Infinity Cache (N = 4096, 4096 x 512: 604 MB read and written per step),
+    FP64, one timed step after one untimed one."""
+    from paper_1805_11169_amd import icwf, inputs
+    wl = inputs.preset("sm_n4096_large", n_bo=0)
+    sim = icwf.Simulation.from_workload(wl, precision=icwf.PREC_FP64, device=0)
+    sim.step(1)
+    sim.sync()
+    sim.set_timing(True)
+    sim.step(1)
+    sim.sync()
+    n, ms = sim.kernel_time("propagate")
+    sim.set_timing(False)
+    sim.close()
+    _, _, prop_bytes = algorithmic_counts(wl.n_traj, wl.n_r, wl.n_R)
+    gbs = prop_bytes / (ms / 1e3 / n) / 1e9
+    return {"workload": wl.name, "n_traj": wl.n_traj, "n_r": wl.n_r, "n_R": wl.n_R, "bytes_per_step": prop_bytes,
+            "avg_launch_ms": ms / n, "achieved_gbs": gbs, "peak_gbs": HBM_PEAK_GBS, "frac": gbs / HBM_PEAK_GBS}
 
 
 def algorithmic_counts(N, nr, nR):
@@ -189,6 +213,8 @@ def main():
         "observables_ms": obs_ms,
         "final_norm": obs["norm"],
     }
+    if not args.no_large_propagation and args.workload != "sm_n4096_large":
+        line["propagation_4096x512"] = large_propagation()
     if not args.no_serving:
         from paper_1805_11169_amd import serving
         line["serving"] = serving.measure(n_sims=args.serve_sims, n_steps=args.serve_steps,

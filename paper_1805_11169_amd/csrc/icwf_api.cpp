@@ -66,7 +66,6 @@ Bufs carve(const icwf_config &c, char *base, size_t *total) {
     b.wc64 = L.take<double>(nr * nR);
     b.wc32 = L.take<float>(nr * nR);
     const bool mixed = c.precision == ICWF_PREC_MIXED;
-    b.lr_part = L.take<double2>(mixed ? 4 * Np * Np : 1);
     b.psi1_f32 = L.take<float2>(mixed ? Np * nr : 1);
     b.lr_u = L.take<double>(icwf::kLowRankMax * nr);
     b.lr_v = L.take<double>(icwf::kLowRankMax * nR);

@@ -40,7 +40,6 @@ struct Bufs {
     double *wc64;                         // [nr][nR] W_c(r_i, R_j)
     float *wc32;                          // [nr][nR] FP32 residual of the rank-K split (mixed form)
     double *lr_u, *lr_v;                  // [kLowRankMax][nr], [kLowRankMax][nR] rank-K factors
-    double2 *lr_part;                     // [4][Np][Np] rank-group partials (mixed form only)
     float2 *psi1_f32;                     // [Np][nr] FP32 copy of psi1 (mixed form only)
     double *sinc_r, *dsinc_r;             // [N][nr] periodic sinc and derivative at r^a
     double *sinc_R, *dsinc_R;             // [N][nR]

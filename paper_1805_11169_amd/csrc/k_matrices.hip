@@ -382,113 +382,145 @@ __global__ void __launch_bounds__(256, 2) k_wc(const typename WcTraits<T>::cplx 
     }
 }
 
-// FP64 rank-K part of the two-body contraction for the mixed form:
-//     Wc[b][a] += sum_k (hr sum_i conj(psi1^b_i) u_k(r_i) psi1^a_i)
-//                       (hR sum_j conj(psi2^b_j) v_k(R_j) psi2^a_j),
-// with W_c ~ sum_k u_k(r) v_k(R) + residual.  One wave per 32 x 32 tile of the
-// upper triangle (32-tiles) and rank group g = blockIdx.y (ranks g, g + G, ...);
-// each factor is a conj-NT complex product with the ket weighted by u_k (or
-// v_k) in registers, multiplied elementwise in the epilogue.  Group g writes
-// its partial sum to part[g]; k_lr_reduce adds the groups into Wc in a fixed
-// order (no atomics, so the result does not depend on scheduling).
-constexpr int kLrGroups = 4;
+// FP64 rank-K part of the two-body contraction:
+//     Wc[b][a] (+)= hr hR sum_k alpha_k(b, a) beta_k(b, a),
+//     alpha_k(b, a) = sum_i conj(psi1^b_i) psi1^a_i u_k(r_i),
+//     beta_k(b, a)  = sum_j conj(psi2^b_j) psi2^a_j v_k(R_j),
+// for W_c ~ sum_k u_k(r) v_k(R).  The pair tiles, queue, staging and pair
+// products of k_wc, with the W_c table replaced by 16 rank factors at a time:
+// MFMA rows = a, columns = the rank k of the chunk, reduction over i (then j
+// with the psi2 rows); the epilogue multiplies the two products and sums over
+// the chunk's ranks with 16-lane shuffles.  Ranks above K have zero factors.
+constexpr int kSepKC = 32;   // grid points per staged chunk
 
-__global__ void __launch_bounds__(64) k_wc_lowrank(const double2 *__restrict__ psi1,
-                                                   const double2 *__restrict__ psi2,
-                                                   const double *__restrict__ U, const double *__restrict__ V,
-                                                   int rank, int nr, int nR, double hr, double hR,
-                                                   double2 *__restrict__ part, int Np,
-                                                   const int32_t *__restrict__ flags) {
-    if (flags[kFlagHalt]) return;
-    int tb, ta;
-    triangle_tile(blockIdx.x, &tb, &ta);
-    double2 *Wc = part + (size_t)blockIdx.y * Np * Np;
-    const int lane = threadIdx.x, row = lane & 15, quarter = lane >> 4;
-    const int b0 = tb * 32, a0 = ta * 32;
-    dbl4 wr[2][2], wi[2][2];
+// One factor product of a rank chunk: acc[bb][re/im] (rows a, columns k) =
+// sum_i conj(X^b_i) X^a_i F[k0 + k][i] for the wave's four b rows.
+__device__ inline void sep_pass(dbl4 (&acc)[4][2], const double2 *__restrict__ X, const double *__restrict__ F,
+                                int n, int k0, int a_base, int b_tile, double2 (*sA)[32][kSepKC + 1],
+                                double (*sF)[kSepKC][17]) {
+    const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
+    const int row = lane & 15, quarter = lane >> 4;
+    constexpr int QS = kSepKC / 4;
 #pragma unroll
-    for (int f = 0; f < 2; ++f)
-#pragma unroll
-        for (int g = 0; g < 2; ++g) {
-            wr[f][g] = dbl4{0, 0, 0, 0};
-            wi[f][g] = dbl4{0, 0, 0, 0};
-        }
-    for (int k = blockIdx.y; k < rank; k += gridDim.y) {
-        dbl4 ur[2][2], ui[2][2], vr[2][2], vi[2][2];
-#pragma unroll
-        for (int f = 0; f < 2; ++f)
-#pragma unroll
-            for (int g = 0; g < 2; ++g) {
-                ur[f][g] = dbl4{0, 0, 0, 0};
-                ui[f][g] = dbl4{0, 0, 0, 0};
-                vr[f][g] = dbl4{0, 0, 0, 0};
-                vi[f][g] = dbl4{0, 0, 0, 0};
-            }
-        for (int sp = 0; sp < 2; ++sp) {
-            const double2 *X = sp == 0 ? psi1 : psi2;
-            const double *wgt = (sp == 0 ? U + (size_t)k * nr : V + (size_t)k * nR);
-            const int n = sp == 0 ? nr : nR;
-            const int q = n >> 2;
-            for (int s = 0; s < q; ++s) {
-                const int i = quarter * q + s;
-                const double w = wgt[i];
-                double2 xv[2], yv[2];
-#pragma unroll
-                for (int f = 0; f < 2; ++f) {
-                    xv[f] = X[(size_t)(b0 + 16 * f + row) * n + i];
-                    yv[f] = cscale(X[(size_t)(a0 + 16 * f + row) * n + i], w);
-                }
-#pragma unroll
-                for (int f = 0; f < 2; ++f)
-#pragma unroll
-                    for (int g = 0; g < 2; ++g) {
-                        dbl4 &re = sp == 0 ? ur[f][g] : vr[f][g];
-                        dbl4 &im = sp == 0 ? ui[f][g] : vi[f][g];
-                        re = mfma(xv[f].x, yv[g].x, re);
-                        re = mfma(xv[f].y, yv[g].y, re);
-                        im = mfma(xv[f].x, yv[g].y, im);
-                        im = mfma(-xv[f].y, yv[g].x, im);
-                    }
-            }
-        }
-#pragma unroll
-        for (int f = 0; f < 2; ++f)
-#pragma unroll
-            for (int g = 0; g < 2; ++g)
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const double2 u = make_double2(ur[f][g][v], ui[f][g][v]);
-                    const double2 w = make_double2(vr[f][g][v], vi[f][g][v]);
-                    const double2 p = cmul(u, w);
-                    wr[f][g][v] += p.x;
-                    wi[f][g][v] += p.y;
-                }
+    for (int bb = 0; bb < 4; ++bb) {
+        acc[bb][0] = dbl4{0, 0, 0, 0};
+        acc[bb][1] = dbl4{0, 0, 0, 0};
     }
-    const double sc = hr * hR;
+    const int nchunk = n / kSepKC;
+    // staging: element e = t + 256 m of the 32 psi rows x 32 points (m < 4) and
+    // of the 32 points x 16 ranks of the factors (m < 2)
+    double2 ra0, ra1, ra2, ra3;
+    double rf0, rf1;
+    const int rr0 = t >> 5, cc = t & 31;
+    const int ii0 = t >> 4, kk = t & 15;
+    const double2 *xrow[4];
 #pragma unroll
-    for (int f = 0; f < 2; ++f)
+    for (int m = 0; m < 4; ++m) {
+        const int rr = rr0 + 8 * m;
+        xrow[m] = X + (size_t)(rr < 16 ? a_base + rr : b_tile + rr - 16) * n + cc;
+    }
+    const double *frow = F + (size_t)(k0 + kk) * n + ii0;
+    ra0 = xrow[0][0];
+    ra1 = xrow[1][0];
+    ra2 = xrow[2][0];
+    ra3 = xrow[3][0];
+    rf0 = frow[0];
+    rf1 = frow[16];
+    sA[0][rr0][cc] = ra0;
+    sA[0][rr0 + 8][cc] = ra1;
+    sA[0][rr0 + 16][cc] = ra2;
+    sA[0][rr0 + 24][cc] = ra3;
+    sF[0][ii0][kk] = rf0;
+    sF[0][ii0 + 16][kk] = rf1;
+    __syncthreads();
+    for (int ch = 0; ch < nchunk; ++ch) {
+        const int buf = ch & 1;
+        const bool more = ch + 1 < nchunk;
+        if (more) {
+            const int o = (ch + 1) * kSepKC;
+            ra0 = xrow[0][o];
+            ra1 = xrow[1][o];
+            ra2 = xrow[2][o];
+            ra3 = xrow[3][o];
+            rf0 = frow[o];
+            rf1 = frow[o + 16];
+        }
+#pragma unroll 2
+        for (int s = 0; s < QS; ++s) {
+            const int col = quarter * QS + s;
+            const double2 xa = sA[buf][row][col];
+            const double f = sF[buf][col][row];
 #pragma unroll
-        for (int g = 0; g < 2; ++g)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int b = b0 + 16 * f + mfma_row_f64(lane, v);
-                const int a = a0 + 16 * g + row;
-                Wc[(size_t)b * Np + a] = make_double2(sc * wr[f][g][v], sc * wi[f][g][v]);
+            for (int bb = 0; bb < 4; ++bb) {
+                const double2 p = cmulc(sA[buf][16 + 4 * wave + bb][col], xa);   // conj(X^b_i) X^a_i
+                acc[bb][0] = mfma(p.x, f, acc[bb][0]);
+                acc[bb][1] = mfma(p.y, f, acc[bb][1]);
             }
+        }
+        if (more) {
+            const int nb = buf ^ 1;
+            sA[nb][rr0][cc] = ra0;
+            sA[nb][rr0 + 8][cc] = ra1;
+            sA[nb][rr0 + 16][cc] = ra2;
+            sA[nb][rr0 + 24][cc] = ra3;
+            sF[nb][ii0][kk] = rf0;
+            sF[nb][ii0 + 16][kk] = rf1;
+        }
+        __syncthreads();
+    }
 }
 
-// Wc[b][a] += sum_g part[g][b][a] over the upper triangle b <= a (the half
-// every reader of Wc uses), groups summed in index order.
-__global__ void k_lr_reduce(const double2 *__restrict__ part, int groups, double2 *__restrict__ Wc, int Np,
-                            const int32_t *__restrict__ flags) {
+__global__ void __launch_bounds__(256, 2) k_wc_sep(const double2 *__restrict__ psi1, const double2 *__restrict__ psi2,
+                                                   const double *__restrict__ U, const double *__restrict__ V,
+                                                   int kpad, int nr, int nR, double scale,
+                                                   double2 *__restrict__ Wc, int Np, int accumulate, int ntiles,
+                                                   int32_t *__restrict__ queue, const int32_t *__restrict__ flags) {
     if (flags[kFlagHalt]) return;
-    const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= (size_t)Np * Np) return;
-    const int b = (int)(idx / Np), a = (int)(idx - (size_t)b * Np);
-    if (b > a) return;
-    double2 s = Wc[idx];
-    for (int g = 0; g < groups; ++g) s = cadd(s, part[(size_t)g * Np * Np + idx]);
-    Wc[idx] = s;
+    __shared__ double2 sA[2][32][kSepKC + 1];
+    __shared__ double sF[2][kSepKC][17];
+    __shared__ double2 wl[4][4][16];     // [wave][b][a] block partial of Wc
+    __shared__ int s_tile;
+    for (;;) {
+        if (threadIdx.x == 0) s_tile = atomicAdd(queue, 1);
+        __syncthreads();
+        const int tile = s_tile;
+        __syncthreads();
+        if (tile >= ntiles) break;
+        int tb, ta;
+        triangle_tile(tile, &tb, &ta);
+        const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+        const int row = lane & 15;
+        const int a_base = ta * 16, b_tile = tb * 16, b_base = b_tile + 4 * wave;
+        wl[wave][lane >> 4][lane & 15] = make_double2(0, 0);
+        for (int k0 = 0; k0 < kpad; k0 += 16) {
+            dbl4 acc1[4][2], acc2[4][2];
+            sep_pass(acc1, psi1, U, nr, k0, a_base, b_tile, sA, sF);
+            sep_pass(acc2, psi2, V, nR, k0, a_base, b_tile, sA, sF);
+#pragma unroll
+            for (int bb = 0; bb < 4; ++bb)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    // lane: a = a_base + mfma_row(lane, v), rank k0 + row
+                    double2 x = cmul(make_double2(acc1[bb][0][v], acc1[bb][1][v]),
+                                     make_double2(acc2[bb][0][v], acc2[bb][1][v]));
+#pragma unroll
+                    for (int off = 8; off > 0; off >>= 1) {
+                        x.x += __shfl_xor(x.x, off, 16);
+                        x.y += __shfl_xor(x.y, off, 16);
+                    }
+                    if (row == 0) {
+                        double2 &dst = wl[wave][bb][mfma_row_f64(lane, v)];
+                        dst = cadd(dst, x);
+                    }
+                }
+        }
+        {
+            const int bb = lane >> 4, a = lane & 15;
+            const double2 x = cscale(wl[wave][bb][a], scale);
+            double2 *dst = Wc + (size_t)(b_base + bb) * Np + a_base + a;
+            *dst = accumulate ? cadd(*dst, x) : x;
+        }
+    }
 }
 
 }  // namespace
@@ -537,13 +569,10 @@ void launch_wc(const Dims &d, const Bufs &b, hipStream_t s) {
         hipLaunchKernelGGL(k_wc<float>, dim3(std::min(blocks, d.wc_grid)), dim3(256), 0, s, b.psi1_f32, b.psi2,
                            b.wc32, d.nr, d.nR, scale, b.Wc, Np, 0, blocks, b.wc_queue, b.flags);
         if (d.lr_rank > 0) {
-            const int T32 = Np / 32;
-            const int groups = d.lr_rank < kLrGroups ? d.lr_rank : kLrGroups;
-            hipLaunchKernelGGL(k_wc_lowrank, dim3(T32 * (T32 + 1) / 2, groups), dim3(64), 0, s, b.psi1, b.psi2,
-                               b.lr_u, b.lr_v, d.lr_rank, d.nr, d.nR, d.hr, d.hR, b.lr_part, Np, b.flags);
-            const size_t tot = (size_t)Np * Np;
-            hipLaunchKernelGGL(k_lr_reduce, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, b.lr_part, groups,
-                               b.Wc, Np, b.flags);
+            launch_fill_i32(b.wc_queue, 1, 0, s);
+            hipLaunchKernelGGL(k_wc_sep, dim3(std::min(blocks, d.wc_grid)), dim3(256), 0, s, b.psi1, b.psi2, b.lr_u,
+                               b.lr_v, (d.lr_rank + 15) / 16 * 16, d.nr, d.nR, scale, b.Wc, Np, 1, blocks, b.wc_queue,
+                               b.flags);
         }
     } else {
         launch_fill_i32(b.wc_queue, 1, 0, s);

@@ -130,6 +130,24 @@ def test_cavity_2048_sampled(rng):
     assert omat is not None
 
 
+@pytest.mark.parametrize("n_r,n_R", [(2048, 32), (64, 1024)])
+def test_one_step_on_uneven_grids(n_r, n_R):
+    """Grid sizes the other tests leave out (2048 and 32 points; 64 and 1024),
+    so that every compiled transform size from 32 to 4096 points runs against
+    the oracle somewhere: all CWFs after one step, N = 70."""
+    wl = inputs.gaussian_basis(70, n_r=n_r, n_R=n_R, r_box=(-40.0, 40.0), R_box=(-8.0, 8.0), dt=0.1, seed=15)
+    print(f"[case] {wl.name} one step", flush=True)
+    setup = setup_for(wl)
+    sim = icwf.Simulation.from_workload(wl, C0=wl.extra["C0"])
+    sim.step(1)
+    got = sim.state()
+    sim.close()
+    p1, p2 = oprop.propagate_cwfs(wl.psi1, wl.psi2, setup.model, setup.r, setup.R, setup.hr, setup.hR,
+                                  setup.m_r, setup.m_R, wl.r0, wl.R0, setup.dt)
+    assert np.max(np.abs(got["psi1"] - p1)) < 1e-12
+    assert np.max(np.abs(got["psi2"] - p2)) < 1e-12
+
+
 @pytest.mark.parametrize("model", [inputs.MODEL_SHIN_METIU, inputs.MODEL_CAVITY])
 def test_one_step_on_the_4096_point_grid(model):
     """The 4096-point electronic grid takes the four-step transform (64 x 64,

@@ -70,9 +70,16 @@ typedef enum {
 
 typedef enum {
     ICWF_PREC_FP64 = 0,  /* every step in FP64                                        */
-    ICWF_PREC_MIXED = 1  /* Eq. 9b's two-body contraction in FP32 on the matrix cores,
+    ICWF_PREC_MIXED = 1, /* Eq. 9b's two-body contraction in FP32 on the matrix cores,
                             accumulated in FP32 inside each R tile and in FP64 across
                             tiles; everything else FP64                              */
+    ICWF_PREC_SEPARABLE = 2 /* FP64 throughout, Eq. 9b's two-body sum taken through a
+                            sum of products W_c(r_i, R_j) = sum_k u_k(r_i) v_k(R_j)
+                            of at most 64 terms, found at creation by cross
+                            approximation of the W_c table until its residual is
+                            below 4 FP64 roundings of max |W_c| (exact rank 1 for
+                            the cavity coupling); creation fails with ICWF_EINVAL
+                            when no such sum exists                                 */
 } icwf_precision;
 
 typedef struct {
@@ -170,6 +177,12 @@ icwf_status icwf_set_timing(icwf_sim *sim, int32_t enable);
  * number of timed launches and their summed duration in milliseconds. */
 icwf_status icwf_kernel_time(icwf_sim *sim, const char *name, int64_t *launches,
                              double *total_ms);
+
+/* Number of terms K of the sum of products W_c = sum_k u_k v_k the handle's
+ * two-body contraction uses (Eq. 9b): the rank-K FP64 part of
+ * ICWF_PREC_MIXED, the whole contraction of ICWF_PREC_SEPARABLE, 0 for
+ * ICWF_PREC_FP64.  *rank: caller-owned host int32.  ICWF_EINVAL on NULL. */
+icwf_status icwf_contraction_rank(const icwf_sim *sim, int32_t *rank);
 
 /* Release the handle (not the workspace).  NULL is ignored. */
 void icwf_destroy(icwf_sim *sim);

@@ -109,7 +109,8 @@ const char *validate(const icwf_config *c) {
     if (!(c->dt > 0) || !std::isfinite(c->dt)) return "dt must be > 0";
     if (!(c->tikhonov_eps >= 0) || !std::isfinite(c->tikhonov_eps)) return "tikhonov_eps must be >= 0";
     if (c->model != ICWF_MODEL_SHIN_METIU && c->model != ICWF_MODEL_CAVITY) return "unknown model";
-    if (c->precision != ICWF_PREC_FP64 && c->precision != ICWF_PREC_MIXED) return "unknown precision";
+    if (c->precision != ICWF_PREC_FP64 && c->precision != ICWF_PREC_MIXED && c->precision != ICWF_PREC_SEPARABLE)
+        return "unknown precision";
     if (c->n_bo < 0 || c->n_bo > c->n_r) return "n_bo must be in [0, n_r]";
     for (int i = 0; i < 8; ++i)
         if (!std::isfinite(c->model_params[i])) return "model parameters must be finite";
@@ -176,6 +177,8 @@ int cross_approximation(std::vector<double> &W, int n, int m, double tol, int km
 
 // Relative size of the residual the mixed form leaves to FP32.
 constexpr double kMixedSplitTol = 1e-4;
+// Residual the separable form accepts: a few roundings of the table itself.
+constexpr double kSeparableTol = 4.0 * 2.220446049250313e-16;
 
 struct Timer {
     std::vector<std::pair<hipEvent_t, hipEvent_t>> recs;
@@ -441,6 +444,16 @@ icwf_status icwf_create(const icwf_config *cfg, const double *r0, const double *
         std::vector<double> res = wc;
         d.lr_rank = cross_approximation(res, nr, nR, kMixedSplitTol, icwf::kLowRankMax, lr_u, lr_v);
         for (size_t e = 0; e < res.size(); ++e) wc32[e] = static_cast<float>(res[e]);
+    } else if (cfg->precision == ICWF_PREC_SEPARABLE) {
+        std::vector<double> res = wc;
+        d.lr_rank = cross_approximation(res, nr, nR, kSeparableTol, icwf::kLowRankMax, lr_u, lr_v);
+        double wmax = 0.0, rmax = 0.0;
+        for (size_t e = 0; e < wc.size(); ++e) {
+            wmax = std::max(wmax, std::fabs(wc[e]));
+            rmax = std::max(rmax, std::fabs(res[e]));
+        }
+        if (rmax > kSeparableTol * wmax)
+            return cleanup_fail(ICWF_EINVAL, "W_c is not a sum of at most 64 products to FP64 rounding; use the FP64 form");
     }
     auto fill_k = [&](std::vector<double2> &kin, std::vector<double2> &tw, int n, double h, double m) {
         for (int k = 0; k < n; ++k) {
@@ -629,6 +642,12 @@ icwf_status icwf_set_timing(icwf_sim *s, int32_t enable) {
         }
     s->timers.clear();
     s->timing = enable != 0;
+    return ICWF_OK;
+}
+
+icwf_status icwf_contraction_rank(const icwf_sim *s, int32_t *rank) {
+    if (!s || !rank) return ICWF_EINVAL;
+    *rank = s->d.lr_rank;
     return ICWF_OK;
 }
 

@@ -25,7 +25,7 @@ struct Dims {
 constexpr int kPad = 64;
 inline int padded(int N) { return (N + kPad - 1) / kPad * kPad; }
 constexpr int kCholNb = 64;      // Cholesky panel width
-constexpr int kLowRankMax = 32;  // largest rank of the FP64 part of the mixed contraction
+constexpr int kLowRankMax = 64;  // most terms of a sum-of-products W_c (mixed and separable forms)
 constexpr int kWcReserve = 64;   // CU slots the persistent contraction leaves to the other stream
 
 struct Bufs {

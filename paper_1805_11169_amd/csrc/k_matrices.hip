@@ -574,6 +574,12 @@ void launch_wc(const Dims &d, const Bufs &b, hipStream_t s) {
                                b.lr_v, (d.lr_rank + 15) / 16 * 16, d.nr, d.nR, scale, b.Wc, Np, 1, blocks, b.wc_queue,
                                b.flags);
         }
+    } else if (d.prec == 2) {
+        // separable: the whole contraction through the sum of products (assigns Wc)
+        launch_fill_i32(b.wc_queue, 1, 0, s);
+        hipLaunchKernelGGL(k_wc_sep, dim3(std::min(blocks, d.wc_grid)), dim3(256), 0, s, b.psi1, b.psi2, b.lr_u,
+                           b.lr_v, (d.lr_rank + 15) / 16 * 16, d.nr, d.nR, scale, b.Wc, Np, 0, blocks, b.wc_queue,
+                           b.flags);
     } else {
         launch_fill_i32(b.wc_queue, 1, 0, s);
         hipLaunchKernelGGL(k_wc<double>, dim3(std::min(blocks, d.wc_grid)), dim3(256), 0, s, b.psi1, b.psi2,

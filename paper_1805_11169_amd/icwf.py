@@ -17,11 +17,12 @@ LIB_PATH = os.path.join(HERE, "libicwf.so")
 
 OK, EINVAL, ENOMEM, EDEVICE, ENONFINITE, ENODE, ESOLVE, ESTATE, ETIMEDOUT = 0, -1, -2, -3, -4, -5, -6, -7, -8
 MODEL_SHIN_METIU, MODEL_CAVITY = 1, 2
-PREC_FP64, PREC_MIXED = 0, 1
+PREC_FP64, PREC_MIXED, PREC_SEPARABLE = 0, 1, 2
 
 # the entry points include/icwf.h declares
 EXPORTS = ("icwf_workspace_bytes", "icwf_create", "icwf_step", "icwf_sync", "icwf_observables",
            "icwf_get_state", "icwf_get_matrices", "icwf_velocities", "icwf_set_timing", "icwf_kernel_time",
+           "icwf_contraction_rank",
            "icwf_destroy", "icwf_last_error", "icwf_status_string")
 # the entry points include/icwf_serve.h declares
 SERVE_EXPORTS = ("icwf_server_create", "icwf_server_submit", "icwf_server_wait", "icwf_server_result",
@@ -103,6 +104,8 @@ def lib():
         L.icwf_set_timing.restype = c_int32
         L.icwf_kernel_time.argtypes = [c_void_p, c_char_p, POINTER(c_int64), POINTER(c_double)]
         L.icwf_kernel_time.restype = c_int32
+        L.icwf_contraction_rank.argtypes = [c_void_p, POINTER(c_int32)]
+        L.icwf_contraction_rank.restype = c_int32
         L.icwf_destroy.argtypes = [c_void_p]
         L.icwf_destroy.restype = None
         L.icwf_last_error.argtypes = [c_void_p]
@@ -266,6 +269,11 @@ class Simulation:
         self._check(lib().icwf_kernel_time(self.h, name.encode(), byref(n), byref(ms)))
         return n.value, ms.value
 
+    def contraction_rank(self):
+        k = c_int32()
+        self._check(lib().icwf_contraction_rank(self.h, byref(k)))
+        return k.value
+
     def close(self):
         if getattr(self, "h", None):
             lib().icwf_destroy(self.h)
@@ -351,6 +359,11 @@ class Server:
 
     def clock(self):
         return lib().icwf_server_clock(self.h)
+
+    def contraction_rank(self):
+        k = c_int32()
+        self._check(lib().icwf_contraction_rank(self.h, byref(k)))
+        return k.value
 
     def close(self):
         if getattr(self, "h", None):

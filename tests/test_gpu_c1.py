@@ -1,9 +1,11 @@
 """End-to-end parity on the Shin-Metiu parity workload (N = 64 trajectories,
-512 x 256 grid, dt = 0.1, 200 steps, product start), FP64 and mixed.
+512 x 256 grid, dt = 0.1, 200 steps, product start), FP64, separable and
+mixed.
 
-FP64 bar: observables (norm, reduced densities, BO populations, decoherence)
-within 1e-10 of the oracle, relative to each array's largest entry.  Mixed
-bar: the same observables within 1e-5."""
+FP64 bar (also for the separable form, which is FP64 throughout): observables
+(norm, reduced densities, BO populations, decoherence) within 1e-10 of the
+oracle, relative to each array's largest entry.  Mixed bar: the same
+observables within 1e-5."""
 
 import numpy as np
 import pytest
@@ -66,3 +68,17 @@ def test_mixed_within_1e5(c1):
     w = _compare(gpu, ref)
     for key in ("rho_r", "rho_R", "pop", "D", "norm"):
         assert w[key] < 1e-5, key
+
+
+def test_separable_matches_oracle(c1):
+    """The contraction through the sum of products of W_c (cross approximation
+    down to FP64 rounding): the FP64 bar."""
+    wl, ref = c1
+    sim = icwf.Simulation.from_workload(wl, precision=icwf.PREC_SEPARABLE)
+    rank = sim.contraction_rank()
+    sim.close()
+    assert 1 <= rank <= 64
+    gpu = _gpu_history(wl, icwf.PREC_SEPARABLE)
+    w = _compare(gpu, ref)
+    for key in ("rho_r", "rho_R", "pop", "D", "norm"):
+        assert w[key] < 1e-10, key

@@ -119,3 +119,40 @@ def test_one_step_phases_beyond_a_quarter_turn(dt):
     assert np.max(np.abs(got["psi1"] - ref.psi1)) < 1e-12
     assert np.max(np.abs(got["psi2"] - ref.psi2)) < 1e-12
     sim.close()
+
+
+def test_separable_form_one_step(case):
+    """ICWF_PREC_SEPARABLE (FP64, Eq. 9b through W_c = sum_k u_k v_k): the
+    matrices at t = 0 and one step to the plain form's bars; the cavity
+    coupling lambda q x takes exactly one term."""
+    wl, setup, st0 = case
+    sim = icwf.Simulation.from_workload(wl, precision=icwf.PREC_SEPARABLE, C0=wl.extra["C0"])
+    rank = sim.contraction_rank()
+    if wl.model == inputs.MODEL_CAVITY:
+        assert rank == 1
+    else:
+        assert 1 <= rank <= 64
+    S, K, Wc = sim.matrices()
+    Wc_ref = omat.two_body(st0.psi1, st0.psi2, wc_table(setup), setup.hr, setup.hR)
+    assert rel_max(Wc, Wc_ref) < 1e-12
+    assert rel_max(K, st0.K) < 1e-12
+    sim.step(1)
+    sim.sync()
+    got = sim.state()
+    S1, K1, _ = sim.matrices()
+    ref = oicwf.step(setup, st0)
+    sim.close()
+    assert np.max(np.abs(got["psi1"] - ref.psi1)) < 1e-12
+    assert rel_max(K1, ref.K) < 1e-12
+    assert s_norm_diff(got["C"], ref.C, ref.S) < 1e-10 * np.sqrt(abs(np.conj(ref.C) @ ref.S @ ref.C))
+
+
+def test_separable_form_refuses_a_coupling_without_a_short_sum():
+    """A Shin-Metiu coupling too sharp for 64 products on a fine grid: creation
+    fails with ICWF_EINVAL instead of silently truncating."""
+    wl = inputs.gaussian_basis(40, n_r=1024, n_R=512, r_box=(-40.0, 40.0), R_box=(-20.0, 20.0),
+                               params=[19.0, 0.05, 3.1, 4.0], seed=12)
+    print("[case] sharp Shin-Metiu coupling, separable form", flush=True)
+    with pytest.raises(icwf.ICWFError) as e:
+        icwf.Simulation.from_workload(wl, precision=icwf.PREC_SEPARABLE, C0=wl.extra["C0"])
+    assert e.value.status == icwf.EINVAL

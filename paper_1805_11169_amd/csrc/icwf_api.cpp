@@ -460,7 +460,8 @@ icwf_status icwf_create(const icwf_config *cfg, const double *r0, const double *
             const int kk = (k <= n / 2) ? k : k - n;
             const double kw = 2.0 * M_PI * kk / (n * h);
             const double ph = -0.5 * d.dt * kw * kw / m;
-            kin[k] = make_double2(std::cos(ph), std::sin(ph));
+            // times 1/n, the normalisation of the inverse transform (exact: n is a power of two)
+            kin[k] = make_double2(std::cos(ph) / n, std::sin(ph) / n);
             const double a = -2.0 * M_PI * k / n;
             tw[k] = make_double2(std::cos(a), std::sin(a));
         }

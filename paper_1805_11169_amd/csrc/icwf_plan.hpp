@@ -35,7 +35,7 @@ struct Bufs {
     double2 *y;                           // forward-substitution result of an RK stage
     double2 *rhs;                         // K v of an RK stage
     double2 *vphase_r, *vphase_R;         // exp(-i V_1(r_i) dt/2), exp(-i V_2(R_j) dt/2)
-    double2 *kin_r, *kin_R;               // exp(-i k^2 dt / 2m), FFT order
+    double2 *kin_r, *kin_R;               // exp(-i k^2 dt / 2m) / n, FFT order
     double2 *tw_r, *tw_R;                 // exp(-2 pi i k / n)
     double *wc64;                         // [nr][nR] W_c(r_i, R_j)
     float *wc32;                          // [nr][nR] FP32 residual of the rank-K split (mixed form)

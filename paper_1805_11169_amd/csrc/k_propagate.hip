@@ -35,6 +35,8 @@ namespace {
 constexpr int kPts = 8;   // points per thread
 // the erf(z)/z table in LDS, in 16-byte slots
 constexpr int kErfTableSlots = (kErfPieces * kErfTerms * 8 + 15) / 16;
+// the 64th roots of unity w64^(a b), a, b < 8, of the four-step transform
+constexpr int kW64Slots = 64;
 
 // LDS position of FFT element i: one pad slot after every 8 elements.  The
 // early Stockham passes write with strides 8 and 64 (element 8 t + r, and
@@ -206,14 +208,11 @@ __device__ inline int slot_a(int lo, int a, int b) { return 64 * a + 8 * (b ^ (a
 // element (b, p, e) of the second one (lanes (p, b) -> (e, b))
 __device__ inline int slot_c(int b, int p, int e) { return 64 * b + 8 * (e ^ (b & 1)) + (p ^ e); }
 
-// v[r] *= w^r, r = 1..7 (powers by products, a few ulp)
-__device__ inline void twiddle_powers(double2 (&v)[kPts], double2 w) {
-    double2 wr = w;
+// v[r] *= w64^(a r), r = 1..7, from the LDS table w64[8 a + r] of the 64th
+// roots of unity w64^(a r), a, r < 8
+__device__ inline void twiddle_row(double2 (&v)[kPts], const double2 *w64, int a) {
 #pragma unroll
-    for (int r = 1; r < kPts; ++r) {
-        v[r] = cmul(v[r], wr);
-        if (r + 1 < kPts) wr = cmul(wr, w);
-    }
+    for (int r = 1; r < kPts; ++r) v[r] = cmul(v[r], w64[8 * a + r]);
 }
 
 // v[c] *= w4096^(i1 (hi + 8 c)), c = 0..7
@@ -237,11 +236,12 @@ __device__ inline void cross_wave(double2 (&v)[kPts], double2 *B, int w, int l) 
 }
 
 // forward, input layout -> output layout
-__device__ inline void fft4096_fwd(double2 (&v)[kPts], double2 *B0, double2 *B1, int w, int l, const double2 *tw) {
+__device__ inline void fft4096_fwd(double2 (&v)[kPts], double2 *B0, double2 *B1, int w, int l, const double2 *tw,
+                                   const double2 *w64) {
     const int lo = l & 7, hi = l >> 3;
     double2 *R0 = B0 + w * 512, *R1 = B1 + w * 512;
     dft8(v);                                              // over i2's high part
-    twiddle_powers(v, tw[64 * hi]);                       // w64^(a b), a = hi
+    twiddle_row(v, w64, hi);                              // w64^(a b), a = hi
 #pragma unroll
     for (int b = 0; b < kPts; ++b) R1[slot_a(lo, hi, b)] = v[b];
     wave_sync();
@@ -251,7 +251,7 @@ __device__ inline void fft4096_fwd(double2 (&v)[kPts], double2 *B0, double2 *B1,
     twiddle_middle(v, lo + 8 * w, hi, tw);
     cross_wave(v, B0, w, l);
     dft8(v);                                              // over i1's high part
-    twiddle_powers(v, tw[64 * lo]);                       // w64^(p e), p = lo
+    twiddle_row(v, w64, lo);                              // w64^(p e), p = lo
 #pragma unroll
     for (int e = 0; e < kPts; ++e) R0[slot_c(hi, lo, e)] = v[e];
     wave_sync();
@@ -261,7 +261,8 @@ __device__ inline void fft4096_fwd(double2 (&v)[kPts], double2 *B0, double2 *B1,
 }
 
 // the same stages in reverse: output layout -> input layout
-__device__ inline void fft4096_rev(double2 (&v)[kPts], double2 *B0, double2 *B1, int w, int l, const double2 *tw) {
+__device__ inline void fft4096_rev(double2 (&v)[kPts], double2 *B0, double2 *B1, int w, int l, const double2 *tw,
+                                   const double2 *w64) {
     const int lo = l & 7, hi = l >> 3;
     double2 *R0 = B0 + w * 512, *R1 = B1 + w * 512;
     dft8(v);
@@ -270,7 +271,7 @@ __device__ inline void fft4096_rev(double2 (&v)[kPts], double2 *B0, double2 *B1,
     wave_sync();
 #pragma unroll
     for (int e = 0; e < kPts; ++e) v[e] = R0[slot_c(hi, lo, e)];
-    twiddle_powers(v, tw[64 * lo]);
+    twiddle_row(v, w64, lo);
     dft8(v);
     cross_wave(v, B1, w, l);
     twiddle_middle(v, lo + 8 * w, hi, tw);
@@ -280,7 +281,7 @@ __device__ inline void fft4096_rev(double2 (&v)[kPts], double2 *B0, double2 *B1,
     wave_sync();
 #pragma unroll
     for (int b = 0; b < kPts; ++b) v[b] = R1[slot_a(lo, hi, b)];
-    twiddle_powers(v, tw[64 * hi]);
+    twiddle_row(v, w64, hi);
     dft8(v);
 }
 
@@ -367,7 +368,8 @@ __device__ inline double erf_over_x_table(double d, double inv_a, const double *
 // n = 2^LOG2N points; blockDim.x = max(64, n/8) threads: n/8 per CWF,
 // cpb = blockDim.x / (n/8) CWFs per work-group; work-group g takes the CWF
 // groups g, g + G, ... of the ngroups = Np / cpb (G = gridDim.x).  LDS: the
-// n/8 twiddles, the erf(z)/z table, then two padded buffers per CWF.
+// n/8 twiddles, the erf(z)/z table, the w64^(a b) table, then two (padded)
+// buffers per CWF.
 template <int LOG2N>
 __global__ void __launch_bounds__(512) k_propagate(double2 *__restrict__ psi, int ngroups,
                                                    const double2 *__restrict__ vphase, double x_min, double h,
@@ -386,8 +388,11 @@ __global__ void __launch_bounds__(512) k_propagate(double2 *__restrict__ psi, in
     const int lc = threadIdx.x / q, t0 = threadIdx.x - lc * q;
     double2 *stw = sh_all;
     double *serf = reinterpret_cast<double *>(sh_all + q);
-    double2 *sh = sh_all + q + kErfTableSlots + lc * 2 * ld;
+    double2 *sw64 = sh_all + q + kErfTableSlots;
+    double2 *sh = sh_all + q + kErfTableSlots + kW64Slots + lc * 2 * ld;
     for (int j = threadIdx.x; j < q; j += blockDim.x) stw[j] = tw[j];
+    if constexpr (LOG2N == kFourStepLog2)
+        for (int j = threadIdx.x; j < kW64Slots; j += blockDim.x) sw64[j] = tw[64 * (j >> 3) * (j & 7)];
     for (int j = threadIdx.x; j < kErfPieces * kErfTerms; j += blockDim.x) serf[j] = (&kErfOverZ[0][0])[j];
     int par = 0;
     // this thread's points: x index xi + m q, FFT-order k index ki + m q
@@ -456,17 +461,16 @@ __global__ void __launch_bounds__(512) k_propagate(double2 *__restrict__ psi, in
         double2 kv[kPts];
 #pragma unroll
         for (int m = 0; m < kPts; ++m) kv[m] = kin[ki + m * q];
-        if constexpr (four_step) fft4096_fwd(v, sh, sh + n, t >> 6, t & 63, stw);
+        if constexpr (four_step) fft4096_fwd(v, sh, sh + n, t >> 6, t & 63, stw, sw64);
         else fft8<LOG2N>(v, sh, ld, par, t, stw);
 #pragma unroll
         for (int m = 0; m < kPts; ++m) v[m] = cconj(cmul(kv[m], v[m]));
-        if constexpr (four_step) fft4096_rev(v, sh, sh + n, t >> 6, t & 63, stw);
+        if constexpr (four_step) fft4096_rev(v, sh, sh + n, t >> 6, t & 63, stw, sw64);
         else fft8<LOG2N>(v, sh, ld, par, t, stw);
-        const double inv_n = 1.0 / n;
 #pragma unroll
         for (int m = 0; m < kPts; ++m) {
             const int i = xi + m * q;
-            const double2 o = cmul(ph[m], cscale(cconj(v[m]), inv_n));
+            const double2 o = cmul(ph[m], cconj(v[m]));   // the 1/n of the inverse is in the kinetic table
             p[i] = o;
             // FP32 copy for the mixed form's FP32 contraction
             if (psi_f32) psi_f32[(size_t)cw * n + i] = make_float2((float)o.x, (float)o.y);
@@ -491,7 +495,7 @@ size_t lds_for(int n) {
     const int q = n / kPts;
     const int cpb = threads_for(n) / q;
     const size_t ld = ilog2(n) == kFourStepLog2 ? n : n + n / 8;
-    return sizeof(double2) * ((size_t)q + kErfTableSlots + 2 * ld * cpb);
+    return sizeof(double2) * ((size_t)q + kErfTableSlots + kW64Slots + 2 * ld * cpb);
 }
 }  // namespace
 

@@ -77,6 +77,7 @@ Bufs carve(const icwf_config &c, char *base, size_t *total) {
     b.v_r = L.take<double>(Np);
     b.v_R = L.take<double>(Np);
     b.psi_at = L.take<double2>(Np);
+    b.cphase = L.take<double2>(2 * (size_t)Np);
     b.G1a = L.take<double2>(Np * nr);
     b.G1b = L.take<double2>(Np * nr);
     b.G2a = L.take<double2>(Np * nR);

@@ -46,6 +46,9 @@ struct Bufs {
     double2 *vpart;                       // [Np/16][Np][3] velocity partial sums
     double *v_r, *v_R;                    // [N] velocities
     double2 *psi_at;                      // [N] Psi(r^a, R^a)
+    double2 *cphase;                      // [2][Np] e^{-i V_2(R^a) dt/2}, e^{-i V_1(r^a) dt/2}: the
+                                          // constant part of each CWF's conditioned potential (zero rows
+                                          // past N)
     double2 *G1a, *G1b;                   // [N][nr] W_c(r_i, R^a) psi_1^a_i at x_k, x_k+1
     double2 *G2a, *G2b;                   // [N][nR] W_c(r^a, R_j) psi_2^a_j at x_k, x_k+1
     double2 *S1, *S2;                     // [N][N] single-species overlaps
@@ -78,7 +81,8 @@ void launch_propagate(const Dims &d, const Bufs &b, int species, hipStream_t s);
 int propagate_grid(int n, int N, int ncu);
 
 // Periodic-sinc tables at the current positions, velocity contraction and
-// reduction; writes v_r, v_R, psi_at, r_new, R_new (x + dt v) and the flags.
+// reduction; writes v_r, v_R, psi_at, r_new, R_new (x + dt v), the constant
+// potential phases cphase of the CWFs conditioned on r, R, and the flags.
 void launch_velocity(const Dims &d, const Bufs &b, bool update_positions, hipStream_t s);
 
 // Conditioned kets G = W_c(., x) psi for the two conditionings x_k, x_k+1.

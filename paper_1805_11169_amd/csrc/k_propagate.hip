@@ -25,6 +25,7 @@
 #include <cmath>
 
 #include "icwf_plan.hpp"
+#include "icwf_expi.hpp"
 
 #include "erf_table.inc"
 
@@ -171,7 +172,7 @@ __device__ inline void fft8(double2 (&v)[kPts], double2 *sh, int ld, int &par, i
     }
 }
 
-// ---- n = 4096: four-step transform, two barriers per CWF ---------------------
+// ---- n = 4096: four-step transform, one LDS buffer, four barriers per CWF ----
 //
 // 4096 = 64 x 64 with i = i1 + 64 i2 and k = k2 + 64 k1: a 64-point DFT over
 // i2 for each i1, the twiddle w4096^(i1 k2), a 64-point DFT over i1 for each
@@ -189,11 +190,13 @@ __device__ inline void fft8(double2 (&v)[kPts], double2 *sh, int ld, int &par, i
 // The same stages in reverse order (the DFT matrix and each stage matrix being
 // symmetric, up to the inverse permutations) compute the DFT from the output
 // layout back to the input layout; the inverse transform is that sequence
-// applied to the conjugate.  Buffer use: the forward exchange writes B0 and
-// the reverse one B1; the 8-lane exchanges use the wave's slice of the buffer
-// whose last cross-wave exchange it has already read.  Every cross-wave write
-// into a buffer is separated by a barrier from the last use of that buffer by
-// any wave.
+// applied to the conjugate.  Buffer use: one 4096-slot buffer per CWF, so that
+// two work-groups (sixteen waves) share a compute unit and one group's
+// exchanges and barriers overlap the other's arithmetic.  Wave w's slice is
+// touched by other waves only through the cross-wave writes, and the wave
+// reads in the cross-wave exchange only its own slice; a barrier before each
+// cross-wave write (every wave done with its slice) and the one after it
+// order all accesses.
 
 constexpr int kFourStepLog2 = 12;
 
@@ -236,96 +239,55 @@ __device__ inline void cross_wave(double2 (&v)[kPts], double2 *B, int w, int l) 
 }
 
 // forward, input layout -> output layout
-__device__ inline void fft4096_fwd(double2 (&v)[kPts], double2 *B0, double2 *B1, int w, int l, const double2 *tw,
+__device__ inline void fft4096_fwd(double2 (&v)[kPts], double2 *B, int w, int l, const double2 *tw,
                                    const double2 *w64) {
     const int lo = l & 7, hi = l >> 3;
-    double2 *R0 = B0 + w * 512, *R1 = B1 + w * 512;
+    double2 *R = B + w * 512;
     dft8(v);                                              // over i2's high part
     twiddle_row(v, w64, hi);                              // w64^(a b), a = hi
 #pragma unroll
-    for (int b = 0; b < kPts; ++b) R1[slot_a(lo, hi, b)] = v[b];
+    for (int b = 0; b < kPts; ++b) R[slot_a(lo, hi, b)] = v[b];
     wave_sync();
 #pragma unroll
-    for (int a = 0; a < kPts; ++a) v[a] = R1[slot_a(lo, a, hi)];
+    for (int a = 0; a < kPts; ++a) v[a] = R[slot_a(lo, a, hi)];
     dft8(v);                                              // over i2's low part
     twiddle_middle(v, lo + 8 * w, hi, tw);
-    cross_wave(v, B0, w, l);
+    __syncthreads();                                      // every slice read by its wave
+    cross_wave(v, B, w, l);
     dft8(v);                                              // over i1's high part
     twiddle_row(v, w64, lo);                              // w64^(p e), p = lo
 #pragma unroll
-    for (int e = 0; e < kPts; ++e) R0[slot_c(hi, lo, e)] = v[e];
+    for (int e = 0; e < kPts; ++e) R[slot_c(hi, lo, e)] = v[e];
     wave_sync();
 #pragma unroll
-    for (int p = 0; p < kPts; ++p) v[p] = R0[slot_c(hi, p, lo)];
+    for (int p = 0; p < kPts; ++p) v[p] = R[slot_c(hi, p, lo)];
     dft8(v);                                              // over i1's low part
 }
 
 // the same stages in reverse: output layout -> input layout
-__device__ inline void fft4096_rev(double2 (&v)[kPts], double2 *B0, double2 *B1, int w, int l, const double2 *tw,
+__device__ inline void fft4096_rev(double2 (&v)[kPts], double2 *B, int w, int l, const double2 *tw,
                                    const double2 *w64) {
     const int lo = l & 7, hi = l >> 3;
-    double2 *R0 = B0 + w * 512, *R1 = B1 + w * 512;
+    double2 *R = B + w * 512;
     dft8(v);
 #pragma unroll
-    for (int p = 0; p < kPts; ++p) R0[slot_c(hi, p, lo)] = v[p];
+    for (int p = 0; p < kPts; ++p) R[slot_c(hi, p, lo)] = v[p];
     wave_sync();
 #pragma unroll
-    for (int e = 0; e < kPts; ++e) v[e] = R0[slot_c(hi, lo, e)];
+    for (int e = 0; e < kPts; ++e) v[e] = R[slot_c(hi, lo, e)];
     twiddle_row(v, w64, lo);
     dft8(v);
-    cross_wave(v, B1, w, l);
+    __syncthreads();                                      // every slice read by its wave
+    cross_wave(v, B, w, l);
     twiddle_middle(v, lo + 8 * w, hi, tw);
     dft8(v);
 #pragma unroll
-    for (int a = 0; a < kPts; ++a) R1[slot_a(lo, a, hi)] = v[a];
+    for (int a = 0; a < kPts; ++a) R[slot_a(lo, a, hi)] = v[a];
     wave_sync();
 #pragma unroll
-    for (int b = 0; b < kPts; ++b) v[b] = R1[slot_a(lo, hi, b)];
+    for (int b = 0; b < kPts; ++b) v[b] = R[slot_a(lo, hi, b)];
     twiddle_row(v, w64, hi);
     dft8(v);
-}
-
-// e^{i theta} for |theta| <= pi/4 by the Taylor series of sin and cos in
-// u = theta^2, to degrees 15 and 16: the first dropped terms are below
-// (pi/4)^17/17! = 5e-17 and (pi/4)^18/18! = 2e-18, under half an ulp of
-// the results.  Horner's rule from the highest power.
-__device__ inline double2 expi_small(double th) {
-    const double u = th * th;
-    double s = -1.0 / 1307674368000.0;   // -1/15!
-    s = fma(s, u, 1.0 / 6227020800.0);   // +1/13!
-    s = fma(s, u, -1.0 / 39916800.0);    // -1/11!
-    s = fma(s, u, 1.0 / 362880.0);       // +1/9!
-    s = fma(s, u, -1.0 / 5040.0);        // -1/7!
-    s = fma(s, u, 1.0 / 120.0);          // +1/5!
-    s = fma(s, u, -1.0 / 6.0);           // -1/3!
-    double c = 1.0 / 20922789888000.0;   // +1/16!
-    c = fma(c, u, -1.0 / 87178291200.0); // -1/14!
-    c = fma(c, u, 1.0 / 479001600.0);    // +1/12!
-    c = fma(c, u, -1.0 / 3628800.0);     // -1/10!
-    c = fma(c, u, 1.0 / 40320.0);        // +1/8!
-    c = fma(c, u, -1.0 / 720.0);         // -1/6!
-    c = fma(c, u, 1.0 / 24.0);           // +1/4!
-    c = fma(c, u, -0.5);                 // -1/2!
-    return make_double2(fma(u, c, 1.0), fma(th * u, s, th));
-}
-
-// e^{i theta} for any theta: theta = k pi/2 + r with k = rint(2 theta/pi),
-// r = theta - k pi/2 by the three-term split of pi/2 of Cody and Waite (three
-// doubles whose sum is pi/2 to 160 bits; each product is exact inside its
-// FMA), so |r| <= pi/4 up to rounding; then e^{i theta} = i^k e^{i r}.  The
-// absolute error stays at a few 1e-16 for |theta| < 2^30, far beyond any
-// phase a time step takes.
-__device__ inline double2 expi(double th) {
-    const double k = rint(th * 0.63661977236758134308);
-    double r = fma(-k, 1.5707963267948966, th);      // pi/2 rounded to a double
-    r = fma(-k, 6.123233995736766e-17, r);           // pi/2 minus that, rounded
-    r = fma(-k, -1.4973849048591698e-33, r);         // the remainder, rounded
-    const double2 e = expi_small(r);
-    const double k4 = k - 4.0 * floor(0.25 * k);     // k mod 4
-    // i^k (c + i s): k = 0: (c, s), 1: (-s, c), 2: (-c, -s), 3: (s, -c)
-    const bool odd = k4 == 1.0 || k4 == 3.0;
-    const double a = odd ? e.y : e.x, b = odd ? e.x : e.y;
-    return make_double2((k4 == 1.0 || k4 == 2.0) ? -a : a, k4 >= 2.0 ? -b : b);
 }
 
 // e^{i theta} for |theta| <= 0.05: the Taylor series of sin and cos to
@@ -368,28 +330,35 @@ __device__ inline double erf_over_x_table(double d, double inv_a, const double *
 // n = 2^LOG2N points; blockDim.x = max(64, n/8) threads: n/8 per CWF,
 // cpb = blockDim.x / (n/8) CWFs per work-group; work-group g takes the CWF
 // groups g, g + G, ... of the ngroups = Np / cpb (G = gridDim.x).  LDS: the
-// n/8 twiddles, the erf(z)/z table, the w64^(a b) table, then two (padded)
-// buffers per CWF.
+// n/8 twiddles, the erf(z)/z table, the w64^(a b) table, then per CWF two
+// (padded) buffers, one at n = 4096.  At n = 4096 the kernel is held to 128
+// VGPRs (four waves per SIMD), so that two work-groups fit a compute unit;
+// for that the per-CWF constant phase comes precomputed (cph) rather than
+// from the model's erf, whose constants would stay in registers across the
+// loop, and every global access is a uniform base plus a 32-bit lane offset.
 template <int LOG2N>
-__global__ void __launch_bounds__(512) k_propagate(double2 *__restrict__ psi, int ngroups,
-                                                   const double2 *__restrict__ vphase, double x_min, double h,
-                                                   const double *__restrict__ cond, int species, ModelParams mp,
-                                                   const double2 *__restrict__ kin,
-                                                   const double2 *__restrict__ tw, double dt, int tiny,
-                                                   float2 *__restrict__ psi_f32,
-                                                   const int32_t *__restrict__ flags) {
+__global__ void __launch_bounds__(512, LOG2N == kFourStepLog2 ? 4 : 1)
+    k_propagate(double2 *__restrict__ psi, int ngroups, const double2 *__restrict__ vphase, double x_min, double h,
+                const double *__restrict__ cond, const double2 *__restrict__ cph, int species, ModelParams mp,
+                const double2 *__restrict__ kin, const double2 *__restrict__ tw, double dt, int tiny,
+                float2 *__restrict__ psi_f32, const int32_t *__restrict__ flags) {
     if (flags[kFlagHalt]) return;
     extern __shared__ double2 sh_all[];
     constexpr int n = 1 << LOG2N;
     constexpr int q = n / kPts;
     constexpr int cpb = q < 64 ? 64 / q : 1;
     constexpr bool four_step = LOG2N == kFourStepLog2;
-    constexpr int ld = four_step ? n : n + n / 8;   // one (padded) buffer; two per CWF
+    constexpr int ld = four_step ? n : n + n / 8;   // one (padded) buffer
+    constexpr int nbuf = four_step ? 1 : 2;         // buffers per CWF
+    // points whose potential phases are evaluated together: at 128 VGPRs one
+    // at a time, else two (all eight in flight at once need more registers
+    // than the wave has)
+    constexpr int group = four_step ? 1 : 2;
     const int lc = threadIdx.x / q, t0 = threadIdx.x - lc * q;
     double2 *stw = sh_all;
     double *serf = reinterpret_cast<double *>(sh_all + q);
     double2 *sw64 = sh_all + q + kErfTableSlots;
-    double2 *sh = sh_all + q + kErfTableSlots + kW64Slots + lc * 2 * ld;
+    double2 *sh = sh_all + q + kErfTableSlots + kW64Slots + lc * nbuf * ld;
     for (int j = threadIdx.x; j < q; j += blockDim.x) stw[j] = tw[j];
     if constexpr (LOG2N == kFourStepLog2)
         for (int j = threadIdx.x; j < kW64Slots; j += blockDim.x) sw64[j] = tw[64 * (j >> 3) * (j & 7)];
@@ -402,9 +371,11 @@ __global__ void __launch_bounds__(512) k_propagate(double2 *__restrict__ psi, in
         xi0 = lo + 8 * w + 64 * hi;
         ki0 = hi + 8 * w + 64 * lo;
     }
-    // the conditioning coordinate is read one CWF ahead: the phases of a CWF
-    // cannot start before it arrives
-    double c_next = blockIdx.x < (unsigned)ngroups ? cond[blockIdx.x * cpb + lc] : 0.0;
+    // the conditioning coordinate and the constant phase are read one CWF
+    // ahead: the phases of a CWF cannot start before they arrive
+    const bool any = blockIdx.x < (unsigned)ngroups;
+    double c_next = any ? cond[blockIdx.x * cpb + lc] : 0.0;
+    double2 pc_next = any ? cph[blockIdx.x * cpb + lc] : make_double2(0.0, 0.0);
     __syncthreads();                         // tables in place
     for (int g = blockIdx.x; g < ngroups; g += gridDim.x) {
         // the thread index, opaque to the compiler within each iteration:
@@ -413,18 +384,20 @@ __global__ void __launch_bounds__(512) k_propagate(double2 *__restrict__ psi, in
         // across it, which spills
         int t = t0, xi = xi0, ki = ki0;
         asm volatile("" : "+v"(t), "+v"(xi), "+v"(ki));
+        const unsigned ux = (unsigned)xi, uk = (unsigned)ki;
         const int cw = g * cpb + lc;
         double2 *p = psi + (size_t)cw * n;
         const double c = c_next;
-        if (g + (int)gridDim.x < ngroups) c_next = cond[(g + gridDim.x) * cpb + lc];
+        const double2 pc = pc_next;          // e^{-i V_c dt/2}, V_c the part of the potential constant on the grid
+        if (g + (int)gridDim.x < ngroups) {
+            c_next = cond[(g + gridDim.x) * cpb + lc];
+            pc_next = cph[(g + gridDim.x) * cpb + lc];
+        }
         double2 v[kPts];
 #pragma unroll
-        for (int m = 0; m < kPts; ++m) v[m] = p[xi + m * q];
-        // e^{-i V dt/2} = e^{-i V_s(x) dt/2} (table) x e^{-i V_c dt/2} (the part
-        // of the conditioned potential constant on this CWF's grid) x
+        for (int m = 0; m < kPts; ++m) v[m] = (p + m * q)[ux];
+        // e^{-i V dt/2} = e^{-i V_s(x) dt/2} (table) x e^{-i V_c dt/2} x
         // e^{-i W_c(x) dt/2} (the coupling, evaluated per point)
-        const double vconst = (species == 1) ? model_v2(mp, c) : model_v1(mp, c);
-        const double2 pc = expi(-0.5 * dt * vconst);
         double2 ph[kPts];
         if (mp.kind == 1) {                  // Shin-Metiu: W_c = -g(r - R; R_f), 0 <= g <= 2/(sqrt(pi) R_f)
             const double inv_a = 1.0 / mp.p[1];
@@ -433,18 +406,16 @@ __global__ void __launch_bounds__(512) k_propagate(double2 *__restrict__ psi, in
                 for (int m = 0; m < kPts; ++m) {
                     const double x = x_min + (xi + m * q) * h;
                     const double2 e = expi_tiny(0.5 * dt * erf_over_x_table(x - c, inv_a, serf));
-                    ph[m] = cmul(cmul(vphase[xi + m * q], pc), e);
-                    // two points at a time: all eight in flight at once need
-                    // more registers than the wave has
-                    if (m % 2 == 1) __builtin_amdgcn_sched_barrier(0);
+                    ph[m] = cmul(cmul((vphase + m * q)[ux], pc), e);
+                    if (m % group == group - 1) __builtin_amdgcn_sched_barrier(0);
                 }
             } else {
 #pragma unroll
                 for (int m = 0; m < kPts; ++m) {
                     const double x = x_min + (xi + m * q) * h;
                     const double2 e = expi(0.5 * dt * erf_over_x_table(x - c, inv_a, serf));
-                    ph[m] = cmul(cmul(vphase[xi + m * q], pc), e);
-                    if (m % 2 == 1) __builtin_amdgcn_sched_barrier(0);
+                    ph[m] = cmul(cmul((vphase + m * q)[ux], pc), e);
+                    if (m % group == group - 1) __builtin_amdgcn_sched_barrier(0);
                 }
             }
         } else {
@@ -452,28 +423,35 @@ __global__ void __launch_bounds__(512) k_propagate(double2 *__restrict__ psi, in
             for (int m = 0; m < kPts; ++m) {
                 const double x = x_min + (xi + m * q) * h;
                 const double wcv = (species == 1) ? model_wc(mp, x, c) : model_wc(mp, c, x);
-                ph[m] = cmul(cmul(vphase[xi + m * q], pc), expi(-0.5 * dt * wcv));
-                if (m % 2 == 1) __builtin_amdgcn_sched_barrier(0);
+                ph[m] = cmul(cmul((vphase + m * q)[ux], pc), expi(-0.5 * dt * wcv));
+                if (m % group == group - 1) __builtin_amdgcn_sched_barrier(0);
             }
         }
 #pragma unroll
         for (int m = 0; m < kPts; ++m) v[m] = cmul(ph[m], v[m]);
+        // the kinetic phases: ahead of the forward transform where registers
+        // allow, after it at 128 VGPRs
         double2 kv[kPts];
+        if constexpr (!four_step) {
 #pragma unroll
-        for (int m = 0; m < kPts; ++m) kv[m] = kin[ki + m * q];
-        if constexpr (four_step) fft4096_fwd(v, sh, sh + n, t >> 6, t & 63, stw, sw64);
-        else fft8<LOG2N>(v, sh, ld, par, t, stw);
+            for (int m = 0; m < kPts; ++m) kv[m] = (kin + m * q)[uk];
+            fft8<LOG2N>(v, sh, ld, par, t, stw);
+        } else {
+            fft4096_fwd(v, sh, t >> 6, t & 63, stw, sw64);
+#pragma unroll
+            for (int m = 0; m < kPts; ++m) kv[m] = (kin + m * q)[uk];
+        }
 #pragma unroll
         for (int m = 0; m < kPts; ++m) v[m] = cconj(cmul(kv[m], v[m]));
-        if constexpr (four_step) fft4096_rev(v, sh, sh + n, t >> 6, t & 63, stw, sw64);
+        if constexpr (four_step) fft4096_rev(v, sh, t >> 6, t & 63, stw, sw64);
         else fft8<LOG2N>(v, sh, ld, par, t, stw);
+        float2 *pf = psi_f32 ? psi_f32 + (size_t)cw * n : nullptr;
 #pragma unroll
         for (int m = 0; m < kPts; ++m) {
-            const int i = xi + m * q;
             const double2 o = cmul(ph[m], cconj(v[m]));   // the 1/n of the inverse is in the kinetic table
-            p[i] = o;
+            (p + m * q)[ux] = o;
             // FP32 copy for the mixed form's FP32 contraction
-            if (psi_f32) psi_f32[(size_t)cw * n + i] = make_float2((float)o.x, (float)o.y);
+            if (pf) (pf + m * q)[ux] = make_float2((float)o.x, (float)o.y);
         }
     }
 }
@@ -495,14 +473,15 @@ size_t lds_for(int n) {
     const int q = n / kPts;
     const int cpb = threads_for(n) / q;
     const size_t ld = ilog2(n) == kFourStepLog2 ? n : n + n / 8;
-    return sizeof(double2) * ((size_t)q + kErfTableSlots + kW64Slots + 2 * ld * cpb);
+    const size_t nbuf = ilog2(n) == kFourStepLog2 ? 1 : 2;
+    return sizeof(double2) * ((size_t)q + kErfTableSlots + kW64Slots + nbuf * ld * cpb);
 }
 }  // namespace
 
 namespace {
 // The instantiation for n = 2^l, 32 <= n <= 4096.
-using PropKernel = void (*)(double2 *, int, const double2 *, double, double, const double *, int, ModelParams,
-                            const double2 *, const double2 *, double, int, float2 *, const int32_t *);
+using PropKernel = void (*)(double2 *, int, const double2 *, double, double, const double *, const double2 *, int,
+                            ModelParams, const double2 *, const double2 *, double, int, float2 *, const int32_t *);
 PropKernel kernel_for(int n) {
     switch (ilog2(n)) {
     case 5: return k_propagate<5>;
@@ -539,11 +518,11 @@ void launch_propagate(const Dims &d, const Bufs &b, int species, hipStream_t s) 
     // the Shin-Metiu coupling phase stays within the short series' range
     const int tiny = d.mp.kind == 1 && 0.5 * std::fabs(d.dt) * 2.0 / (std::sqrt(M_PI) * d.mp.p[1]) <= kTinyPhase;
     if (species == 1) {
-        hipLaunchKernelGGL(k, dim3(grid), dim3(T), lds, s, b.psi1, ngroups, b.vphase_r, d.r_min, d.hr, b.R, 1, d.mp,
-                           b.kin_r, b.tw_r, d.dt, tiny, d.prec == 1 ? b.psi1_f32 : nullptr, b.flags);
+        hipLaunchKernelGGL(k, dim3(grid), dim3(T), lds, s, b.psi1, ngroups, b.vphase_r, d.r_min, d.hr, b.R, b.cphase,
+                           1, d.mp, b.kin_r, b.tw_r, d.dt, tiny, d.prec == 1 ? b.psi1_f32 : nullptr, b.flags);
     } else {
-        hipLaunchKernelGGL(k, dim3(grid), dim3(T), lds, s, b.psi2, ngroups, b.vphase_R, d.R_min, d.hR, b.r, 2, d.mp,
-                           b.kin_R, b.tw_R, d.dt, tiny, nullptr, b.flags);
+        hipLaunchKernelGGL(k, dim3(grid), dim3(T), lds, s, b.psi2, ngroups, b.vphase_R, d.R_min, d.hR, b.r,
+                           b.cphase + padded(d.N), 2, d.mp, b.kin_R, b.tw_R, d.dt, tiny, nullptr, b.flags);
     }
 }
 

@@ -16,8 +16,10 @@
 //        A1 = S_r psi1^T, D1 = S'_r psi1^T, A2 = S_R psi2^T, D2 = S'_R psi2^T
 //    on FP64 matrix cores (v_mfma_f64_16x16x4), one 16 x 16 (a, b) tile per
 //    wave, followed in registers by the b-sums with C over the tile.
-// 3. k_vel_finish: sums the tile partials, forms v, updates x, raises flags.
+// 3. k_vel_finish: sums the tile partials, forms v, updates x, raises flags,
+//    and writes the per-CWF constant potential phases the propagation uses.
 #include "icwf_plan.hpp"
+#include "icwf_expi.hpp"
 
 namespace icwf {
 
@@ -171,10 +173,17 @@ __global__ void k_vel_finish(const double2 *__restrict__ part, int N, int Np, do
                              const double *__restrict__ r, const double *__restrict__ R, double *__restrict__ r_new,
                              double *__restrict__ R_new, double *__restrict__ v_r, double *__restrict__ v_R,
                              double2 *__restrict__ psi_at, double r_lo, double r_hi, double R_lo, double R_hi,
-                             int update, int32_t *__restrict__ flags, unsigned long long *__restrict__ min_bits) {
+                             ModelParams mp, double2 *__restrict__ cphase, int update, int32_t *__restrict__ flags,
+                             unsigned long long *__restrict__ min_bits) {
     if (flags[kFlagHalt]) return;
     const int a = blockIdx.x * blockDim.x + threadIdx.x;
     if (a >= N) return;
+    // the phases e^{-i V dt/2} of the one-coordinate potential part that is
+    // constant on the grid of each CWF conditioned on this trajectory (V_2 at
+    // R^a for the electronic CWF, V_1 at r^a for the nuclear one), at the
+    // positions the propagation of this step conditions on
+    cphase[a] = expi(-0.5 * dt * model_v2(mp, R[a]));
+    cphase[Np + a] = expi(-0.5 * dt * model_v1(mp, r[a]));
     const int ntile = Np >> 4;
     double2 ps = make_double2(0, 0), nr = make_double2(0, 0), nR = make_double2(0, 0);
     for (int t = 0; t < ntile; ++t) {
@@ -231,8 +240,8 @@ void launch_velocity(const Dims &d, const Bufs &b, bool update, hipStream_t s) {
     hipLaunchKernelGGL(k_vel_reset, dim3(1), dim3(64), 0, s, b.flags, min_bits);
     const double r_hi = d.r_min + d.hr * d.nr, R_hi = d.R_min + d.hR * d.nR;
     hipLaunchKernelGGL(k_vel_finish, dim3((d.N + 255) / 256), dim3(256), 0, s, b.vpart, d.N, Np, d.m_r, d.m_R,
-                       d.dt, b.r, b.R, b.r_new, b.R_new, b.v_r, b.v_R, b.psi_at, d.r_min, r_hi, d.R_min, R_hi,
-                       update ? 1 : 0, b.flags, min_bits);
+                       d.dt, b.r, b.R, b.r_new, b.R_new, b.v_r, b.v_R, b.psi_at, d.r_min, r_hi, d.R_min, R_hi, d.mp,
+                       b.cphase, update ? 1 : 0, b.flags, min_bits);
 }
 
 }  // namespace icwf

@@ -327,6 +327,18 @@ __device__ inline double erf_over_x_table(double d, double inv_a, const double *
     return z < 6.0 ? e * inv_a : r;
 }
 
+// Read-only data in the constant address space: with a wave-uniform index the
+// loads become scalar loads into SGPRs.
+typedef const __attribute__((address_space(4))) double *ConstDouble;
+
+// x, known to be equal on all lanes, moved to SGPRs
+__device__ inline double wave_uniform(double x) {
+    const long long b = __double_as_longlong(x);
+    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)b);
+    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(b >> 32));
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
 // n = 2^LOG2N points; blockDim.x = max(64, n/8) threads: n/8 per CWF,
 // cpb = blockDim.x / (n/8) CWFs per work-group; work-group g takes the CWF
 // groups g, g + G, ... of the ngroups = Np / cpb (G = gridDim.x).  LDS: the
@@ -372,10 +384,22 @@ __global__ void __launch_bounds__(512, LOG2N == kFourStepLog2 ? 4 : 1)
         ki0 = hi + 8 * w + 64 * lo;
     }
     // the conditioning coordinate and the constant phase are read one CWF
-    // ahead: the phases of a CWF cannot start before they arrive
-    const bool any = blockIdx.x < (unsigned)ngroups;
-    double c_next = any ? cond[blockIdx.x * cpb + lc] : 0.0;
-    double2 pc_next = any ? cph[blockIdx.x * cpb + lc] : make_double2(0.0, 0.0);
+    // ahead: the phases of a CWF cannot start before they arrive.  With one
+    // CWF per work-group they are uniform: scalar loads, held in SGPRs.
+    double c_next = 0.0;
+    double2 pc_next = make_double2(0.0, 0.0);
+    auto fetch = [&](int gn) {
+        if constexpr (cpb == 1) {
+            c_next = ((ConstDouble)cond)[gn];
+            const ConstDouble pp = (ConstDouble)cph;
+            pc_next = make_double2(pp[2 * gn], pp[2 * gn + 1]);
+        } else {
+            c_next = cond[gn * cpb + lc];
+            pc_next = cph[gn * cpb + lc];
+        }
+    };
+    if (blockIdx.x < (unsigned)ngroups) fetch(blockIdx.x);
+    const double inv_a = wave_uniform(1.0 / mp.p[1]);   // Shin-Metiu: 1/R_f
     __syncthreads();                         // tables in place
     for (int g = blockIdx.x; g < ngroups; g += gridDim.x) {
         // the thread index, opaque to the compiler within each iteration:
@@ -389,10 +413,7 @@ __global__ void __launch_bounds__(512, LOG2N == kFourStepLog2 ? 4 : 1)
         double2 *p = psi + (size_t)cw * n;
         const double c = c_next;
         const double2 pc = pc_next;          // e^{-i V_c dt/2}, V_c the part of the potential constant on the grid
-        if (g + (int)gridDim.x < ngroups) {
-            c_next = cond[(g + gridDim.x) * cpb + lc];
-            pc_next = cph[(g + gridDim.x) * cpb + lc];
-        }
+        if (g + (int)gridDim.x < ngroups) fetch(g + gridDim.x);
         double2 v[kPts];
 #pragma unroll
         for (int m = 0; m < kPts; ++m) v[m] = (p + m * q)[ux];
@@ -400,7 +421,6 @@ __global__ void __launch_bounds__(512, LOG2N == kFourStepLog2 ? 4 : 1)
         // e^{-i W_c(x) dt/2} (the coupling, evaluated per point)
         double2 ph[kPts];
         if (mp.kind == 1) {                  // Shin-Metiu: W_c = -g(r - R; R_f), 0 <= g <= 2/(sqrt(pi) R_f)
-            const double inv_a = 1.0 / mp.p[1];
             if (tiny) {                      // dt/(sqrt(pi) R_f) <= kTinyPhase
 #pragma unroll
                 for (int m = 0; m < kPts; ++m) {

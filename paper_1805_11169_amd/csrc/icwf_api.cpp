@@ -73,7 +73,7 @@ Bufs carve(const icwf_config &c, char *base, size_t *total) {
     b.dsinc_r = L.take<double>(Np * nr);
     b.sinc_R = L.take<double>(Np * nR);
     b.dsinc_R = L.take<double>(Np * nR);
-    b.vpart = L.take<double2>((Np / 16) * Np * 3);
+    b.vpart = L.take<double2>((Np / 32) * Np * 3);
     b.v_r = L.take<double>(Np);
     b.v_R = L.take<double>(Np);
     b.psi_at = L.take<double2>(Np);

@@ -43,7 +43,7 @@ struct Bufs {
     float2 *psi1_f32;                     // [Np][nr] FP32 copy of psi1 (mixed form only)
     double *sinc_r, *dsinc_r;             // [N][nr] periodic sinc and derivative at r^a
     double *sinc_R, *dsinc_R;             // [N][nR]
-    double2 *vpart;                       // [Np/16][Np][3] velocity partial sums
+    double2 *vpart;                       // [Np/32][Np][3] velocity partial sums
     double *v_r, *v_R;                    // [N] velocities
     double2 *psi_at;                      // [N] Psi(r^a, R^a)
     double2 *cphase;                      // [2][Np] e^{-i V_2(R^a) dt/2}, e^{-i V_1(r^a) dt/2}: the

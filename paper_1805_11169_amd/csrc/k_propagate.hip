@@ -315,15 +315,18 @@ __device__ inline double2 expi_tiny(double th) {
 __device__ inline double erf_over_x_table(double d, double inv_a, const double *tab) {
     const double ax = fabs(d);
     const double z = ax * inv_a;
+    double r = __builtin_amdgcn_rcp(ax);
+    r = fma(fma(-ax, r, 1.0), r, r);
+    r = fma(fma(-ax, r, 1.0), r, r);
+    // the table only where some lane of the wave needs it (on a wide grid
+    // about half of the point groups lie beyond z = 6 for every lane)
+    if (__builtin_amdgcn_ballot_w64(z < 6.0) == 0) return r;
     const int j = (int)fmin(z * 4.0, (double)(kErfPieces - 1));
     const double s = z - (j + 0.5) * 0.25;
     const double *cf = tab + j * kErfTerms;
     double e = cf[kErfTerms - 1];
 #pragma unroll
     for (int k = kErfTerms - 2; k >= 0; --k) e = fma(e, s, cf[k]);
-    double r = __builtin_amdgcn_rcp(ax);
-    r = fma(fma(-ax, r, 1.0), r, r);
-    r = fma(fma(-ax, r, 1.0), r, r);
     return z < 6.0 ? e * inv_a : r;
 }
 

@@ -11,10 +11,11 @@
 // the regularised matrices handed to the factorisation.
 //
 // Cholesky (lower, in place, two matrices per launch): right-looking with
-// 64-wide panels.  k_chol_panel factors the 64 x 64 diagonal block with the
-// block's rows held in registers (thread = one row quarter, the pivot column
-// broadcast through LDS), then solves 64 rows of the panel, x L11^H = a, per
-// work-group (the solved column broadcast within each row's four lanes).
+// 64-wide panels.  Each k_chol_panel work-group eliminates, column by column,
+// the 128 x 64 slab of the diagonal block and 64 of the rows below it, held
+// in registers (lane = column, wave = 8 rows; the pivot column through LDS,
+// one barrier per column); every work-group factors the diagonal block
+// itself, so the panel needs no communication between work-groups.
 // k_chol_update subtracts L21 L21^H from the trailing lower triangle on FP64
 // matrix cores.  A pivot that is not positive raises the solve flag.
 //
@@ -111,12 +112,14 @@ __device__ inline double bcast(double v, int src) {
 
 // The panel: the 64 x 64 diagonal block stacked on this work-group's 64 rows
 // below it (a 128 x 64 slab), eliminated column by column (right-looking):
-// step j takes the pivot d = sqrt(a_jj), scales column j below it by 1/d and
-// subtracts l_rj conj(l_cj) = a_rj conj(a_cj) / d^2 from every later column c.
-// On the diagonal rows this is the Cholesky factor L11; on the rows below it
-// is x L11^H = a.
-// 512 threads: wave g owns slab rows 16 g .. 16 g + 15 (g < 4: diagonal-block
-// rows; g >= 4: 16 of the rows below), lane c owns column c; 16 entries per
+// step j takes the pivot d = sqrt(a_jj) and subtracts
+// l_rj conj(l_cj) = a_rj conj(a_cj) / d^2 from every later column c; column j
+// below the pivot is scaled by 1/d once, after the last step (its entries do
+// not change after step j, and the updates use the unscaled values).  On the
+// diagonal rows this is the Cholesky factor L11; on the rows below it is
+// x L11^H = a.
+// 1024 threads: wave g owns slab rows 8 g .. 8 g + 7 (g < 8: diagonal-block
+// rows; g >= 8: 8 of the rows below), lane c owns column c; 8 entries per
 // thread in registers with static indices.  At step j a wave takes its rows'
 // column-j entries from lane j by readlane; the column-j entries of the
 // diagonal rows (the pivot and every lane's a_cj) come through LDS, written by
@@ -129,31 +132,38 @@ __device__ inline double bcast(double v, int src) {
 // work-groups of the same launch may still be reading the unfactored block.
 // Work-group 0 of the next launch (or k_chol_flush after the last panel) copies
 // it into place.
-__global__ void __launch_bounds__(512) k_chol_panel(double2 *A0, double2 *A1, int Np, int kb,
-                                                    double2 *__restrict__ diag, int32_t *__restrict__ flags) {
+constexpr int kPanelRows = 8;                   // slab rows per wave
+constexpr int kPanelThreads = 64 * 2 * NB / kPanelRows;
+constexpr int kPanelDiagWaves = NB / kPanelRows;
+
+__global__ void __launch_bounds__(kPanelThreads) k_chol_panel(double2 *A0, double2 *A1, int Np, int kb,
+                                                              double2 *__restrict__ diag,
+                                                              int32_t *__restrict__ flags) {
     if (flags[kFlagHalt]) return;
     __shared__ double2 lcol[2][NB];      // column j over the diagonal rows, unscaled, alternating with j
-    __shared__ double dpiv[NB];
+    __shared__ double dpiv[NB], dinvs[NB];
     double2 *A = blockIdx.y ? A1 : A0;
     double2 *D = diag + (size_t)blockIdx.y * NB * NB;
     const int t = threadIdx.x, c = t & 63, g = t >> 6;
     if (blockIdx.x == 0 && kb > 0) {
         const int pb = kb - NB;
-        for (int e = t; e < NB * NB; e += 512) {
+        for (int e = t; e < NB * NB; e += kPanelThreads) {
             const int rr = e / NB, cc = e % NB;
             if (cc <= rr) A[(size_t)(pb + rr) * Np + pb + cc] = D[e];
         }
     }
     const bool below = kb + NB < Np;
-    const bool mine = g < 4 || below;                 // rows below exist for this wave
-    const int srow = 16 * g;                          // first slab row of this wave
-    const int grow = g < 4 ? kb + srow : kb + NB + blockIdx.x * NB + 16 * (g - 4);
-    double2 a[16];
+    const bool diagw = g < kPanelDiagWaves;
+    const bool mine = diagw || below;                 // rows below exist for this wave
+    const int srow = kPanelRows * g;                  // first slab row of this wave
+    const int grow = diagw ? kb + srow : kb + NB + blockIdx.x * NB + kPanelRows * (g - kPanelDiagWaves);
+    double2 a[kPanelRows];
 #pragma unroll
-    for (int v = 0; v < 16; ++v) a[v] = mine ? A[(size_t)(grow + v) * Np + kb + c] : make_double2(0.0, 0.0);
-    if (c == 0 && g < 4) {
+    for (int v = 0; v < kPanelRows; ++v)
+        a[v] = mine ? A[(size_t)(grow + v) * Np + kb + c] : make_double2(0.0, 0.0);
+    if (c == 0 && diagw) {
 #pragma unroll
-        for (int v = 0; v < 16; ++v) lcol[0][srow + v] = a[v];
+        for (int v = 0; v < kPanelRows; ++v) lcol[0][srow + v] = a[v];
     }
     __syncthreads();
     bool bad = false;
@@ -162,9 +172,9 @@ __global__ void __launch_bounds__(512) k_chol_panel(double2 *A0, double2 *A1, in
         const double2 *lj = lcol[j & 1];
         double piv = lj[j].x;
         const double2 lcj = lj[c];
-        double2 lr[16];
+        double2 lr[kPanelRows];
 #pragma unroll
-        for (int v = 0; v < 16; ++v) lr[v] = make_double2(bcast(a[v].x, j), bcast(a[v].y, j));
+        for (int v = 0; v < kPanelRows; ++v) lr[v] = make_double2(bcast(a[v].x, j), bcast(a[v].y, j));
         if (!(piv > 0.0)) {
             bad = true;
             piv = 1.0;
@@ -173,24 +183,26 @@ __global__ void __launch_bounds__(512) k_chol_panel(double2 *A0, double2 *A1, in
         if (c > j) {
             const double2 lc = cscale(cconj(lcj), dinv * dinv);
 #pragma unroll
-            for (int v = 0; v < 16; ++v) a[v] = csub(a[v], cmul(lr[v], lc));
-            if (c == j + 1 && g < 4) {
+            for (int v = 0; v < kPanelRows; ++v) a[v] = csub(a[v], cmul(lr[v], lc));
+            if (c == j + 1 && diagw) {
                 double2 *ln = lcol[(j + 1) & 1];
 #pragma unroll
-                for (int v = 0; v < 16; ++v) ln[srow + v] = a[v];
+                for (int v = 0; v < kPanelRows; ++v) ln[srow + v] = a[v];
             }
-        } else if (c == j) {
-#pragma unroll
-            for (int v = 0; v < 16; ++v) a[v] = cscale(a[v], dinv);
-            if (t == j) dpiv[j] = d;
+        } else if (t == j) {
+            dpiv[j] = d;
+            dinvs[j] = dinv;
         }
         __syncthreads();
     }
     if (bad && t == 0 && blockIdx.x == 0) raise_solve(flags);
-    if (g < 4) {
+    const double sc = dinvs[c];
+#pragma unroll
+    for (int v = 0; v < kPanelRows; ++v) a[v] = cscale(a[v], sc);
+    if (diagw) {
         if (blockIdx.x == 0) {
 #pragma unroll
-            for (int v = 0; v < 16; ++v) {
+            for (int v = 0; v < kPanelRows; ++v) {
                 const int r = srow + v;
                 if (r > c) D[r * NB + c] = a[v];
                 else if (r == c) D[r * NB + c] = make_double2(dpiv[c], 0.0);
@@ -198,7 +210,7 @@ __global__ void __launch_bounds__(512) k_chol_panel(double2 *A0, double2 *A1, in
         }
     } else if (below) {
 #pragma unroll
-        for (int v = 0; v < 16; ++v) A[(size_t)(grow + v) * Np + kb + c] = a[v];
+        for (int v = 0; v < kPanelRows; ++v) A[(size_t)(grow + v) * Np + kb + c] = a[v];
     }
 }
 
@@ -597,7 +609,8 @@ void launch_cholesky(const Dims &d, const Bufs &b, double2 *A0, double2 *A1, dou
     for (int kb = 0; kb < Np; kb += NB) {
         const int below = Np - kb - NB;
         const int gx = below > 0 ? below / 64 : 1;
-        hipLaunchKernelGGL(k_chol_panel, dim3(gx, count), dim3(512), 0, s, A0, A1, Np, kb, b.chol_diag, b.flags);
+        hipLaunchKernelGGL(k_chol_panel, dim3(gx, count), dim3(kPanelThreads), 0, s, A0, A1, Np, kb, b.chol_diag,
+                           b.flags);
         if (below > 0) {
             const int mt = below / 32;
             hipLaunchKernelGGL(k_chol_update, dim3(mt * (mt + 1) / 2, count), dim3(64), 0, s, A0, A1, Np, kb,

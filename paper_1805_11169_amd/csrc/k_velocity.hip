@@ -14,8 +14,8 @@
 //    constant vanish), which removes the cancellation of the closed form there.
 // 2. k_vel_gemm: the four real x complex contractions
 //        A1 = S_r psi1^T, D1 = S'_r psi1^T, A2 = S_R psi2^T, D2 = S'_R psi2^T
-//    on FP64 matrix cores (v_mfma_f64_16x16x4), one 16 x 16 (a, b) tile per
-//    wave, followed in registers by the b-sums with C over the tile.
+//    on FP64 matrix cores (v_mfma_f64_16x16x4), 64 (a) x 32 (b) tiles staged
+//    through LDS, followed in registers by the b-sums with C over the tile.
 // 3. k_vel_finish: sums the tile partials, forms v, updates x, raises flags,
 //    and writes the per-CWF constant potential phases the propagation uses.
 #include "icwf_plan.hpp"
@@ -77,10 +77,106 @@ __global__ void k_sinc(const double *__restrict__ pos, int Np, int n, double x_m
     if (tid == 0) Dprow[near] = -red[0];
 }
 
-// One wave per 16 (a) x 16 (b) tile; block = 4 waves = 32 x 32.  Lane l holds
-// A = table[a0 + l%16][k], B = psi[b0 + l%16][k] with the k range split in
-// four contiguous quarters by l/16.  Accumulator layout: lane l, register v
-// holds D[mfma_row_f64(l, v)][l%16].
+// Work-group of 4 waves per 64 (a) x 32 (b) tile, wave w on the rows
+// a0 + 16 w .. + 15 against all 32 columns (two MFMA fragments, rows = a,
+// columns = b, k the grid index).  Lane l supplies A = table[a][k] and
+// B = psi[b][k] with a, b = l % 16 of the fragment and k = l / 16 of the k
+// step.  The 64 table rows (S and S') and the 32 psi rows of a 16-wide k
+// chunk are staged in LDS by coalesced loads (two buffers: the loads of chunk
+// c + 1 are in flight while the matrix cores work on chunk c); species r's
+// chunks come first, then species R's, into their own accumulators.  The
+// epilogue forms the three products with C_b and sums them over the tile's
+// 32 columns (registers, then 16-lane shuffles).
+constexpr int kVA = 64, kVB = 32, kVKC = 16, kVLD = kVKC + 1;
+
+struct VelStage {
+    double S[2][kVA][kVLD];
+    double D[2][kVA][kVLD];
+    double2 P[2][kVB][kVLD];
+};
+
+// acc[0..3][g] += (S, S') x (Re, Im) psi over the k range of one species
+__device__ __forceinline__ void vel_species(const double *__restrict__ Sg, const double *__restrict__ Dg,
+                                   const double2 *__restrict__ Pg, int K, int a0, int b0, VelStage &st,
+                                   dbl4 (&acc)[4][2]) {
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int row = lane & 15, quarter = lane >> 4;
+    // staging: table element e = t + 256 m (m < 4) is row e / 16, k e % 16;
+    // psi element e = t + 256 m (m < 2) likewise
+    const int srow = t >> 4, sk = t & 15;
+    const double *sp = Sg + (size_t)(a0 + srow) * K + sk;
+    const double *dp = Dg + (size_t)(a0 + srow) * K + sk;
+    const double2 *pp = Pg + (size_t)(b0 + srow) * K + sk;
+    const size_t rs = (size_t)16 * K;
+    // staged values held as plain doubles (an array of double2 would be
+    // placed in scratch memory)
+    double rsv[4], rdv[4], rpx[2], rpy[2];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        rsv[m] = sp[m * rs];
+        rdv[m] = dp[m * rs];
+    }
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+        const double2 p = pp[m * rs];
+        rpx[m] = p.x;
+        rpy[m] = p.y;
+    }
+    __syncthreads();                         // the previous user of the buffers is done
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        st.S[0][srow + 16 * m][sk] = rsv[m];
+        st.D[0][srow + 16 * m][sk] = rdv[m];
+    }
+#pragma unroll
+    for (int m = 0; m < 2; ++m) st.P[0][srow + 16 * m][sk] = make_double2(rpx[m], rpy[m]);
+    __syncthreads();
+    const int nch = K / kVKC;
+    for (int ch = 0; ch < nch; ++ch) {
+        const int buf = ch & 1;
+        const bool more = ch + 1 < nch;
+        if (more) {
+            const int k0 = (ch + 1) * kVKC;
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                rsv[m] = sp[m * rs + k0];
+                rdv[m] = dp[m * rs + k0];
+            }
+#pragma unroll
+            for (int m = 0; m < 2; ++m) {
+                const double2 p = pp[m * rs + k0];
+                rpx[m] = p.x;
+                rpy[m] = p.y;
+            }
+        }
+#pragma unroll
+        for (int s4 = 0; s4 < kVKC / 4; ++s4) {
+            const int kk = 4 * s4 + quarter;
+            const double sv = st.S[buf][16 * wave + row][kk];
+            const double dv = st.D[buf][16 * wave + row][kk];
+#pragma unroll
+            for (int g = 0; g < 2; ++g) {
+                const double2 pv = st.P[buf][16 * g + row][kk];
+                acc[0][g] = mfma_f64(sv, pv.x, acc[0][g]);
+                acc[1][g] = mfma_f64(sv, pv.y, acc[1][g]);
+                acc[2][g] = mfma_f64(dv, pv.x, acc[2][g]);
+                acc[3][g] = mfma_f64(dv, pv.y, acc[3][g]);
+            }
+        }
+        if (more) {
+            const int nb = buf ^ 1;
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                st.S[nb][srow + 16 * m][sk] = rsv[m];
+                st.D[nb][srow + 16 * m][sk] = rdv[m];
+            }
+#pragma unroll
+            for (int m = 0; m < 2; ++m) st.P[nb][srow + 16 * m][sk] = make_double2(rpx[m], rpy[m]);
+        }
+        __syncthreads();
+    }
+}
+
 __global__ void __launch_bounds__(256) k_vel_gemm(const double *__restrict__ Sr, const double *__restrict__ Dr,
                                                   const double2 *__restrict__ psi1, int nr,
                                                   const double *__restrict__ SR, const double *__restrict__ DR,
@@ -88,66 +184,40 @@ __global__ void __launch_bounds__(256) k_vel_gemm(const double *__restrict__ Sr,
                                                   const double2 *__restrict__ C, int Np,
                                                   double2 *__restrict__ part, const int32_t *__restrict__ flags) {
     if (flags[kFlagHalt]) return;
-    const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
-    const int a0 = blockIdx.x * 32 + 16 * (wave >> 1);
-    const int b0 = blockIdx.y * 32 + 16 * (wave & 1);
+    __shared__ VelStage st;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int row = lane & 15;
-    const int quarter = lane >> 4;
-
-    dbl4 ar = {0, 0, 0, 0}, ai = {0, 0, 0, 0}, dr = {0, 0, 0, 0}, di = {0, 0, 0, 0};
-    {
-        const int q = nr >> 2;
-        const double *ta = Sr + (size_t)(a0 + row) * nr + quarter * q;
-        const double *td = Dr + (size_t)(a0 + row) * nr + quarter * q;
-        const double2 *pb = psi1 + (size_t)(b0 + row) * nr + quarter * q;
-        for (int s = 0; s < q; s += 2) {
-            const double2 t = *reinterpret_cast<const double2 *>(ta + s);
-            const double2 dd = *reinterpret_cast<const double2 *>(td + s);
-            const double2 p0 = pb[s], p1 = pb[s + 1];
-            ar = mfma_f64(t.x, p0.x, ar);
-            ai = mfma_f64(t.x, p0.y, ai);
-            dr = mfma_f64(dd.x, p0.x, dr);
-            di = mfma_f64(dd.x, p0.y, di);
-            ar = mfma_f64(t.y, p1.x, ar);
-            ai = mfma_f64(t.y, p1.y, ai);
-            dr = mfma_f64(dd.y, p1.x, dr);
-            di = mfma_f64(dd.y, p1.y, di);
+    const int a0 = blockIdx.x * kVA, b0 = blockIdx.y * kVB;
+    // [0] S psi.re, [1] S psi.im, [2] S' psi.re, [3] S' psi.im per column fragment
+    dbl4 x1[4][2], x2[4][2];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int g = 0; g < 2; ++g) {
+            x1[i][g] = dbl4{0, 0, 0, 0};
+            x2[i][g] = dbl4{0, 0, 0, 0};
         }
-    }
-    dbl4 br = {0, 0, 0, 0}, bi = {0, 0, 0, 0}, er = {0, 0, 0, 0}, ei = {0, 0, 0, 0};
-    {
-        const int q = nR >> 2;
-        const double *ta = SR + (size_t)(a0 + row) * nR + quarter * q;
-        const double *td = DR + (size_t)(a0 + row) * nR + quarter * q;
-        const double2 *pb = psi2 + (size_t)(b0 + row) * nR + quarter * q;
-        for (int s = 0; s < q; s += 2) {
-            const double2 t = *reinterpret_cast<const double2 *>(ta + s);
-            const double2 dd = *reinterpret_cast<const double2 *>(td + s);
-            const double2 p0 = pb[s], p1 = pb[s + 1];
-            br = mfma_f64(t.x, p0.x, br);
-            bi = mfma_f64(t.x, p0.y, bi);
-            er = mfma_f64(dd.x, p0.x, er);
-            ei = mfma_f64(dd.x, p0.y, ei);
-            br = mfma_f64(t.y, p1.x, br);
-            bi = mfma_f64(t.y, p1.y, bi);
-            er = mfma_f64(dd.y, p1.x, er);
-            ei = mfma_f64(dd.y, p1.y, ei);
-        }
-    }
-    // epilogue: this lane holds column b = b0 + row, rows a = a0 + mfma_row_f64(lane, v)
-    const double2 cb = C[b0 + row];
+    vel_species(Sr, Dr, psi1, nr, a0, b0, st, x1);
+    vel_species(SR, DR, psi2, nR, a0, b0, st, x2);
+    // epilogue: this lane holds columns b = b0 + 16 g + row, rows
+    // a = a0 + 16 wave + mfma_row_f64(lane, v)
+    const double2 cb0 = C[b0 + row], cb1 = C[b0 + 16 + row];
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-        const double2 A1 = make_double2(ar[v], ai[v]);
-        const double2 D1 = make_double2(dr[v], di[v]);
-        const double2 A2 = make_double2(br[v], bi[v]);
-        const double2 D2 = make_double2(er[v], ei[v]);
-        const double2 cA2 = cmul(cb, A2);
-        double2 pPsi = cmul(cA2, A1);
-        double2 pr = cmul(cA2, D1);
-        double2 pR = cmul(cmul(cb, A1), D2);
-        // sum over the 16 columns b held by lanes 16 quarter .. 16 quarter + 15
+        double2 pPsi = make_double2(0.0, 0.0), pr = pPsi, pR = pPsi;
+#pragma unroll
+        for (int g = 0; g < 2; ++g) {
+            const double2 A1 = make_double2(x1[0][g][v], x1[1][g][v]);
+            const double2 D1 = make_double2(x1[2][g][v], x1[3][g][v]);
+            const double2 A2 = make_double2(x2[0][g][v], x2[1][g][v]);
+            const double2 D2 = make_double2(x2[2][g][v], x2[3][g][v]);
+            const double2 cb = g ? cb1 : cb0;
+            const double2 cA2 = cmul(cb, A2);
+            pPsi = cadd(pPsi, cmul(cA2, A1));
+            pr = cadd(pr, cmul(cA2, D1));
+            pR = cadd(pR, cmul(cmul(cb, A1), D2));
+        }
+        // sum over the 16 columns held by lanes 16 quarter .. 16 quarter + 15
 #pragma unroll
         for (int off = 8; off > 0; off >>= 1) {
             pPsi.x += __shfl_xor(pPsi.x, off, 16);
@@ -158,8 +228,8 @@ __global__ void __launch_bounds__(256) k_vel_gemm(const double *__restrict__ Sr,
             pR.y += __shfl_xor(pR.y, off, 16);
         }
         if (row == 0) {
-            const int a = a0 + mfma_row_f64(lane, v);
-            double2 *dst = part + ((size_t)(b0 >> 4) * Np + a) * 3;
+            const int a = a0 + 16 * wave + mfma_row_f64(lane, v);
+            double2 *dst = part + ((size_t)blockIdx.y * Np + a) * 3;
             dst[0] = pPsi;
             dst[1] = pr;
             dst[2] = pR;
@@ -184,7 +254,7 @@ __global__ void k_vel_finish(const double2 *__restrict__ part, int N, int Np, do
     // positions the propagation of this step conditions on
     cphase[a] = expi(-0.5 * dt * model_v2(mp, R[a]));
     cphase[Np + a] = expi(-0.5 * dt * model_v1(mp, r[a]));
-    const int ntile = Np >> 4;
+    const int ntile = Np / kVB;
     double2 ps = make_double2(0, 0), nr = make_double2(0, 0), nR = make_double2(0, 0);
     for (int t = 0; t < ntile; ++t) {
         const double2 *src = part + ((size_t)t * Np + a) * 3;
@@ -234,7 +304,7 @@ void launch_velocity(const Dims &d, const Bufs &b, bool update, hipStream_t s) {
     hipLaunchKernelGGL(k_sinc, dim3(Np), dim3(256), 0, s, b.r, Np, d.nr, d.r_min, d.hr, b.sinc_r, b.dsinc_r, b.flags);
     hipLaunchKernelGGL(k_sinc, dim3(Np), dim3(256), 0, s, b.R, Np, d.nR, d.R_min, d.hR, b.sinc_R, b.dsinc_R,
                        b.flags);
-    hipLaunchKernelGGL(k_vel_gemm, dim3(Np / 32, Np / 32), dim3(256), 0, s, b.sinc_r, b.dsinc_r, b.psi1, d.nr,
+    hipLaunchKernelGGL(k_vel_gemm, dim3(Np / kVA, Np / kVB), dim3(256), 0, s, b.sinc_r, b.dsinc_r, b.psi1, d.nr,
                        b.sinc_R, b.dsinc_R, b.psi2, d.nR, b.C, Np, b.vpart, b.flags);
     unsigned long long *min_bits = reinterpret_cast<unsigned long long *>(b.scal);
     hipLaunchKernelGGL(k_vel_reset, dim3(1), dim3(64), 0, s, b.flags, min_bits);

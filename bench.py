@@ -40,10 +40,10 @@ HBM_PEAK_GBS = 8000.0
 # any change the traffic is reported as null until measured again.
 TRAFFIC = {
     "sm_n1024": {
-        "sources_sha256_16": "3ebbf25283f4eff5",
-        "fp64": 1335198496.0,      # k_wc<double>: fetch 647304.9 KiB x2, write 9295.0 KiB
-        "mixed": 510333408.0,      # k_wc<float> + k_wc_sep
-        "separable": 565709088.0,  # k_wc_sep (K = 29)
+        "sources_sha256_16": "98c5da56f17a5c9d",
+        "fp64": 1338614944.0,      # k_wc<double>: fetch 648991.1 KiB x2, write 9295.0 KiB
+        "mixed": 516121816.0,      # k_wc<float> + k_wc_sep
+        "separable": 577194018.0,  # k_wc_sep (K = 29)
     },
 }
 TRAFFIC_SOURCES = ("paper_1805_11169_amd/csrc/k_matrices.hip", "paper_1805_11169_amd/csrc/icwf_device.hpp")
@@ -203,9 +203,10 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if prec == icwf.PREC_FP64 else "f32-contraction/f64",
+        "dtype": "f32-contraction/f64" if prec == icwf.PREC_MIXED else "f64",
         "data": "synthetic",
-        "config": {"workload": wl.name, "model": "shin_metiu", "n_traj": N, "n_r": nr, "n_R": nR,
+        "config": {"workload": wl.name, "model": {1: "shin_metiu", 2: "cavity"}[wl.model], "n_traj": N,
+                   "n_r": nr, "n_R": nR,
                    "dt": wl.dt, "precision": args.precision, "contraction_rank": rank,
                    "timing": "kernel-by-kernel with HIP events"},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK[args.precision], "unit": "TFLOP/s",

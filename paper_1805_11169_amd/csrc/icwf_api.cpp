@@ -444,7 +444,16 @@ icwf_status icwf_create(const icwf_config *cfg, const double *r0, const double *
     if (cfg->precision == ICWF_PREC_MIXED) {
         std::vector<double> res = wc;
         d.lr_rank = cross_approximation(res, nr, nR, kMixedSplitTol, icwf::kLowRankMax, lr_u, lr_v);
-        for (size_t e = 0; e < res.size(); ++e) wc32[e] = static_cast<float>(res[e]);
+        double wmax = 0.0, rmax = 0.0;
+        for (size_t e = 0; e < res.size(); ++e) {
+            wc32[e] = static_cast<float>(res[e]);
+            wmax = std::max(wmax, std::fabs(wc[e]));
+            rmax = std::max(rmax, std::fabs(res[e]));
+        }
+        // a residual at the table's own rounding level (an exactly separable
+        // coupling, such as the cavity's lambda q x) leaves the FP32 pass
+        // nothing to add: the FP64 rank-K part is then the whole contraction
+        d.fp32_residual = !(d.lr_rank > 0 && rmax <= kSeparableTol * wmax);
     } else if (cfg->precision == ICWF_PREC_SEPARABLE) {
         std::vector<double> res = wc;
         d.lr_rank = cross_approximation(res, nr, nR, kSeparableTol, icwf::kLowRankMax, lr_u, lr_v);
@@ -506,7 +515,7 @@ icwf_status icwf_create(const icwf_config *cfg, const double *r0, const double *
     else CREATE_HIP(hipMemcpyAsync(b.Cstage, b0, sizeof(double2) * N, hipMemcpyHostToDevice, st));
 
     // ---- initial S_0, K_0 and the factor of S_0 + eps I
-    if (d.prec == ICWF_PREC_MIXED) icwf::launch_psi1_f32(d, b, st);
+    if (d.prec == ICWF_PREC_MIXED && d.fp32_residual) icwf::launch_psi1_f32(d, b, st);
     icwf::launch_cond_kets(d, b, st);
     icwf::launch_single_species(d, b, false, st);
     icwf::launch_wc(d, b, st);

@@ -13,6 +13,7 @@ namespace icwf {
 struct Dims {
     int N, nr, nR, n_bo, prec;
     int lr_rank;                          // rank of the FP64 part of the mixed contraction
+    int fp32_residual;                    // mixed form: the residual left to FP32 is not negligible
     int wc_grid;                          // work-groups of the persistent two-body contraction
     int prop_grid[2];                     // work-groups of the persistent propagation, per species
     double r_min, hr, R_min, hR, m_r, m_R, dt, eps;

@@ -565,14 +565,17 @@ void launch_wc(const Dims &d, const Bufs &b, hipStream_t s) {
     const double scale = d.hr * d.hR;
     if (d.prec == 1) {
         // mixed: FP32 matrix cores on the residual of the rank-K split, FP64 rank-K part added
-        launch_fill_i32(b.wc_queue, 1, 0, s);
-        hipLaunchKernelGGL(k_wc<float>, dim3(std::min(blocks, d.wc_grid)), dim3(256), 0, s, b.psi1_f32, b.psi2,
-                           b.wc32, d.nr, d.nR, scale, b.Wc, Np, 0, blocks, b.wc_queue, b.flags);
+        // (the FP32 pass only where the residual is above the table's rounding)
+        if (d.fp32_residual) {
+            launch_fill_i32(b.wc_queue, 1, 0, s);
+            hipLaunchKernelGGL(k_wc<float>, dim3(std::min(blocks, d.wc_grid)), dim3(256), 0, s, b.psi1_f32, b.psi2,
+                               b.wc32, d.nr, d.nR, scale, b.Wc, Np, 0, blocks, b.wc_queue, b.flags);
+        }
         if (d.lr_rank > 0) {
             launch_fill_i32(b.wc_queue, 1, 0, s);
             hipLaunchKernelGGL(k_wc_sep, dim3(std::min(blocks, d.wc_grid)), dim3(256), 0, s, b.psi1, b.psi2, b.lr_u,
-                               b.lr_v, (d.lr_rank + 15) / 16 * 16, d.nr, d.nR, scale, b.Wc, Np, 1, blocks, b.wc_queue,
-                               b.flags);
+                               b.lr_v, (d.lr_rank + 15) / 16 * 16, d.nr, d.nR, scale, b.Wc, Np,
+                               d.fp32_residual ? 1 : 0, blocks, b.wc_queue, b.flags);
         }
     } else if (d.prec == 2) {
         // separable: the whole contraction through the sum of products (assigns Wc)

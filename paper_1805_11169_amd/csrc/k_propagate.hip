@@ -542,7 +542,7 @@ void launch_propagate(const Dims &d, const Bufs &b, int species, hipStream_t s) 
     const int tiny = d.mp.kind == 1 && 0.5 * std::fabs(d.dt) * 2.0 / (std::sqrt(M_PI) * d.mp.p[1]) <= kTinyPhase;
     if (species == 1) {
         hipLaunchKernelGGL(k, dim3(grid), dim3(T), lds, s, b.psi1, ngroups, b.vphase_r, d.r_min, d.hr, b.R, b.cphase,
-                           1, d.mp, b.kin_r, b.tw_r, d.dt, tiny, d.prec == 1 ? b.psi1_f32 : nullptr, b.flags);
+                           1, d.mp, b.kin_r, b.tw_r, d.dt, tiny, d.prec == 1 && d.fp32_residual ? b.psi1_f32 : nullptr, b.flags);
     } else {
         hipLaunchKernelGGL(k, dim3(grid), dim3(T), lds, s, b.psi2, ngroups, b.vphase_R, d.R_min, d.hR, b.r,
                            b.cphase + padded(d.N), 2, d.mp, b.kin_R, b.tw_R, d.dt, tiny, nullptr, b.flags);

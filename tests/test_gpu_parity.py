@@ -147,6 +147,29 @@ def test_separable_form_one_step(case):
     assert s_norm_diff(got["C"], ref.C, ref.S) < 1e-10 * np.sqrt(abs(np.conj(ref.C) @ ref.S @ ref.C))
 
 
+def test_mixed_form_on_an_exactly_separable_coupling(case):
+    """The mixed form on the cavity coupling lambda q x: its one-term FP64 split
+    leaves a residual at the table's rounding level, so no FP32 pass runs and
+    the matrices and one step meet the plain form's bars.  (On Shin-Metiu the
+    FP32 residual pass stays; its bar is the 1e-5 of the C1 tests.)"""
+    wl, setup, st0 = case
+    if wl.model != inputs.MODEL_CAVITY:
+        pytest.skip("Shin-Metiu keeps an FP32 residual")
+    sim = icwf.Simulation.from_workload(wl, precision=icwf.PREC_MIXED, C0=wl.extra["C0"])
+    assert sim.contraction_rank() == 1
+    S, K, Wc = sim.matrices()
+    Wc_ref = omat.two_body(st0.psi1, st0.psi2, wc_table(setup), setup.hr, setup.hR)
+    assert rel_max(Wc, Wc_ref) < 1e-12
+    assert rel_max(K, st0.K) < 1e-12
+    sim.step(1)
+    sim.sync()
+    got = sim.state()
+    ref = oicwf.step(setup, st0)
+    sim.close()
+    assert np.max(np.abs(got["psi1"] - ref.psi1)) < 1e-12
+    assert s_norm_diff(got["C"], ref.C, ref.S) < 1e-10 * np.sqrt(abs(np.conj(ref.C) @ ref.S @ ref.C))
+
+
 def test_separable_form_refuses_a_coupling_without_a_short_sum():
     """A Shin-Metiu coupling too sharp for 64 products on a fine grid: creation
     fails with ICWF_EINVAL instead of silently truncating."""

@@ -227,10 +227,11 @@ __global__ void __launch_bounds__(256) k_chol_flush(double2 *A0, double2 *A1, in
 }
 
 // Trailing update A[i][k] -= sum_j L[i][j] conj(L[k][j]) over the lower
-// triangle i >= k of rows/cols kb+NB .. Np-1, j over the panel; one wave per
-// 32 x 32 tile.
-__global__ void __launch_bounds__(64) k_chol_update(double2 *A0, double2 *A1, int Np, int kb,
-                                                    const int32_t *__restrict__ flags) {
+// triangle i >= k of rows/cols kb+NB .. Np-1, j over the panel; one
+// work-group per 32 x 32 tile, wave w on its 16 x 16 fragment (w / 2, w % 2),
+// so a tile's 64-deep reduction runs on four matrix-core streams at once.
+__global__ void __launch_bounds__(256) k_chol_update(double2 *A0, double2 *A1, int Np, int kb,
+                                                     const int32_t *__restrict__ flags) {
     if (flags[kFlagHalt]) return;
     double2 *A = blockIdx.y ? A1 : A0;
     const int t = blockIdx.x;
@@ -239,53 +240,30 @@ __global__ void __launch_bounds__(64) k_chol_update(double2 *A0, double2 *A1, in
     while (ti * (ti + 1) / 2 > t) --ti;
     const int tk = t - ti * (ti + 1) / 2;
     const int base = kb + NB;
-    const int i0 = base + 32 * ti, k0 = base + 32 * tk;
-    const int lane = threadIdx.x, row = lane & 15, quarter = lane >> 4;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int f = wave >> 1, g = wave & 1;
+    const int i0 = base + 32 * ti + 16 * f, k0 = base + 32 * tk + 16 * g;
+    const int row = lane & 15, quarter = lane >> 4;
     const int q = NB / 4;
-    dbl4 re[2][2], im[2][2];
-#pragma unroll
-    for (int f = 0; f < 2; ++f)
-#pragma unroll
-        for (int g = 0; g < 2; ++g) {
-            re[f][g] = dbl4{0, 0, 0, 0};
-            im[f][g] = dbl4{0, 0, 0, 0};
-        }
-    const double2 *xp[2], *yp[2];
-#pragma unroll
-    for (int f = 0; f < 2; ++f) {
-        xp[f] = A + (size_t)(i0 + 16 * f + row) * Np + kb + quarter * q;
-        yp[f] = A + (size_t)(k0 + 16 * f + row) * Np + kb + quarter * q;
-    }
+    dbl4 re = {0, 0, 0, 0}, im = {0, 0, 0, 0};
+    const double2 *xp = A + (size_t)(i0 + row) * Np + kb + quarter * q;
+    const double2 *yp = A + (size_t)(k0 + row) * Np + kb + quarter * q;
     for (int s = 0; s < q; ++s) {
-        double2 xv[2], yv[2];
-#pragma unroll
-        for (int f = 0; f < 2; ++f) {
-            xv[f] = xp[f][s];
-            yv[f] = yp[f][s];
-        }
-#pragma unroll
-        for (int f = 0; f < 2; ++f)
-#pragma unroll
-            for (int g = 0; g < 2; ++g) {
-                // x conj(y) = (xr yr + xi yi) + i (xi yr - xr yi)
-                re[f][g] = mfma(xv[f].x, yv[g].x, re[f][g]);
-                re[f][g] = mfma(xv[f].y, yv[g].y, re[f][g]);
-                im[f][g] = mfma(xv[f].y, yv[g].x, im[f][g]);
-                im[f][g] = mfma(-xv[f].x, yv[g].y, im[f][g]);
-            }
+        const double2 xv = xp[s], yv = yp[s];
+        // x conj(y) = (xr yr + xi yi) + i (xi yr - xr yi)
+        re = mfma(xv.x, yv.x, re);
+        re = mfma(xv.y, yv.y, re);
+        im = mfma(xv.y, yv.x, im);
+        im = mfma(-xv.x, yv.y, im);
     }
 #pragma unroll
-    for (int f = 0; f < 2; ++f)
-#pragma unroll
-        for (int g = 0; g < 2; ++g)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int ii = i0 + 16 * f + mfma_row_f64(lane, v);
-                const int kk = k0 + 16 * g + row;
-                double2 *p = A + (size_t)ii * Np + kk;
-                const double2 o = *p;
-                *p = make_double2(o.x - re[f][g][v], o.y - im[f][g][v]);
-            }
+    for (int v = 0; v < 4; ++v) {
+        const int ii = i0 + mfma_row_f64(lane, v);
+        const int kk = k0 + row;
+        double2 *p = A + (size_t)ii * Np + kk;
+        const double2 o = *p;
+        *p = make_double2(o.x - re[v], o.y - im[v]);
+    }
 }
 
 // Inverse of each 64 x 64 diagonal block of a lower Cholesky factor,
@@ -613,7 +591,7 @@ void launch_cholesky(const Dims &d, const Bufs &b, double2 *A0, double2 *A1, dou
                            b.flags);
         if (below > 0) {
             const int mt = below / 32;
-            hipLaunchKernelGGL(k_chol_update, dim3(mt * (mt + 1) / 2, count), dim3(64), 0, s, A0, A1, Np, kb,
+            hipLaunchKernelGGL(k_chol_update, dim3(mt * (mt + 1) / 2, count), dim3(256), 0, s, A0, A1, Np, kb,
                                b.flags);
         }
     }

@@ -140,6 +140,9 @@ __global__ void __launch_bounds__(kPanelThreads) k_chol_panel(double2 *A0, doubl
                                                               double2 *__restrict__ diag,
                                                               int32_t *__restrict__ flags) {
     if (flags[kFlagHalt]) return;
+    // the panel is a latency chain that shares compute units with the
+    // contraction on the other stream: its waves take the issue slots first
+    __builtin_amdgcn_s_setprio(3);
     __shared__ double2 lcol[2][NB];      // column j over the diagonal rows, unscaled, alternating with j
     __shared__ double dpiv[NB], dinvs[NB];
     double2 *A = blockIdx.y ? A1 : A0;

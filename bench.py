@@ -40,10 +40,10 @@ HBM_PEAK_GBS = 8000.0
 # any change the traffic is reported as null until measured again.
 TRAFFIC = {
     "sm_n1024": {
-        "sources_sha256_16": "98c5da56f17a5c9d",
-        "fp64": 1338614944.0,      # k_wc<double>: fetch 648991.1 KiB x2, write 9295.0 KiB
-        "mixed": 516121816.0,      # k_wc<float> + k_wc_sep
-        "separable": 577194018.0,  # k_wc_sep (K = 29)
+        "sources_sha256_16": "4ca89a513f6dc5fd",
+        "fp64": 1308726052.9,      # k_wc<double>: fetch 629867.3 KiB x2, write 18353.0 KiB
+        "mixed": 541047281.1,       # k_wc<float> + k_wc_sep
+        "separable": 571406616.9,   # k_wc_sep (K = 29)
     },
 }
 TRAFFIC_SOURCES = ("paper_1805_11169_amd/csrc/k_matrices.hip", "paper_1805_11169_amd/csrc/icwf_device.hpp")

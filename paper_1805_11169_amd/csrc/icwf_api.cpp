@@ -44,7 +44,8 @@ Bufs carve(const icwf_config &c, char *base, size_t *total) {
     const size_t Np = icwf::padded(c.n_traj), nr = c.n_r, nR = c.n_R, nbo = c.n_bo;
     Bufs b{};
     b.flags = L.take<int32_t>(icwf::kNumFlags);
-    b.wc_queue = L.take<int32_t>(1);
+    b.wc_queue = L.take<int32_t>(1 + icwf::wc_split_tiles((int)Np));
+    b.wc_part = L.take<double2>((size_t)icwf::wc_split_tiles((int)Np) * icwf::kWcParts * 256);
     b.scal = L.take<double>(8);
     b.psi1 = L.take<double2>(Np * nr);
     b.psi2 = L.take<double2>(Np * nR);

@@ -28,6 +28,15 @@ inline int padded(int N) { return (N + kPad - 1) / kPad * kPad; }
 constexpr int kCholNb = 64;      // Cholesky panel width
 constexpr int kLowRankMax = 64;  // most terms of a sum-of-products W_c (mixed and separable forms)
 constexpr int kWcReserve = 64;   // CU slots the persistent contraction leaves to the other stream
+constexpr int kWcSplitMax = 512; // most tiles the contraction splits at the end of its queue
+constexpr int kWcParts = 4;      // units per split tile (FP64 step at N = 1024: 6.32 ms with 2, 6.27 with 4)
+// Tiles the split applies to for Np padded trajectories: the last round of
+// the persistent contraction, at most all tiles.
+inline int wc_split_tiles(int Np) {
+    const int t = Np / 16;
+    const int tiles = t * (t + 1) / 2;
+    return tiles < kWcSplitMax ? tiles : kWcSplitMax;
+}
 
 struct Bufs {
     double2 *psi1, *psi2;                 // [N][nr], [N][nR] CWFs (Eq. 7)
@@ -67,7 +76,9 @@ struct Bufs {
     double2 *obs_chi;                     // [n_bo][nR]
     double *obs_out;                      // packed observables
     int32_t *flags;                       // kNumFlags status flags
-    int32_t *wc_queue;                    // tile counter of the persistent two-body contraction
+    int32_t *wc_queue;                    // [1 + wc_split_tiles(Np)] tile counter of the persistent two-body
+                                          // contraction, then the completion counters of its split tiles
+    double2 *wc_part;                     // [wc_split_tiles(Np)][kWcParts][256] partial sums of split tiles
     double *scal;                         // small device scalars (min |Psi|, ...)
 };
 

@@ -237,8 +237,8 @@ __global__ void __launch_bounds__(256, 2) k_wc(const typename WcTraits<T>::cplx 
                                                const double2 *__restrict__ psi2,
                                                const T *__restrict__ wtab, int nr, int nR, double scale,
                                                double2 *__restrict__ Wc, int Np, int accumulate,
-                                               int ntiles, int32_t *__restrict__ queue,
-                                               const int32_t *__restrict__ flags) {
+                                               int ntiles, int nsplit, int nparts, int32_t *__restrict__ queue,
+                                               double2 *__restrict__ part, const int32_t *__restrict__ flags) {
     typedef typename WcTraits<T>::acc4 acc4;
     typedef typename WcTraits<T>::cplx C2;
     typedef WcChunk<T> CK;
@@ -247,16 +247,26 @@ __global__ void __launch_bounds__(256, 2) k_wc(const typename WcTraits<T>::cplx 
     __shared__ C2 sA[2][32][LDA];      // rows 0..15: a rows, 16..31: b rows of the tile
     __shared__ T sW[2][KC][LDW];
     __shared__ double2 wl[4][4][16];   // [wave][b][a] block partial of Wc
-    __shared__ int s_tile;
+    __shared__ int s_tile, s_done;
     // persistent: the work-group takes upper-triangle tiles from a queue until
     // none is left (fewer work-groups than CU slots leaves room for work on
-    // another stream)
+    // another stream).  The last nsplit tiles of the queue come as nparts
+    // units each, one per nparts-th of the j tiles, so that the final round
+    // ends with small pieces of work: each unit leaves its partial sum in
+    // `part`, and the unit that completes last adds them in part order
+    // (whatever the order of completion) and writes the tile.
+    const int nfull = ntiles - nsplit;
     for (;;) {
         if (threadIdx.x == 0) s_tile = atomicAdd(queue, 1);
         __syncthreads();
-        const int tile = s_tile;
+        const int unit = s_tile;
         __syncthreads();
-        if (tile >= ntiles) break;
+        if (unit >= nfull + nsplit * nparts) break;
+        int tile = unit, half = -1;   // half: this unit's part of a split tile
+        if (unit >= nfull) {
+            tile = nfull + (unit - nfull) / nparts;
+            half = (unit - nfull) - (tile - nfull) * nparts;
+        }
         int tb, ta;
         triangle_tile(tile, &tb, &ta);
 
@@ -269,12 +279,13 @@ __global__ void __launch_bounds__(256, 2) k_wc(const typename WcTraits<T>::cplx 
 
         for (int e = lane; e < 64; e += 64) wl[wave][e >> 4][e & 15] = make_double2(0, 0);
 
-        const int nchunk = nr / KC, ntj = nR / 32, nsteps = nchunk * ntj;
+        const int nchunk = nr / KC, ntj = half < 0 ? nR / 32 : nR / 32 / nparts, nsteps = nchunk * ntj;
+        const int jt0 = half > 0 ? half * ntj : 0;   // first j tile of this unit
         // staging registers for one (j tile, i chunk) step
         C2 ra[PER];
         T rw[PER];
         auto fetch = [&](int step) {
-            const int jt = step / nchunk, ch = step - jt * nchunk;
+            const int jl = step / nchunk, ch = step - jl * nchunk, jt = jt0 + jl;
             const int i0 = ch * KC, j0 = jt * 32;
     #pragma unroll
             for (int m = 0; m < PER; ++m) {
@@ -302,7 +313,7 @@ __global__ void __launch_bounds__(256, 2) k_wc(const typename WcTraits<T>::cplx 
         __syncthreads();
         for (int step = 0; step < nsteps; ++step) {
             const int buf = step & 1;
-            const int jt = step / nchunk, ch = step - jt * nchunk;
+            const int jl = step / nchunk, ch = step - jl * nchunk, jt = jt0 + jl;
             if (ch == 0) {
     #pragma unroll
                 for (int bb = 0; bb < 4; ++bb)
@@ -373,11 +384,26 @@ __global__ void __launch_bounds__(256, 2) k_wc(const typename WcTraits<T>::cplx 
             __syncthreads();
         }
         // write the 4 x 16 partials of this wave
-        {
-            const int bb = lane >> 4, a = lane & 15;
+        const int bb = lane >> 4, a = lane & 15;
+        double2 *dst = Wc + (size_t)(b_base + bb) * Np + a_base + a;
+        if (half < 0) {
             const double2 x = cscale(wl[wave][bb][a], scale);
-            double2 *dst = Wc + (size_t)(b_base + bb) * Np + a_base + a;
             *dst = accumulate ? cadd(*dst, x) : x;
+        } else {
+            const int slot = tile - nfull;
+            double2 *pp = part + (size_t)slot * nparts * 256 + wave * 64 + lane;
+            pp[256 * half] = wl[wave][bb][a];
+            __threadfence();
+            __syncthreads();
+            if (threadIdx.x == 0) s_done = atomicAdd(&queue[1 + slot], 1);
+            __syncthreads();
+            if (s_done == nparts - 1) {
+                __threadfence();
+                double2 acc = pp[0];
+                for (int h = 1; h < nparts; ++h) acc = cadd(acc, pp[256 * h]);
+                const double2 x = cscale(acc, scale);
+                *dst = accumulate ? cadd(*dst, x) : x;
+            }
         }
     }
 }
@@ -563,13 +589,18 @@ void launch_wc(const Dims &d, const Bufs &b, hipStream_t s) {
     const int T16 = Np / 16;
     const int blocks = T16 * (T16 + 1) / 2;
     const double scale = d.hr * d.hR;
+    // the last round of tiles split in kWcParts (fewer where R has fewer
+    // 32-point j tiles)
+    const int grid = std::min(blocks, d.wc_grid);
+    const int nparts = std::min(kWcParts, d.nR / 32);
+    const int nsplit = nparts >= 2 ? std::min(grid, wc_split_tiles(Np)) : 0;
     if (d.prec == 1) {
         // mixed: FP32 matrix cores on the residual of the rank-K split, FP64 rank-K part added
         // (the FP32 pass only where the residual is above the table's rounding)
         if (d.fp32_residual) {
-            launch_fill_i32(b.wc_queue, 1, 0, s);
-            hipLaunchKernelGGL(k_wc<float>, dim3(std::min(blocks, d.wc_grid)), dim3(256), 0, s, b.psi1_f32, b.psi2,
-                               b.wc32, d.nr, d.nR, scale, b.Wc, Np, 0, blocks, b.wc_queue, b.flags);
+            launch_fill_i32(b.wc_queue, 1 + nsplit, 0, s);
+            hipLaunchKernelGGL(k_wc<float>, dim3(grid), dim3(256), 0, s, b.psi1_f32, b.psi2, b.wc32, d.nr, d.nR,
+                               scale, b.Wc, Np, 0, blocks, nsplit, nparts, b.wc_queue, b.wc_part, b.flags);
         }
         if (d.lr_rank > 0) {
             launch_fill_i32(b.wc_queue, 1, 0, s);
@@ -584,9 +615,9 @@ void launch_wc(const Dims &d, const Bufs &b, hipStream_t s) {
                            b.lr_v, (d.lr_rank + 15) / 16 * 16, d.nr, d.nR, scale, b.Wc, Np, 0, blocks, b.wc_queue,
                            b.flags);
     } else {
-        launch_fill_i32(b.wc_queue, 1, 0, s);
-        hipLaunchKernelGGL(k_wc<double>, dim3(std::min(blocks, d.wc_grid)), dim3(256), 0, s, b.psi1, b.psi2,
-                           b.wc64, d.nr, d.nR, scale, b.Wc, Np, 0, blocks, b.wc_queue, b.flags);
+        launch_fill_i32(b.wc_queue, 1 + nsplit, 0, s);
+        hipLaunchKernelGGL(k_wc<double>, dim3(grid), dim3(256), 0, s, b.psi1, b.psi2, b.wc64, d.nr, d.nR, scale,
+                           b.Wc, Np, 0, blocks, nsplit, nparts, b.wc_queue, b.wc_part, b.flags);
     }
 }
 

@@ -249,12 +249,13 @@ void timed(icwf_sim *s, const char *name, hipStream_t st, F fn) {
     s->timers[name].recs.emplace_back(a, b);
 }
 
-// One step on stream st.  The two Cholesky factorisations need only S (from
-// the single-species overlaps), not the two-body contraction: from
-// kOverlapMinN padded trajectories on, after the single-species kernels the
-// step forks, the side stream assembles S and factors S + eps I while st
-// contracts W_c and assembles K, and st waits for the side stream before the
-// RK4 stages.  The persistent contraction leaves CU slots free for the side
+// One step on stream st.  The two-body contraction needs neither the
+// single-species integrals nor the Cholesky factorisations, which need only S:
+// from kOverlapMinN padded trajectories on, the step forks, the side stream
+// assembles S and factors S + eps I (in the FP64 form, where the contraction
+// is the longest branch, after computing the single-species integrals
+// itself) while st contracts W_c; st then waits for the side stream,
+// assembles K and runs the RK4 stages.  The persistent contraction leaves CU slots free for the side
 // stream's latency-bound kernels.  Smaller simulations (whose contraction
 // does not fill the GPU, and which a server runs many at a time) stay on one
 // stream: event waits between streams would serialise other simulations'
@@ -270,23 +271,31 @@ void enqueue_step(icwf_sim *s, int parity, hipStream_t st, hipStream_t side) {
         icwf::launch_propagate(d, b, 1, st);
         icwf::launch_propagate(d, b, 2, st);
     });
-    timed(s, "zgemm", st, [&] {
-        icwf::launch_cond_kets(d, b, st);
-        icwf::launch_single_species(d, b, true, st);
-    });
     const bool fork = side != st;
+    // the single-species integrals join the side stream where the contraction
+    // is the longer branch (FP64); the shorter mixed and separable
+    // contractions leave them on st, ahead of the fork
+    const hipStream_t ss = fork && d.prec == ICWF_PREC_FP64 ? side : st;
+    auto single_species = [&] {
+        timed(s, "zgemm", ss, [&] {
+            icwf::launch_cond_kets(d, b, ss);
+            icwf::launch_single_species(d, b, true, ss);
+        });
+    };
+    if (ss == st) single_species();
     if (fork) {
         (void)hipEventRecord(s->ev_fork, st);
         (void)hipStreamWaitEvent(side, s->ev_fork, 0);
     }
+    if (ss != st) single_species();
     timed(s, "cholesky", side, [&] {
         icwf::launch_assemble(d, b, parity, icwf::kAssembleS, side);
         icwf::launch_cholesky(d, b, b.Lmid, b.L[1 - parity], b.Linvmid, b.Linv[1 - parity], 2, side);
     });
     if (fork) (void)hipEventRecord(s->ev_join, side);
     timed(s, "wc_contract", st, [&] { icwf::launch_wc(d, b, st); });
-    timed(s, "assemble", st, [&] { icwf::launch_assemble(d, b, parity, icwf::kAssembleK, st); });
     if (fork) (void)hipStreamWaitEvent(st, s->ev_join, 0);
+    timed(s, "assemble", st, [&] { icwf::launch_assemble(d, b, parity, icwf::kAssembleK, st); });
     timed(s, "rk4", st, [&] { icwf::launch_rk4(d, b, parity, st); });
 }
 

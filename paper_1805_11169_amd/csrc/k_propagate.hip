@@ -15,13 +15,14 @@
 // inverse pass, and the last inverse pass and the store all run in registers.
 // The passes between them go through two LDS buffers (radix 8, with one
 // radix 2 or 4 pass first when log2 n is not a multiple of 3; twiddles from an
-// LDS table).  The CWF is read once from HBM and written once, both
+// LDS table); n = 4096 uses a four-step 64 x 64 transform through one buffer
+// instead (below).  The CWF is read once from HBM and written once, both
 // coalesced.  The potential phase is evaluated once per point and kept in
 // registers for both half steps, as the product of a table of the
-// one-coordinate part's phase, the constant part's phase, and the coupling's
-// (from a piecewise-polynomial erf table, e^{i theta} by a Taylor series,
-// reduced when needed).  The inverse FFT is the forward one applied to the
-// conjugate.
+// one-coordinate part's phase, the constant part's phase (per CWF, written by
+// the velocity kernel), and the coupling's (from a piecewise-polynomial erf
+// table, e^{i theta} by a Taylor series, reduced when needed).  The inverse
+// FFT is the forward one applied to the conjugate.
 #include <cmath>
 
 #include "icwf_plan.hpp"

@@ -212,7 +212,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f32-contraction/f64" if prec == icwf.PREC_MIXED else "f64",
         "data": "synthetic",
-        "config": {"workload": wl.name, "model": {1: "shin_metiu", 2: "cavity"}[wl.model], "n_traj": N,
+        "config": {"workload": wl.name, "hamiltonian": {1: "shin_metiu", 2: "cavity"}[wl.model], "n_traj": N,
                    "n_r": nr, "n_R": nR,
                    "dt": wl.dt, "precision": args.precision, "contraction_rank": rank,
                    "timing": "kernel-by-kernel with HIP events"},

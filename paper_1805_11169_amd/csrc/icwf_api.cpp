@@ -89,6 +89,12 @@ Bufs carve(const icwf_config &c, char *base, size_t *total) {
     b.Linv[0] = L.take<double2>(Np * icwf::kCholNb);
     b.Linv[1] = L.take<double2>(Np * icwf::kCholNb);
     b.Linvmid = L.take<double2>(Np * icwf::kCholNb);
+    {
+        // explicit inverses for the RK4 stages (see use_sinv)
+        const size_t nn = icwf::use_sinv((int)Np, c.precision) ? Np * Np : 1;
+        for (double2 **m : {&b.Xinv[0], &b.Xinv[1], &b.Tinv[0], &b.Tinv[1], &b.Sinv[0], &b.Sinv[1], &b.Sinvmid})
+            *m = L.take<double2>(nn);
+    }
     b.chol_diag = L.take<double2>(2 * icwf::kCholNb * icwf::kCholNb);
     b.xsol = L.take<double2>(Np);
     b.solve_sync = L.take<int32_t>(130);
@@ -273,9 +279,9 @@ void enqueue_step(icwf_sim *s, int parity, hipStream_t st, hipStream_t side) {
     });
     const bool fork = side != st;
     // the single-species integrals join the side stream where the contraction
-    // is the longer branch (FP64); the shorter mixed and separable
-    // contractions leave them on st, ahead of the fork
-    const hipStream_t ss = fork && d.prec == ICWF_PREC_FP64 ? side : st;
+    // is the longer branch (FP64 without the explicit inverses, which take that
+    // room on the side stream); otherwise they stay on st, ahead of the fork
+    const hipStream_t ss = fork && d.prec == ICWF_PREC_FP64 && !d.sinv ? side : st;
     auto single_species = [&] {
         timed(s, "zgemm", ss, [&] {
             icwf::launch_cond_kets(d, b, ss);
@@ -290,7 +296,8 @@ void enqueue_step(icwf_sim *s, int parity, hipStream_t st, hipStream_t side) {
     if (ss != st) single_species();
     timed(s, "cholesky", side, [&] {
         icwf::launch_assemble(d, b, parity, icwf::kAssembleS, side);
-        icwf::launch_cholesky(d, b, b.Lmid, b.L[1 - parity], b.Linvmid, b.Linv[1 - parity], 2, side);
+        icwf::launch_cholesky(d, b, b.Lmid, b.L[1 - parity], b.Linvmid, b.Linv[1 - parity], 2, side,
+                              d.sinv ? b.Sinvmid : nullptr, b.Sinv[1 - parity]);
     });
     if (fork) (void)hipEventRecord(s->ev_join, side);
     timed(s, "wc_contract", st, [&] { icwf::launch_wc(d, b, st); });
@@ -394,6 +401,7 @@ icwf_status icwf_create(const icwf_config *cfg, const double *r0, const double *
     d.nR = nR;
     d.n_bo = nbo;
     d.prec = cfg->precision;
+    d.sinv = icwf::use_sinv(icwf::padded(N), cfg->precision) ? 1 : 0;
     d.r_min = cfg->r_min;
     d.hr = (cfg->r_max - cfg->r_min) / nr;
     d.R_min = cfg->R_min;
@@ -530,7 +538,8 @@ icwf_status icwf_create(const icwf_config *cfg, const double *r0, const double *
     icwf::launch_single_species(d, b, false, st);
     icwf::launch_wc(d, b, st);
     icwf::launch_assemble(d, b, 0, icwf::kAssembleInitial, st);
-    icwf::launch_cholesky(d, b, b.L[0], b.L[0], b.Linv[0], b.Linv[0], 1, st);
+    icwf::launch_cholesky(d, b, b.L[0], b.L[0], b.Linv[0], b.Linv[0], 1, st, d.sinv ? b.Sinv[0] : nullptr,
+                          nullptr);
     if (!C0) icwf::launch_solve_initial(d, b, 0, b.Cstage, st);
     CREATE_HIP(hipGetLastError());
     const icwf_status ds = device_status(s);

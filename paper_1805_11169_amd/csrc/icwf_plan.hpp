@@ -14,6 +14,7 @@ struct Dims {
     int N, nr, nR, n_bo, prec;
     int lr_rank;                          // rank of the FP64 part of the mixed contraction
     int fp32_residual;                    // mixed form: the residual left to FP32 is not negligible
+    int sinv;                             // RK4 stages through explicit inverses of S + eps I
     int wc_grid;                          // work-groups of the persistent two-body contraction
     int prop_grid[2];                     // work-groups of the persistent propagation, per species
     double r_min, hr, R_min, hR, m_r, m_R, dt, eps;
@@ -68,6 +69,10 @@ struct Bufs {
     double2 *Kminus, *Kmid;               // K(psi_k+1, x_k) and the midpoint K
     double2 *L[2], *Lmid;                 // Cholesky factors of S + eps I (lower)
     double2 *Linv[2], *Linvmid;           // [Np][64] inverses of their 64 x 64 diagonal blocks
+    double2 *Xinv[2];                     // [Np][Np] inverses of the two factors in flight (lower;
+                                          // zero above the diagonal; sinv only)
+    double2 *Tinv[2];                     // [Np][Np] scratch of the block inversion (sinv only)
+    double2 *Sinv[2], *Sinvmid;           // [Np][Np] (S + eps I)^-1 with L, Lmid (sinv only)
     double2 *chol_diag;                   // [2][64][64] factored diagonal blocks in flight
     double2 *xsol;                        // [Np] back-substitution result of an RK stage
     int32_t *solve_sync;                  // [130] block flags and tickets of the stage solves
@@ -81,6 +86,14 @@ struct Bufs {
     double2 *wc_part;                     // [wc_split_tiles(Np)][kWcParts][256] partial sums of split tiles
     double *scal;                         // small device scalars (min |Psi|, ...)
 };
+
+// RK4 through explicit inverses of S + eps I: where the factorisations run on
+// the second stream beside a contraction long enough to hide the inversion
+// (FP64 and mixed forms, from 1024 padded trajectories, a power of two so
+// that the block inversion halves evenly).
+inline bool use_sinv(int Np, int precision) {
+    return Np >= 1024 && (Np & (Np - 1)) == 0 && precision != 2;
+}
 
 // ---- launchers (each defined next to its kernels) -------------------------------------------
 
@@ -114,9 +127,10 @@ enum AssemblePart { kAssembleS = 1, kAssembleK = 2, kAssembleInitial = 3 };
 void launch_assemble(const Dims &d, const Bufs &b, int parity, AssemblePart part, hipStream_t s);
 
 // In-place lower Cholesky of `count` matrices (A0, A1), each Np x Np, and the
-// inverses of their 64 x 64 diagonal blocks into X0, X1 ([Np][64]).
+// inverses of their 64 x 64 diagonal blocks into X0, X1 ([Np][64]).  With
+// S0 non-null (d.sinv), also (L L^H)^-1 of each factor into S0, S1 ([Np][Np]).
 void launch_cholesky(const Dims &d, const Bufs &b, double2 *A0, double2 *A1, double2 *X0, double2 *X1, int count,
-                     hipStream_t s);
+                     hipStream_t s, double2 *S0 = nullptr, double2 *S1 = nullptr);
 
 // One RK4 step of Eq. 8 with the factors / matrices of the given parity.
 void launch_rk4(const Dims &d, const Bufs &b, int parity, hipStream_t s);

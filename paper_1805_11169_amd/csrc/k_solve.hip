@@ -280,13 +280,15 @@ __global__ void __launch_bounds__(256) k_chol_update(double2 *A0, double2 *A1, i
 // The stage solves apply X_B and X_B^H as matrix-vector products instead of a
 // 64-step substitution on their critical path.  Output: X[(B 64 + r) 64 + c].
 __global__ void __launch_bounds__(256) k_tri_inv(const double2 *__restrict__ A0, const double2 *__restrict__ A1,
-                                                 double2 *__restrict__ X0, double2 *__restrict__ X1, int Np,
+                                                 double2 *__restrict__ X0, double2 *__restrict__ X1,
+                                                 double2 *__restrict__ F0, double2 *__restrict__ F1, int Np,
                                                  const int32_t *__restrict__ flags) {
     if (flags[kFlagHalt]) return;
     // 66.5 KB of LDS: fits beside a two-body contraction work-group on one CU
     __shared__ double2 sX[NB][NB + 1];        // the inverse (lower; zero above)
     const double2 *A = blockIdx.y ? A1 : A0;
     double2 *X = blockIdx.y ? X1 : X0;
+    double2 *F = blockIdx.y ? F1 : F0;        // the same blocks in a full Np x Np inverse, or null
     const int r0 = blockIdx.x * NB;
     const double2 *Lb = A + (size_t)r0 * Np + r0;   // L_BB(r, k) = Lb[r Np + k]
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
@@ -378,7 +380,141 @@ __global__ void __launch_bounds__(256) k_tri_inv(const double2 *__restrict__ A0,
     for (int e = t; e < NB * NB; e += 256) {
         const int rr = e / NB, cc = e % NB;
         X[(size_t)(r0 + rr) * NB + cc] = sX[rr][cc];
+        if (F) F[(size_t)(r0 + rr) * Np + r0 + cc] = sX[rr][cc];
     }
+}
+
+// ------------------------------------------------------------------ explicit inverse of L L^H
+// Batched complex GEMM on 64 x 64 output tiles, O = alpha op(A) B with
+// op(A)[i][k] = A[i][k], or conj(A[k][i]) (trans_a); 4 waves per tile, each
+// on a 32 x 32 quarter as 2 x 2 MFMA fragments (rows i, columns j, reduction
+// k), 16-wide k chunks of op(A) and B staged through double-buffered LDS.
+// Batch entry z: factor f = z / npairs, pair p = z % npairs, operands at
+// base[f] + p stride.  herm: the output is op(A) B with A = B lower
+// triangular (X^H X): only tiles with j0 >= i0, the reduction from k = j0
+// (conj(X[k][i]) X[k][j] vanishes below), each off-diagonal tile mirrored as
+// its conjugate transpose.
+struct GemmBatch {
+    const double2 *A[2], *B[2];
+    double2 *O[2];
+    long long stride;      // element offset between consecutive pairs (A, B and O alike)
+    int lda, ldb, ldo;
+    int M, N, K;           // output rows and columns, reduction length (multiples of 64)
+    int npairs;
+    double alpha;
+    int trans_a, herm;
+};
+
+constexpr int kGT = 64, kGKC = 16, kGLD = kGKC + 1;
+
+__global__ void __launch_bounds__(256, 2) k_cgemm(GemmBatch g, const int32_t *__restrict__ flags) {
+    if (flags[kFlagHalt]) return;
+    __shared__ double2 sA[2][kGT][kGLD];   // [i][k] of op(A)
+    __shared__ double2 sB[2][kGT][kGLD];   // [j][k] of B
+    const int z = blockIdx.z, f = z / g.npairs, p = z - f * g.npairs;
+    const size_t off = (size_t)p * g.stride;
+    const double2 *__restrict__ A = (f ? g.A[1] : g.A[0]) + off;
+    const double2 *__restrict__ B = (f ? g.B[1] : g.B[0]) + off;
+    double2 *__restrict__ O = (f ? g.O[1] : g.O[0]) + off;
+    int ti, tj;
+    if (g.herm) {
+        const int t = blockIdx.x;   // lower-triangle tile (r >= c) -> i = c, j = r
+        int r = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+        while ((r + 1) * (r + 2) / 2 <= t) ++r;
+        while (r * (r + 1) / 2 > t) --r;
+        ti = t - r * (r + 1) / 2;
+        tj = r;
+    } else {
+        const int nt = g.N / kGT;
+        ti = blockIdx.x / nt;
+        tj = blockIdx.x - ti * nt;
+    }
+    const int i0 = ti * kGT, j0 = tj * kGT;
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int row = lane & 15, quarter = lane >> 4;
+    const int wi = 32 * (wave >> 1), wj = 32 * (wave & 1);
+    dbl4 re[2][2], im[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            re[a][c] = dbl4{0, 0, 0, 0};
+            im[a][c] = dbl4{0, 0, 0, 0};
+        }
+    const int kbeg = g.herm ? j0 : 0;
+    const int nch = (g.K - kbeg) / kGKC;
+    // staging: element e = t + 256 m (m < 4); op(A) as [i][k] (64 x 16), B as
+    // [k][j] (16 x 64); held as plain doubles (an array of double2 would be
+    // placed in scratch memory)
+    double rax[4], ray[4], rbx[4], rby[4];
+    auto fetch = [&](int k0) {
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            const int e = t + 256 * m;
+            double2 va;
+            if (g.trans_a) va = cconj(A[(size_t)(k0 + (e >> 6)) * g.lda + i0 + (e & 63)]);
+            else va = A[(size_t)(i0 + (e >> 4)) * g.lda + k0 + (e & 15)];
+            const double2 vb = B[(size_t)(k0 + (e >> 6)) * g.ldb + j0 + (e & 63)];
+            rax[m] = va.x;
+            ray[m] = va.y;
+            rbx[m] = vb.x;
+            rby[m] = vb.y;
+        }
+    };
+    auto stash = [&](int buf) {
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            const int e = t + 256 * m;
+            if (g.trans_a) sA[buf][e & 63][e >> 6] = make_double2(rax[m], ray[m]);
+            else sA[buf][e >> 4][e & 15] = make_double2(rax[m], ray[m]);
+            sB[buf][e & 63][e >> 6] = make_double2(rbx[m], rby[m]);
+        }
+    };
+    if (nch > 0) {
+        fetch(kbeg);
+        stash(0);
+    }
+    __syncthreads();
+    for (int ch = 0; ch < nch; ++ch) {
+        const int buf = ch & 1;
+        const bool more = ch + 1 < nch;
+        if (more) fetch(kbeg + (ch + 1) * kGKC);
+#pragma unroll
+        for (int s4 = 0; s4 < kGKC / 4; ++s4) {
+            const int kk = 4 * s4 + quarter;
+            double2 xv[2], yv[2];
+#pragma unroll
+            for (int a = 0; a < 2; ++a) {
+                xv[a] = sA[buf][wi + 16 * a + row][kk];
+                yv[a] = sB[buf][wj + 16 * a + row][kk];
+            }
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int c = 0; c < 2; ++c) {
+                    // x y = (xr yr - xi yi) + i (xr yi + xi yr)
+                    re[a][c] = mfma(xv[a].x, yv[c].x, re[a][c]);
+                    re[a][c] = mfma(-xv[a].y, yv[c].y, re[a][c]);
+                    im[a][c] = mfma(xv[a].x, yv[c].y, im[a][c]);
+                    im[a][c] = mfma(xv[a].y, yv[c].x, im[a][c]);
+                }
+        }
+        if (more) stash(buf ^ 1);
+        __syncthreads();
+    }
+    const bool mirror = g.herm && ti != tj;
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int i = i0 + wi + 16 * a + mfma_row_f64(lane, v);
+                const int j = j0 + wj + 16 * c + row;
+                const double2 o = make_double2(g.alpha * re[a][c][v], g.alpha * im[a][c][v]);
+                O[(size_t)i * g.ldo + j] = o;
+                if (mirror) O[(size_t)j * g.ldo + i] = cconj(o);
+            }
 }
 
 // ------------------------------------------------------------------ RK4 stage solves
@@ -479,6 +615,45 @@ __global__ void __launch_bounds__(256) k_rk_fwd(const double2 *__restrict__ rhs,
     publish_block(&sync[kSyncFwd + B]);
 }
 
+// The RK4 stage update of row ii from its solve x = (S + eps I)^-1 K v:
+// k = -i x; stage 0 stores the initial coefficients C = x.
+__device__ inline void stage_update(int ii, double2 u, int stage, double dt, int N, double2 *__restrict__ C,
+                                    double2 *__restrict__ Cacc, double2 *__restrict__ Cstage,
+                                    double *__restrict__ r, double *__restrict__ R,
+                                    const double *__restrict__ r_new, const double *__restrict__ R_new,
+                                    int32_t *__restrict__ flags) {
+    bool bad = false;
+    if (stage == 0) {
+        C[ii] = (ii < N) ? u : make_double2(0, 0);
+        bad = !(isfinite(u.x) && isfinite(u.y));
+    } else {
+        const double2 k = make_double2(u.y, -u.x);   // -i x
+        const double2 c = C[ii];
+        if (stage == 1) {
+            Cacc[ii] = k;
+            Cstage[ii] = cadd(c, cscale(k, 0.5 * dt));
+        } else if (stage == 2) {
+            Cacc[ii] = cadd(Cacc[ii], cscale(k, 2.0));
+            Cstage[ii] = cadd(c, cscale(k, 0.5 * dt));
+        } else if (stage == 3) {
+            Cacc[ii] = cadd(Cacc[ii], cscale(k, 2.0));
+            Cstage[ii] = cadd(c, cscale(k, dt));
+        } else {
+            const double2 cn = cadd(c, cscale(cadd(Cacc[ii], k), dt / 6.0));
+            C[ii] = cn;
+            bad = !(isfinite(cn.x) && isfinite(cn.y));
+            if (ii < N) {
+                r[ii] = r_new[ii];
+                R[ii] = R_new[ii];
+            }
+        }
+    }
+    if (bad) {
+        atomicOr(&flags[kFlagNonfinite], 1);
+        atomicOr(&flags[kFlagHalt], 1);
+    }
+}
+
 // Backward stage kernel: x_B = L_BB^-H (y_B - sum_{C>B} L_CB^H x_C), blocks
 // from the bottom up; then the RK4 stage update of the block's rows.
 // stage: 1..4; 0 = initial coefficients (C = x).
@@ -531,40 +706,65 @@ __global__ void __launch_bounds__(256) k_rk_bwd(const double2 *__restrict__ L, c
     u.y += __shfl_xor(u.y, 2);
     if (!halted && q == 0) {
         xbuf[r0 + i] = u;
-        // stage update of this block's rows
-        const int ii = r0 + i;
-        bool bad = false;
-        if (stage == 0) {
-            C[ii] = (ii < N) ? u : make_double2(0, 0);
-            bad = !(isfinite(u.x) && isfinite(u.y));
-        } else {
-            const double2 k = make_double2(u.y, -u.x);   // -i x
-            const double2 c = C[ii];
-            if (stage == 1) {
-                Cacc[ii] = k;
-                Cstage[ii] = cadd(c, cscale(k, 0.5 * dt));
-            } else if (stage == 2) {
-                Cacc[ii] = cadd(Cacc[ii], cscale(k, 2.0));
-                Cstage[ii] = cadd(c, cscale(k, 0.5 * dt));
-            } else if (stage == 3) {
-                Cacc[ii] = cadd(Cacc[ii], cscale(k, 2.0));
-                Cstage[ii] = cadd(c, cscale(k, dt));
-            } else {
-                const double2 cn = cadd(c, cscale(cadd(Cacc[ii], k), dt / 6.0));
-                C[ii] = cn;
-                bad = !(isfinite(cn.x) && isfinite(cn.y));
-                if (ii < N) {
-                    r[ii] = r_new[ii];
-                    R[ii] = R_new[ii];
-                }
-            }
-        }
-        if (bad) {
-            atomicOr(&flags[kFlagNonfinite], 1);
-            atomicOr(&flags[kFlagHalt], 1);
-        }
+        stage_update(r0 + i, u, stage, dt, N, C, Cacc, Cstage, r, R, r_new, R_new, flags);
     }
     publish_block(&sync[kSyncBwd + B]);
+}
+
+// Stages through the explicit inverse, with one step of iterative
+// refinement: x0 = A^-1 rhs (k_matvec), res = rhs - A x0 (k_rk_resid, A
+// formed from S as in the assembly), x = x0 + A^-1 res (k_rk_apply, then the
+// stage update of the row).  The refinement brings the explicit inverse's
+// error, of the order of cond(A) times its rounding, back to that of a
+// solve with the factor.  One wave per row, four rows per work-group.
+__global__ void __launch_bounds__(256) k_rk_resid(const double2 *__restrict__ Sa, const double2 *__restrict__ Sb,
+                                                  double eps, const double2 *__restrict__ x,
+                                                  const double2 *__restrict__ rhs, double2 *__restrict__ res, int Np,
+                                                  const int32_t *__restrict__ flags) {
+    if (flags[kFlagHalt]) return;
+    const int lane = threadIdx.x & 63;
+    const int rowi = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const double2 *ma = Sa + (size_t)rowi * Np;
+    const double2 *mb = Sb ? Sb + (size_t)rowi * Np : nullptr;
+    double2 acc = make_double2(0, 0);
+    for (int c = lane; c < Np; c += 64) {
+        const double reg = (c == rowi) ? eps : 0.0;
+        const double2 sa = ma[c];
+        double2 a;
+        if (mb) {                                    // midpoint: (S_a + S_b) / 2 + eps I
+            const double2 sb = mb[c];
+            a = make_double2(0.5 * (sa.x + sb.x) + reg, 0.5 * (sa.y + sb.y));
+        } else {                                     // endpoint: S_a + eps I
+            a = make_double2(sa.x + reg, sa.y);
+        }
+        acc = cadd(acc, cmul(a, x[c]));
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        acc.x += __shfl_xor(acc.x, off);
+        acc.y += __shfl_xor(acc.y, off);
+    }
+    if (lane == 0) res[rowi] = csub(rhs[rowi], acc);
+}
+
+__global__ void __launch_bounds__(256) k_rk_apply(const double2 *__restrict__ Sinv, const double2 *__restrict__ res,
+                                                  const double2 *__restrict__ x0, int Np, int stage, double dt, int N,
+                                                  double2 *__restrict__ C, double2 *__restrict__ Cacc,
+                                                  double2 *__restrict__ Cstage, double *__restrict__ r,
+                                                  double *__restrict__ R, const double *__restrict__ r_new,
+                                                  const double *__restrict__ R_new, int32_t *__restrict__ flags) {
+    if (flags[kFlagHalt]) return;
+    const int lane = threadIdx.x & 63;
+    const int rowi = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const double2 *m = Sinv + (size_t)rowi * Np;
+    double2 acc = make_double2(0, 0);
+    for (int c = lane; c < Np; c += 64) acc = cadd(acc, cmul(m[c], res[c]));
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        acc.x += __shfl_xor(acc.x, off);
+        acc.y += __shfl_xor(acc.y, off);
+    }
+    if (lane == 0) stage_update(rowi, cadd(x0[rowi], acc), stage, dt, N, C, Cacc, Cstage, r, R, r_new, R_new, flags);
 }
 
 __global__ void k_fill_i32(int32_t *p, int n, int32_t v) {
@@ -585,7 +785,7 @@ void launch_assemble(const Dims &d, const Bufs &b, int parity, AssemblePart part
 }
 
 void launch_cholesky(const Dims &d, const Bufs &b, double2 *A0, double2 *A1, double2 *X0, double2 *X1, int count,
-                     hipStream_t s) {
+                     hipStream_t s, double2 *S0, double2 *S1) {
     const int Np = padded(d.N);
     for (int kb = 0; kb < Np; kb += NB) {
         const int below = Np - kb - NB;
@@ -599,7 +799,50 @@ void launch_cholesky(const Dims &d, const Bufs &b, double2 *A0, double2 *A1, dou
         }
     }
     hipLaunchKernelGGL(k_chol_flush, dim3(1, count), dim3(256), 0, s, A0, A1, Np, Np - NB, b.chol_diag, b.flags);
-    hipLaunchKernelGGL(k_tri_inv, dim3(Np / NB, count), dim3(256), 0, s, A0, A1, X0, X1, Np, b.flags);
+    double2 *F0 = S0 ? b.Xinv[0] : nullptr, *F1 = S0 ? b.Xinv[1] : nullptr;
+    hipLaunchKernelGGL(k_tri_inv, dim3(Np / NB, count), dim3(256), 0, s, A0, A1, X0, X1, F0, F1, Np, b.flags);
+    if (!S0) return;
+    // X = L^-1 by block recursion, [[A, 0], [C, D]]^-1 = [[A', 0], [-D' C A', D']],
+    // from the 64 x 64 diagonal inverses up: at block size h, the Np / (2 h) pairs
+    // of every factor take T = C A' and then -D' T (X's upper triangle stays zero)
+    const double2 *L2[2] = {A0, A1};
+    for (int h = NB; h < Np; h *= 2) {
+        GemmBatch g{};
+        g.lda = g.ldb = g.ldo = Np;
+        g.M = g.N = g.K = h;
+        g.npairs = Np / (2 * h);
+        g.stride = 2LL * h * (Np + 1);
+        const dim3 grid((h / kGT) * (h / kGT), 1, count * g.npairs);
+        for (int f = 0; f < 2; ++f) {                      // T = C A'
+            g.A[f] = L2[f] + (size_t)h * Np;
+            g.B[f] = b.Xinv[f];
+            g.O[f] = b.Tinv[f] + (size_t)h * Np;
+        }
+        g.alpha = 1.0;
+        hipLaunchKernelGGL(k_cgemm, grid, dim3(256), 0, s, g, b.flags);
+        for (int f = 0; f < 2; ++f) {                      // X_DA = -D' T
+            g.A[f] = b.Xinv[f] + (size_t)h * Np + h;
+            g.B[f] = b.Tinv[f] + (size_t)h * Np;
+            g.O[f] = b.Xinv[f] + (size_t)h * Np;
+        }
+        g.alpha = -1.0;
+        hipLaunchKernelGGL(k_cgemm, grid, dim3(256), 0, s, g, b.flags);
+    }
+    // (L L^H)^-1 = X^H X: upper tiles, mirrored
+    GemmBatch g{};
+    g.lda = g.ldb = g.ldo = Np;
+    g.M = g.N = g.K = Np;
+    g.npairs = 1;
+    g.alpha = 1.0;
+    g.trans_a = 1;
+    g.herm = 1;
+    double2 *S2[2] = {S0, S1};
+    for (int f = 0; f < 2; ++f) {
+        g.A[f] = g.B[f] = b.Xinv[f];
+        g.O[f] = S2[f];
+    }
+    const int T = Np / kGT;
+    hipLaunchKernelGGL(k_cgemm, dim3(T * (T + 1) / 2, 1, count), dim3(256), 0, s, g, b.flags);
 }
 
 void launch_rk4(const Dims &d, const Bufs &b, int parity, hipStream_t s) {
@@ -608,9 +851,21 @@ void launch_rk4(const Dims &d, const Bufs &b, int parity, hipStream_t s) {
     const double2 *Ks[4] = {b.Kmat[cur], b.Kmid, b.Kmid, b.Kminus};
     const double2 *Ls[4] = {b.L[cur], b.Lmid, b.Lmid, b.L[nxt]};
     const double2 *Xs[4] = {b.Linv[cur], b.Linvmid, b.Linvmid, b.Linv[nxt]};
+    const double2 *Ss[4] = {b.Sinv[cur], b.Sinvmid, b.Sinvmid, b.Sinv[nxt]};
     for (int st = 1; st <= 4; ++st) {
         const double2 *v = (st == 1) ? b.C : b.Cstage;
         hipLaunchKernelGGL(k_matvec, dim3(Np / 4), dim3(256), 0, s, Ks[st - 1], v, b.rhs, Np, b.flags);
+        if (d.sinv) {
+            // A of the stage: S_k + eps I, the midpoint average + eps I (stages 2, 3), S_k+1 + eps I
+            const double2 *Sa = st == 4 ? b.Smat[nxt] : b.Smat[cur];
+            const double2 *Sb = (st == 2 || st == 3) ? b.Smat[nxt] : nullptr;
+            hipLaunchKernelGGL(k_matvec, dim3(Np / 4), dim3(256), 0, s, Ss[st - 1], b.rhs, b.y, Np, b.flags);
+            hipLaunchKernelGGL(k_rk_resid, dim3(Np / 4), dim3(256), 0, s, Sa, Sb, d.eps, b.y, b.rhs, b.xsol, Np,
+                               b.flags);
+            hipLaunchKernelGGL(k_rk_apply, dim3(Np / 4), dim3(256), 0, s, Ss[st - 1], b.xsol, b.y, Np, st, d.dt,
+                               d.N, b.C, b.Cacc, b.Cstage, b.r, b.R, b.r_new, b.R_new, b.flags);
+            continue;
+        }
         hipLaunchKernelGGL(k_rk_fwd, dim3(nblk), dim3(256), 0, s, b.rhs, Ls[st - 1], Xs[st - 1], b.y, Np,
                            b.solve_sync, b.flags);
         hipLaunchKernelGGL(k_rk_bwd, dim3(nblk), dim3(256), 0, s, Ls[st - 1], Xs[st - 1], b.y, b.xsol, Np, nblk, st,

@@ -73,6 +73,26 @@ def test_bench_case_three_steps():
     assert s_norm_diff(got["C"], st.C, st.S) < 1e-9
 
 
+def test_bench_case_three_steps_mixed():
+    """The same case in the mixed form (FP32 residual contraction; RK4 stages
+    through the explicit inverses with one refinement step, like the FP64
+    form at this size): observables within the mixed form's 1e-5."""
+    wl = inputs.preset("sm_n1024", n_bo=3)
+    print(f"[case] {wl.name}: 3 steps, mixed, oracle vs GPU", flush=True)
+    setup = setup_for(wl)
+    st = init_for(setup, wl)
+    sim = icwf.Simulation.from_workload(wl, precision=icwf.PREC_MIXED)
+    for _ in range(3):
+        st = oicwf.step(setup, st)
+    sim.step(3)
+    o = sim.observables()
+    ref = oicwf.observe(setup, st, wl.bo)
+    sim.close()
+    assert abs(o["norm"] - ref["norm"]) < 1e-5
+    for key in ("rho_r", "rho_R", "pop", "D"):
+        assert rel_max(o[key], ref[key]) < 1e-5, key
+
+
 @pytest.mark.parametrize("precision", [icwf.PREC_FP64, icwf.PREC_MIXED])
 def test_large_grid_contraction_sampled(precision, rng):
     """N = 4096 CWFs on a 4096 x 512 grid (the contraction stress size):

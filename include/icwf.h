@@ -82,6 +82,22 @@ typedef enum {
                             when no such sum exists                                 */
 } icwf_precision;
 
+/* How the RK4 stages solve (S + eps I) x = r (Eq. 8).  Both factor S + eps I
+ * by Cholesky at every step; they differ in what the stages apply. */
+typedef enum {
+    ICWF_SOLVER_AUTO = 0,       /* explicit inverses where they hide beside the
+                                   contraction (FP64 and mixed forms, from 1024
+                                   padded trajectories, a power of two), else
+                                   triangular solves                             */
+    ICWF_SOLVER_TRIANGULAR = 1, /* forward and backward substitution with the factor */
+    ICWF_SOLVER_INVERSE = 2     /* (S + eps I)^-1 = L^-H L^-1 formed per step, each
+                                   stage x0 = A^-1 r plus one refinement step
+                                   x0 + A^-1 (r - A x0); needs the padded N (the
+                                   next multiple of 64) to be a power of two,
+                                   else ICWF_EINVAL; 7 more N x N complex
+                                   matrices of workspace                       */
+} icwf_solver;
+
 typedef struct {
     int32_t n_traj;          /* N: trajectories = basis size of Eq. 7 (the paper's M)   */
     int32_t n_r, n_R;        /* grid points: powers of two, 32 <= n <= 4096             */
@@ -94,6 +110,7 @@ typedef struct {
     double tikhonov_eps;     /* eps >= 0 of (S + eps I); S_aa = 1 for unit-norm CWFs    */
     int32_t precision;       /* icwf_precision                                          */
     int32_t n_bo;            /* BO states used by the populations (0: none)             */
+    int32_t solver;          /* icwf_solver (0: automatic)                              */
 } icwf_config;
 
 /* Observables at the current step (text around the Shin-Metiu figure of the

@@ -91,7 +91,7 @@ Bufs carve(const icwf_config &c, char *base, size_t *total) {
     b.Linvmid = L.take<double2>(Np * icwf::kCholNb);
     {
         // explicit inverses for the RK4 stages (see use_sinv)
-        const size_t nn = icwf::use_sinv((int)Np, c.precision) ? Np * Np : 1;
+        const size_t nn = icwf::use_sinv((int)Np, c.precision, c.solver) ? Np * Np : 1;
         for (double2 **m : {&b.Xinv[0], &b.Xinv[1], &b.Tinv[0], &b.Tinv[1], &b.Sinv[0], &b.Sinv[1], &b.Sinvmid})
             *m = L.take<double2>(nn);
     }
@@ -120,6 +120,9 @@ const char *validate(const icwf_config *c) {
     if (c->precision != ICWF_PREC_FP64 && c->precision != ICWF_PREC_MIXED && c->precision != ICWF_PREC_SEPARABLE)
         return "unknown precision";
     if (c->n_bo < 0 || c->n_bo > c->n_r) return "n_bo must be in [0, n_r]";
+    if (c->solver < ICWF_SOLVER_AUTO || c->solver > ICWF_SOLVER_INVERSE) return "unknown solver";
+    if (c->solver == ICWF_SOLVER_INVERSE && !icwf::use_sinv(icwf::padded(c->n_traj), c->precision, c->solver))
+        return "the explicit-inverse solver needs the padded N (next multiple of 64) to be a power of two";
     for (int i = 0; i < 8; ++i)
         if (!std::isfinite(c->model_params[i])) return "model parameters must be finite";
     if (c->model == ICWF_MODEL_SHIN_METIU) {
@@ -401,7 +404,7 @@ icwf_status icwf_create(const icwf_config *cfg, const double *r0, const double *
     d.nR = nR;
     d.n_bo = nbo;
     d.prec = cfg->precision;
-    d.sinv = icwf::use_sinv(icwf::padded(N), cfg->precision) ? 1 : 0;
+    d.sinv = icwf::use_sinv(icwf::padded(N), cfg->precision, cfg->solver) ? 1 : 0;
     d.r_min = cfg->r_min;
     d.hr = (cfg->r_max - cfg->r_min) / nr;
     d.R_min = cfg->R_min;

@@ -87,12 +87,16 @@ struct Bufs {
     double *scal;                         // small device scalars (min |Psi|, ...)
 };
 
-// RK4 through explicit inverses of S + eps I: where the factorisations run on
-// the second stream beside a contraction long enough to hide the inversion
-// (FP64 and mixed forms, from 1024 padded trajectories, a power of two so
-// that the block inversion halves evenly).
-inline bool use_sinv(int Np, int precision) {
-    return Np >= 1024 && (Np & (Np - 1)) == 0 && precision != 2;
+// RK4 through explicit inverses of S + eps I.  Automatic choice: where the
+// factorisations run on the second stream beside a contraction long enough
+// to hide the inversion (FP64 and mixed forms, from 1024 padded
+// trajectories).  Either way Np must be a power of two, so that the block
+// inversion halves evenly.  solver: 0 automatic, 1 triangular, 2 inverse.
+inline bool use_sinv(int Np, int precision, int solver) {
+    const bool pow2 = (Np & (Np - 1)) == 0;
+    if (solver == 2) return pow2;
+    if (solver == 1) return false;
+    return Np >= 1024 && pow2 && precision != 2;
 }
 
 // ---- launchers (each defined next to its kernels) -------------------------------------------

@@ -52,10 +52,30 @@ def test_workspace_bytes_scales_with_n_squared():
     assert icwf.workspace_bytes(_cfg(n_traj=65)) == icwf.workspace_bytes(_cfg(n_traj=128))
 
 
+def test_workspace_holds_the_explicit_inverses_only_where_they_are_used():
+    def extra(n):  # seven n x n complex128 matrices in place of 256-byte-aligned single elements
+        return 7 * (16 * n * n - 256)
+
+    tri64 = icwf.workspace_bytes(_cfg(n_traj=64, solver=icwf.SOLVER_TRIANGULAR))
+    assert icwf.workspace_bytes(_cfg(n_traj=64)) == tri64
+    assert icwf.workspace_bytes(_cfg(n_traj=64, solver=icwf.SOLVER_INVERSE)) >= tri64 + extra(64)
+    auto = icwf.workspace_bytes(_cfg(n_traj=1024))
+    tri = icwf.workspace_bytes(_cfg(n_traj=1024, solver=icwf.SOLVER_TRIANGULAR))
+    assert icwf.workspace_bytes(_cfg(n_traj=1024, solver=icwf.SOLVER_INVERSE)) == auto
+    assert auto >= tri + extra(1024)
+    # the separable form keeps the triangular solves unless asked
+    sep = icwf.workspace_bytes(_cfg(n_traj=1024, precision=icwf.PREC_SEPARABLE))
+    assert icwf.workspace_bytes(_cfg(n_traj=1024, precision=icwf.PREC_SEPARABLE,
+                                     solver=icwf.SOLVER_INVERSE)) >= sep + extra(1024)
+    # padded N = 192 is not a power of two: automatic falls back to the triangular solves
+    assert icwf.workspace_bytes(_cfg(n_traj=150)) == icwf.workspace_bytes(_cfg(n_traj=150, solver=1))
+
+
 @pytest.mark.parametrize("bad", [dict(n_traj=0), dict(n_traj=5000), dict(n_r=500), dict(n_R=8),
                                  dict(r_box=(1, 1)), dict(m_r=0.0), dict(dt=-0.1), dict(eps=-1.0),
                                  dict(model=7), dict(precision=3), dict(n_bo=-1), dict(n_bo=1000),
-                                 dict(model_params=[19.0, 0.0, 3.1, 4.0])])
+                                 dict(model_params=[19.0, 0.0, 3.1, 4.0]), dict(solver=3), dict(solver=-1),
+                                 dict(n_traj=150, solver=icwf.SOLVER_INVERSE)])
 def test_invalid_configs_are_rejected_on_the_host(bad):
     cfg = _cfg(**bad)
     assert icwf.workspace_bytes(cfg) == 0

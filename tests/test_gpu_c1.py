@@ -30,8 +30,8 @@ def c1():
     return wl, hist
 
 
-def _gpu_history(wl, precision):
-    sim = icwf.Simulation.from_workload(wl, precision=precision)
+def _gpu_history(wl, precision, solver=icwf.SOLVER_AUTO):
+    sim = icwf.Simulation.from_workload(wl, precision=precision, solver=solver)
     out = []
     for _ in range(STEPS // EVERY):
         sim.step(EVERY)
@@ -60,6 +60,17 @@ def test_fp64_matches_oracle(c1):
     for key in ("rho_r", "rho_R", "pop", "D", "norm"):
         assert w[key] < 1e-10, key
     assert gpu[-1]["n_out_of_box"] == ref[-1]["n_out_of_box"]
+
+
+def test_fp64_with_explicit_inverses_matches_oracle(c1):
+    """RK4 stages through (S + eps I)^-1 = L^-H L^-1 and one refinement step
+    (the solver the library picks from 1024 trajectories), here forced at
+    N = 64: the FP64 bar over 200 steps."""
+    wl, ref = c1
+    gpu = _gpu_history(wl, icwf.PREC_FP64, icwf.SOLVER_INVERSE)
+    w = _compare(gpu, ref)
+    for key in ("rho_r", "rho_R", "pop", "D", "norm"):
+        assert w[key] < 1e-10, key
 
 
 def test_mixed_within_1e5(c1):

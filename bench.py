@@ -187,13 +187,17 @@ def main():
     wc_avg_s = ms_wc / 1e3 / n_wc
     achieved = wc_flops / wc_avg_s / 1e12
     n_zg, ms_zg = kt["zgemm"]
-    # S/H build: the contraction plus the single-species integrals.  The FP64
-    # step runs the integrals on the second stream beside the contraction from
-    # 1024 padded trajectories on, unless that stream carries the explicit
-    # inverses of S + eps I (a power-of-two padded count): the build then spans
-    # the longer of the two; otherwise they run one after the other.
+    # S/H build: the contraction plus the single-species integrals.  From 1024
+    # padded trajectories the step runs the integrals on the second stream
+    # beside the contraction where that stream has room: FP64 without the
+    # explicit inverses of S + eps I (used for a power-of-two padded count), or
+    # a dense contraction with n_r n_R >= 256 Np.  The build then spans the
+    # longer of the two; otherwise they run one after the other.
     Np = (N + 63) // 64 * 64
-    concurrent = args.precision == "fp64" and Np >= 1024 and (Np & (Np - 1)) != 0
+    dense = args.precision != "separable"
+    sinv = Np >= 1024 and (Np & (Np - 1)) == 0 and dense
+    roomy = dense and nr * nR >= 256 * Np
+    concurrent = Np >= 1024 and ((args.precision == "fp64" and not sinv) or roomy)
     build_ms = max(ms_wc, ms_zg) if concurrent else ms_wc + ms_zg
     build_tflops = (wc_flops + single_flops) / (build_ms / 1e3 / n_wc) / 1e12
     build_tflops_summed = (wc_flops + single_flops) / ((ms_wc + ms_zg) / 1e3 / n_wc) / 1e12

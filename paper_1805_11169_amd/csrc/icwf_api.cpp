@@ -282,9 +282,13 @@ void enqueue_step(icwf_sim *s, int parity, hipStream_t st, hipStream_t side) {
     });
     const bool fork = side != st;
     // the single-species integrals join the side stream where the contraction
-    // is the longer branch (FP64 without the explicit inverses, which take that
-    // room on the side stream); otherwise they stay on st, ahead of the fork
-    const hipStream_t ss = fork && d.prec == ICWF_PREC_FP64 && !d.sinv ? side : st;
+    // leaves room beside the factorisations: FP64 without the explicit inverses
+    // (which otherwise take that room), or a dense contraction whose cost per
+    // pair, n_r n_R, is at least 256 N (the factorisations and inversions, N^3,
+    // then take a small part of its time); otherwise they stay on st, ahead of
+    // the fork
+    const bool roomy = d.prec != ICWF_PREC_SEPARABLE && (size_t)d.nr * d.nR >= 256 * (size_t)s->Np;
+    const hipStream_t ss = fork && ((d.prec == ICWF_PREC_FP64 && !d.sinv) || roomy) ? side : st;
     auto single_species = [&] {
         timed(s, "zgemm", ss, [&] {
             icwf::launch_cond_kets(d, b, ss);

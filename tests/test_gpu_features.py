@@ -138,3 +138,20 @@ def test_explicit_inverse_and_triangular_solves_agree(n):
         assert rel_max(o1[key], o2[key]) < 1e-10, key
     size = np.sqrt(abs(np.conj(s1["C"]) @ S1 @ s1["C"]))
     assert s_norm_diff(s1["C"], s2["C"], S1) < 1e-9 * size
+
+
+def test_forked_step_with_the_integrals_beside_the_contraction():
+    """N = 1024 on a 512 x 512 grid: the dense contraction is long enough that
+    the single-species integrals run on the factorisation stream beside it.
+    Replay and eager launches agree bitwise; the result agrees with the
+    separable form (FP64 throughout, integrals ahead of the fork) at the FP64
+    bar."""
+    w = inputs.gaussian_basis(1024, n_r=512, n_R=512, seed=24)
+    print(f"[case] {w.name}: integrals on the side stream, 3 steps", flush=True)
+    a = _run(w, 3)
+    assert _same(a, _run(w, 3, timing=True))
+    sep = _run(w, 3, precision=icwf.PREC_SEPARABLE)
+    for key in ("r", "R"):
+        assert np.max(np.abs(a[key] - sep[key])) < 1e-10 * max(1.0, np.max(np.abs(a[key]))), key
+    assert rel_max(sep["psi1"], a["psi1"]) < 1e-10
+    assert rel_max(sep["psi2"], a["psi2"]) < 1e-10

@@ -33,3 +33,22 @@ def reduced_density_R(Psi, hr):
 
 def reduced_density_r(Psi, hR):
     return hR * np.sum(np.abs(Psi) ** 2, axis=1)
+
+
+def bo_projections(Psi, bo, hr):
+    """chi[n, j] = <phi_n(.; R_j)|Psi(., R_j)>_r = hr sum_i phi_n(r_i; R_j) Psi(r_i, R_j)
+    (real BO states bo[j, n, i]), the projection the paper's populations use."""
+    return hr * np.einsum("jni,ij->nj", bo, Psi)
+
+
+def observables(Psi, hr, hR, bo=None):
+    """norm, rho_r, rho_R and, with BO states, P_n and D_nm of a wavefunction on
+    the grid, with the same definitions as the ansatz's observables."""
+    rho_r = reduced_density_r(Psi, hR)
+    rho_R = reduced_density_R(Psi, hr)
+    out = dict(norm=float(hr * np.sum(rho_r)), rho_r=rho_r, rho_R=rho_R)
+    if bo is not None:
+        dens = np.abs(bo_projections(Psi, bo, hr)) ** 2
+        out["pop"] = hR * np.sum(dens, axis=1)
+        out["D"] = hR * dens @ dens.T
+    return out

@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "../../include/icwf.h"
+#include "../../include/icwf_exact.h"
 #include "icwf_plan.hpp"
 
 using icwf::Bufs;
@@ -740,6 +741,171 @@ const char *icwf_status_string(int32_t st) {
         case ICWF_ETIMEDOUT: return "ICWF_ETIMEDOUT";
         default: return "unknown";
     }
+}
+
+}  // extern "C"
+
+// ---- exact grid propagation of the full wavefunction (icwf_exact.h) -----------------------------
+
+struct icwf_exact {
+    icwf_config cfg{};
+    hipStream_t stream = nullptr;
+    icwf::ExactBufs e{};
+    double *bo = nullptr;
+    double2 *chi = nullptr;
+    double *out = nullptr;
+    double hr = 0, hR = 0;
+    int64_t step = 0;
+};
+
+namespace {
+
+icwf::ExactBufs carve_exact(const icwf_config &c, char *base, size_t *total, double **bo, double2 **chi,
+                            double **out) {
+    Layout L;
+    L.base = base;
+    const size_t nr = c.n_r, nR = c.n_R, nbo = c.n_bo;
+    icwf::ExactBufs e{};
+    e.psi = L.take<double2>(nr * nR);
+    e.tmp = L.take<double2>(nr * nR);
+    e.half = L.take<double2>(nr * nR);
+    e.kinT = L.take<double2>(nr * nR);
+    e.tw_r = L.take<double2>(nr / 2);
+    e.tw_R = L.take<double2>(nR / 2);
+    *bo = L.take<double>(std::max<size_t>(1, nR * nbo * nr));
+    *chi = L.take<double2>(std::max<size_t>(1, nbo * nR));
+    *out = L.take<double>(obs_len(c.n_r, c.n_R, c.n_bo));
+    *total = (L.off + 255) & ~size_t(255);
+    return e;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t icwf_exact_workspace_bytes(const icwf_config *cfg) {
+    if (validate(cfg)) return 0;
+    size_t total = 0;
+    double *bo;
+    double2 *chi;
+    double *out;
+    carve_exact(*cfg, nullptr, &total, &bo, &chi, &out);
+    return total;
+}
+
+icwf_status icwf_exact_create(const icwf_config *cfg, const double *psi0, const double *bo_states, void *workspace,
+                              size_t ws_bytes, void *hip_stream, icwf_exact **out) {
+    if (!out) return fail(nullptr, ICWF_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (const char *m = validate(cfg)) return fail(nullptr, ICWF_EINVAL, m);
+    if (!psi0) return fail(nullptr, ICWF_EINVAL, "psi0 is required");
+    if (cfg->n_bo > 0 && !bo_states) return fail(nullptr, ICWF_EINVAL, "n_bo > 0 needs bo_states");
+    if (!workspace || (reinterpret_cast<uintptr_t>(workspace) & 255))
+        return fail(nullptr, ICWF_EINVAL, "workspace must be non-NULL and 256-byte aligned");
+    if (ws_bytes < icwf_exact_workspace_bytes(cfg)) return fail(nullptr, ICWF_EINVAL, "workspace too small");
+    const int nr = cfg->n_r, nR = cfg->n_R, nbo = cfg->n_bo;
+    const size_t np = (size_t)nr * nR;
+    for (size_t e = 0; e < 2 * np; ++e)
+        if (!std::isfinite(psi0[e])) return fail(nullptr, ICWF_ENONFINITE, "non-finite psi0");
+    if (nbo > 0)
+        for (size_t e = 0; e < (size_t)nR * nbo * nr; ++e)
+            if (!std::isfinite(bo_states[e])) return fail(nullptr, ICWF_ENONFINITE, "non-finite bo_states");
+
+    const double hr = (cfg->r_max - cfg->r_min) / nr, hR = (cfg->R_max - cfg->R_min) / nR, dt = cfg->dt;
+    // half-step phase of the full interaction W = V_1 + V_2 + W_c on the grid
+    std::vector<double2> half(np), kinT(np), tw_r(nr / 2), tw_R(nR / 2);
+    for (int i = 0; i < nr; ++i) {
+        const double r = cfg->r_min + i * hr;
+        for (int j = 0; j < nR; ++j) {
+            const double R = cfg->R_min + j * hR;
+            const double w = h_v1(*cfg, r) + h_v2(*cfg, R) + h_wc(*cfg, r, R);
+            if (!std::isfinite(w)) return fail(nullptr, ICWF_ENONFINITE, "the model is singular on the grid");
+            half[(size_t)i * nR + j] = make_double2(std::cos(-0.5 * dt * w), std::sin(-0.5 * dt * w));
+        }
+    }
+    // kinetic phase of both species, transposed ([k_R][k_r]), times 1/(n_r n_R)
+    // (the normalisation of the inverse transform; exact, both are powers of two)
+    const double inv = 1.0 / ((double)nr * nR);
+    for (int kR = 0; kR < nR; ++kR) {
+        const int mR = (kR <= nR / 2) ? kR : kR - nR;
+        const double kwR = 2.0 * M_PI * mR / (nR * hR);
+        for (int kr = 0; kr < nr; ++kr) {
+            const int mr = (kr <= nr / 2) ? kr : kr - nr;
+            const double kwr = 2.0 * M_PI * mr / (nr * hr);
+            const double ph = -dt * (kwr * kwr / (2.0 * cfg->m_r) + kwR * kwR / (2.0 * cfg->m_R));
+            kinT[(size_t)kR * nr + kr] = make_double2(std::cos(ph) * inv, std::sin(ph) * inv);
+        }
+    }
+    for (int k = 0; k < nr / 2; ++k) tw_r[k] = make_double2(std::cos(-2.0 * M_PI * k / nr), std::sin(-2.0 * M_PI * k / nr));
+    for (int k = 0; k < nR / 2; ++k) tw_R[k] = make_double2(std::cos(-2.0 * M_PI * k / nR), std::sin(-2.0 * M_PI * k / nR));
+
+    icwf_exact *x = new icwf_exact();
+    x->cfg = *cfg;
+    x->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    x->hr = hr;
+    x->hR = hR;
+    size_t total = 0;
+    x->e = carve_exact(*cfg, reinterpret_cast<char *>(workspace), &total, &x->bo, &x->chi, &x->out);
+    const hipStream_t st = x->stream;
+    auto copy = [&](void *dst, const void *src, size_t bytes) {
+        return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st) == hipSuccess;
+    };
+    bool ok = hipMemsetAsync(workspace, 0, total, st) == hipSuccess && copy(x->e.psi, psi0, sizeof(double2) * np) &&
+              copy(x->e.half, half.data(), sizeof(double2) * np) && copy(x->e.kinT, kinT.data(), sizeof(double2) * np) &&
+              copy(x->e.tw_r, tw_r.data(), sizeof(double2) * tw_r.size()) &&
+              copy(x->e.tw_R, tw_R.data(), sizeof(double2) * tw_R.size());
+    if (ok && nbo > 0) ok = copy(x->bo, bo_states, sizeof(double) * (size_t)nR * nbo * nr);
+    if (ok) ok = hipStreamSynchronize(st) == hipSuccess;
+    if (!ok) {
+        delete x;
+        return fail(nullptr, ICWF_EDEVICE, std::string("device copy failed: ") + hipGetErrorString(hipGetLastError()));
+    }
+    *out = x;
+    return ICWF_OK;
+}
+
+icwf_status icwf_exact_step(icwf_exact *x, int64_t n_steps) {
+    if (!x || n_steps < 0) return fail(nullptr, ICWF_EINVAL, "bad arguments to icwf_exact_step");
+    for (int64_t k = 0; k < n_steps; ++k) icwf::launch_exact_step(x->cfg.n_r, x->cfg.n_R, x->e, x->stream);
+    if (hipGetLastError() != hipSuccess) return fail(nullptr, ICWF_EDEVICE, "exact step launch failed");
+    x->step += n_steps;
+    return ICWF_OK;
+}
+
+icwf_status icwf_exact_observables(icwf_exact *x, icwf_obs *o) {
+    if (!x || !o) return fail(nullptr, ICWF_EINVAL, "NULL argument");
+    const int nr = x->cfg.n_r, nR = x->cfg.n_R, nbo = x->cfg.n_bo;
+    icwf::launch_grid_observables(x->e.psi, nr, nR, x->hr, x->hR, nbo, x->bo, x->chi, x->out, x->stream);
+    std::vector<double> buf(obs_len(nr, nR, nbo));
+    if (hipMemcpyAsync(buf.data(), x->out, sizeof(double) * buf.size(), hipMemcpyDeviceToHost, x->stream) != hipSuccess ||
+        hipStreamSynchronize(x->stream) != hipSuccess)
+        return fail(nullptr, ICWF_EDEVICE, "observables copy failed");
+    o->t = x->step * x->cfg.dt;
+    o->step = x->step;
+    o->norm = buf[0];
+    if (o->rho_r) std::copy(buf.begin() + 1, buf.begin() + 1 + nr, o->rho_r);
+    if (o->rho_R) std::copy(buf.begin() + 1 + nr, buf.begin() + 1 + nr + nR, o->rho_R);
+    const size_t po = 1 + nr + nR;
+    if (o->pop && nbo) std::copy(buf.begin() + po, buf.begin() + po + nbo, o->pop);
+    if (o->D && nbo) std::copy(buf.begin() + po + nbo, buf.begin() + po + nbo + (size_t)nbo * nbo, o->D);
+    o->n_out_of_box = 0;
+    o->min_abs_psi = 0.0;
+    return ICWF_OK;
+}
+
+icwf_status icwf_exact_get_psi(icwf_exact *x, double *psi) {
+    if (!x || !psi) return fail(nullptr, ICWF_EINVAL, "NULL argument");
+    const size_t np = (size_t)x->cfg.n_r * x->cfg.n_R;
+    if (hipMemcpyAsync(psi, x->e.psi, sizeof(double2) * np, hipMemcpyDeviceToHost, x->stream) != hipSuccess ||
+        hipStreamSynchronize(x->stream) != hipSuccess)
+        return fail(nullptr, ICWF_EDEVICE, "state copy failed");
+    return ICWF_OK;
+}
+
+void icwf_exact_destroy(icwf_exact *x) {
+    if (!x) return;
+    (void)hipStreamSynchronize(x->stream);
+    delete x;
 }
 
 }  // extern "C"

@@ -148,6 +148,23 @@ void launch_commit_positions(const Dims &d, const Bufs &b, hipStream_t s);
 // Observables into b.obs_out (layout in icwf_api.cpp).
 void launch_observables(const Dims &d, const Bufs &b, hipStream_t s);
 
+// Observables of a wavefunction given on the grid, Psi [nr][nR] complex128:
+// out = [norm, rho_r[nr], rho_R[nR], pop[n_bo], D[n_bo][n_bo]]; bo is
+// [nR][n_bo][nr] (real BO states), chi [n_bo][nR] scratch.
+void launch_grid_observables(const double2 *Psi, int nr, int nR, double hr, double hR, int n_bo, const double *bo,
+                             double2 *chi, double *out, hipStream_t s);
+
+// One Strang step of the full two-dimensional wavefunction (Eqs. 1-2 on the
+// product grid; the reference the ansatz converges to):
+//   Psi <- e^{-i W dt/2} IFFT2[ e^{-i T dt} FFT2[ e^{-i W dt/2} Psi ] ].
+// psi [nr][nR] in place, tmp [nR][nr] scratch, half [nr][nR] = e^{-i W dt/2},
+// kinT [nR][nr] = e^{-i (k_r^2/2m_r + k_R^2/2m_R) dt} / (nr nR) (transposed),
+// tw_r [nr/2], tw_R [nR/2] = e^{-2 pi i k/n}.  nr, nR powers of two in [32, 4096].
+struct ExactBufs {
+    double2 *psi, *tmp, *half, *kinT, *tw_r, *tw_R;
+};
+void launch_exact_step(int nr, int nR, const ExactBufs &e, hipStream_t s);
+
 // FP32 copy of psi1 (mixed form; the propagation keeps it current afterwards).
 void launch_psi1_f32(const Dims &d, const Bufs &b, hipStream_t s);
 

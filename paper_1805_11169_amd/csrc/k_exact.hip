@@ -1,0 +1,152 @@
+// Propagation of the full two-dimensional wavefunction Psi(r_i, R_j) (Eq. 1
+// with the Hamiltonian of Eq. 2 on the product grid), by the same Strang
+// split operator the conditional wavefunctions use, in two dimensions:
+//
+//     Psi <- e^{-i W dt/2} IFFT2[ e^{-i (k_r^2/2m_r + k_R^2/2m_R) dt} FFT2[ e^{-i W dt/2} Psi ] ].
+//
+// This is the reference the ansatz of Eq. 7 converges to as N grows; it
+// stores n_r n_R values where the method stores N (n_r + n_R).
+//
+// Three passes per step, one work-group per grid row, each row transformed
+// in LDS by a radix-2 Stockham FFT (autosort: no bit reversal):
+//   1. rows i of Psi [n_r][n_R]: multiply by the half-step potential phase,
+//      FFT along R, write transposed into tmp [n_R][n_r];
+//   2. rows k_R of tmp: FFT along r, multiply by the kinetic phase (which
+//      carries the 1/(n_r n_R) of the inverse transform), inverse FFT along r,
+//      write transposed back into Psi;
+//   3. rows i of Psi: inverse FFT along R, multiply by the half-step phase.
+// The transposed writes are strided; the whole state is 2 MB at 512 x 256
+// and 32 MB at 4096 x 512, so it stays in the caches between passes.
+
+#include <hip/hip_runtime.h>
+
+#include "icwf_device.hpp"
+#include "icwf_plan.hpp"
+
+namespace icwf {
+namespace {
+
+constexpr int kExactThreads = 256;
+
+// In-LDS FFT of n = 2^LOG2N points, starting in a, unscaled in both
+// directions.  Pass s (Ns = 2^s) combines pairs of length-Ns transforms:
+// butterfly j reads a[j] and a[j + n/2], multiplies the second by
+// e^{-/+ 2 pi i (j mod Ns) / (2 Ns)} and writes the sum and difference to
+// b[(j div Ns) 2 Ns + j mod Ns] and Ns further on.  tw[k] = e^{-2 pi i k / n},
+// k < n/2.  Returns the buffer holding the result; every thread has passed a
+// barrier after the last write.
+template <int LOG2N>
+__device__ double2 *lds_fft(double2 *a, double2 *b, const double2 *__restrict__ tw, bool inverse) {
+    constexpr int n = 1 << LOG2N, h = n / 2;
+    for (int ns = 1; ns < n; ns <<= 1) {
+        const int stride = h / ns;
+        for (int j = threadIdx.x; j < h; j += kExactThreads) {
+            const int k = j & (ns - 1);
+            double2 w = tw[k * stride];
+            if (inverse) w.y = -w.y;
+            const double2 v0 = a[j], v1 = cmul(a[j + h], w);
+            const int o = ((j - k) << 1) + k;
+            b[o] = cadd(v0, v1);
+            b[o + ns] = csub(v0, v1);
+        }
+        __syncthreads();
+        double2 *t = a;
+        a = b;
+        b = t;
+    }
+    return a;
+}
+
+// Pass 1: row i of psi (n = n_R points) -> FFT_R(half_i o psi_i), stored as
+// column i of tmp [n_R][n_r].
+template <int LOG2N>
+__global__ void __launch_bounds__(kExactThreads) k_exact_rows_fwd(const double2 *__restrict__ psi,
+                                                                  const double2 *__restrict__ half,
+                                                                  const double2 *__restrict__ tw,
+                                                                  double2 *__restrict__ tmp, int nr) {
+    constexpr int n = 1 << LOG2N;
+    __shared__ double2 buf[2][n];
+    const size_t row = (size_t)blockIdx.x * n;
+    for (int j = threadIdx.x; j < n; j += kExactThreads) buf[0][j] = cmul(half[row + j], psi[row + j]);
+    __syncthreads();
+    const double2 *res = lds_fft<LOG2N>(buf[0], buf[1], tw, false);
+    for (int k = threadIdx.x; k < n; k += kExactThreads) tmp[(size_t)k * nr + blockIdx.x] = res[k];
+}
+
+// Pass 2: row k_R of tmp (n = n_r points) -> IFFT_r(kin o FFT_r(row)), stored
+// as column k_R of psi [n_r][n_R].
+template <int LOG2N>
+__global__ void __launch_bounds__(kExactThreads) k_exact_cols(const double2 *__restrict__ tmp,
+                                                              const double2 *__restrict__ kinT,
+                                                              const double2 *__restrict__ tw,
+                                                              double2 *__restrict__ psi, int nR) {
+    constexpr int n = 1 << LOG2N;
+    __shared__ double2 buf[2][n];
+    const size_t row = (size_t)blockIdx.x * n;
+    for (int i = threadIdx.x; i < n; i += kExactThreads) buf[0][i] = tmp[row + i];
+    __syncthreads();
+    double2 *f = lds_fft<LOG2N>(buf[0], buf[1], tw, false);
+    double2 *g = (f == buf[0]) ? buf[1] : buf[0];
+    for (int k = threadIdx.x; k < n; k += kExactThreads) f[k] = cmul(kinT[row + k], f[k]);
+    __syncthreads();
+    const double2 *res = lds_fft<LOG2N>(f, g, tw, true);
+    for (int i = threadIdx.x; i < n; i += kExactThreads) psi[(size_t)i * nR + blockIdx.x] = res[i];
+}
+
+// Pass 3: row i of psi (n = n_R points) -> half_i o IFFT_R(psi_i), in place.
+template <int LOG2N>
+__global__ void __launch_bounds__(kExactThreads) k_exact_rows_inv(double2 *__restrict__ psi,
+                                                                  const double2 *__restrict__ half,
+                                                                  const double2 *__restrict__ tw) {
+    constexpr int n = 1 << LOG2N;
+    __shared__ double2 buf[2][n];
+    const size_t row = (size_t)blockIdx.x * n;
+    for (int j = threadIdx.x; j < n; j += kExactThreads) buf[0][j] = psi[row + j];
+    __syncthreads();
+    const double2 *res = lds_fft<LOG2N>(buf[0], buf[1], tw, true);
+    for (int j = threadIdx.x; j < n; j += kExactThreads) psi[row + j] = cmul(half[row + j], res[j]);
+}
+
+template <int L>
+void pass_rows_fwd(int nr, const ExactBufs &e, hipStream_t s) {
+    hipLaunchKernelGGL(k_exact_rows_fwd<L>, dim3(nr), dim3(kExactThreads), 0, s, e.psi, e.half, e.tw_R, e.tmp, nr);
+}
+template <int L>
+void pass_cols(int nR, const ExactBufs &e, hipStream_t s) {
+    hipLaunchKernelGGL(k_exact_cols<L>, dim3(nR), dim3(kExactThreads), 0, s, e.tmp, e.kinT, e.tw_r, e.psi, nR);
+}
+template <int L>
+void pass_rows_inv(int nr, const ExactBufs &e, hipStream_t s) {
+    hipLaunchKernelGGL(k_exact_rows_inv<L>, dim3(nr), dim3(kExactThreads), 0, s, e.psi, e.half, e.tw_R);
+}
+
+// n = 2^lg for lg in [5, 12] (grid sizes 32 ... 4096, checked by the caller).
+#define ICWF_EXACT_DISPATCH(fn, lg, ...)  \
+    switch (lg) {                          \
+    case 5: fn<5>(__VA_ARGS__); break;     \
+    case 6: fn<6>(__VA_ARGS__); break;     \
+    case 7: fn<7>(__VA_ARGS__); break;     \
+    case 8: fn<8>(__VA_ARGS__); break;     \
+    case 9: fn<9>(__VA_ARGS__); break;     \
+    case 10: fn<10>(__VA_ARGS__); break;   \
+    case 11: fn<11>(__VA_ARGS__); break;   \
+    case 12: fn<12>(__VA_ARGS__); break;   \
+    default: break;                        \
+    }
+
+int log2i(int n) {
+    int l = 0;
+    while ((1 << l) < n) ++l;
+    return l;
+}
+
+}  // namespace
+
+void launch_exact_step(int nr, int nR, const ExactBufs &e, hipStream_t s) {
+    const int lr = log2i(nr), lR = log2i(nR);
+    ICWF_EXACT_DISPATCH(pass_rows_fwd, lR, nr, e, s);
+    ICWF_EXACT_DISPATCH(pass_cols, lr, nR, e, s);
+    ICWF_EXACT_DISPATCH(pass_rows_inv, lR, nr, e, s);
+}
+
+}  // namespace icwf

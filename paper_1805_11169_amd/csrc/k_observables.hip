@@ -222,21 +222,24 @@ __global__ void k_obs_pop(const double2 *__restrict__ chi, int nR, int n_bo, dou
 
 }  // namespace
 
+void launch_grid_observables(const double2 *Psi, int nr, int nR, double hr, double hR, int n_bo, const double *bo,
+                             double2 *chi, double *out, hipStream_t s) {
+    double *rho_r = out + 1, *rho_R = out + 1 + nr;
+    hipLaunchKernelGGL(k_obs_rho_r, dim3((nr + 3) / 4), dim3(256), 0, s, Psi, nr, nR, hR, rho_r);
+    hipLaunchKernelGGL(k_obs_rho_R, dim3((nR + 63) / 64), dim3(256), 0, s, Psi, nr, nR, hr, rho_R);
+    hipLaunchKernelGGL(k_obs_norm, dim3(1), dim3(256), 0, s, rho_r, nr, hr, out);
+    if (n_bo > 0) {
+        hipLaunchKernelGGL(k_obs_chi, dim3(nR, n_bo), dim3(64), 0, s, bo, Psi, nr, nR, n_bo, hr, chi);
+        double *pop = out + 1 + nr + nR;
+        hipLaunchKernelGGL(k_obs_pop, dim3(1), dim3(256), 0, s, chi, nR, n_bo, hR, pop, pop + n_bo);
+    }
+}
+
 void launch_observables(const Dims &d, const Bufs &b, hipStream_t s) {
     const int Np = padded(d.N);
-    double *out = b.obs_out;
-    double *rho_r = out + 1, *rho_R = out + 1 + d.nr;
     const dim3 tiles((d.nR + kOT - 1) / kOT, (d.nr + kOT - 1) / kOT);
     hipLaunchKernelGGL(k_obs_psi, tiles, dim3(256), 0, s, b.psi1, b.psi2, b.C, d.nr, d.nR, Np, b.obs_psi);
-    hipLaunchKernelGGL(k_obs_rho_r, dim3((d.nr + 3) / 4), dim3(256), 0, s, b.obs_psi, d.nr, d.nR, d.hR, rho_r);
-    hipLaunchKernelGGL(k_obs_rho_R, dim3((d.nR + 63) / 64), dim3(256), 0, s, b.obs_psi, d.nr, d.nR, d.hr, rho_R);
-    hipLaunchKernelGGL(k_obs_norm, dim3(1), dim3(256), 0, s, rho_r, d.nr, d.hr, out);
-    if (d.n_bo > 0) {
-        hipLaunchKernelGGL(k_obs_chi, dim3(d.nR, d.n_bo), dim3(64), 0, s, b.bo, b.obs_psi, d.nr, d.nR, d.n_bo, d.hr,
-                           b.obs_chi);
-        double *pop = out + 1 + d.nr + d.nR;
-        hipLaunchKernelGGL(k_obs_pop, dim3(1), dim3(256), 0, s, b.obs_chi, d.nR, d.n_bo, d.hR, pop, pop + d.n_bo);
-    }
+    launch_grid_observables(b.obs_psi, d.nr, d.nR, d.hr, d.hR, d.n_bo, b.bo, b.obs_chi, b.obs_out, s);
 }
 
 }  // namespace icwf

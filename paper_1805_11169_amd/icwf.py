@@ -28,6 +28,9 @@ EXPORTS = ("icwf_workspace_bytes", "icwf_create", "icwf_step", "icwf_sync", "icw
 # the entry points include/icwf_serve.h declares
 SERVE_EXPORTS = ("icwf_server_create", "icwf_server_submit", "icwf_server_wait", "icwf_server_result",
                  "icwf_server_get_stats", "icwf_server_clock", "icwf_server_destroy")
+# the entry points include/icwf_exact.h declares
+EXACT_EXPORTS = ("icwf_exact_workspace_bytes", "icwf_exact_create", "icwf_exact_step", "icwf_exact_observables",
+                 "icwf_exact_get_psi", "icwf_exact_destroy")
 
 
 class Config(ctypes.Structure):
@@ -128,6 +131,18 @@ def lib():
         L.icwf_server_clock.restype = c_double
         L.icwf_server_destroy.argtypes = [c_void_p]
         L.icwf_server_destroy.restype = None
+        L.icwf_exact_workspace_bytes.argtypes = [POINTER(Config)]
+        L.icwf_exact_workspace_bytes.restype = c_size_t
+        L.icwf_exact_create.argtypes = [POINTER(Config), _DP, _DP, c_void_p, c_size_t, c_void_p, POINTER(c_void_p)]
+        L.icwf_exact_create.restype = c_int32
+        L.icwf_exact_step.argtypes = [c_void_p, c_int64]
+        L.icwf_exact_step.restype = c_int32
+        L.icwf_exact_observables.argtypes = [c_void_p, POINTER(Obs)]
+        L.icwf_exact_observables.restype = c_int32
+        L.icwf_exact_get_psi.argtypes = [c_void_p, _DP]
+        L.icwf_exact_get_psi.restype = c_int32
+        L.icwf_exact_destroy.argtypes = [c_void_p]
+        L.icwf_exact_destroy.restype = None
         _lib = L
     return _lib
 
@@ -280,6 +295,73 @@ class Simulation:
     def close(self):
         if getattr(self, "h", None):
             lib().icwf_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class ExactPropagator:
+    """Grid propagation of the full wavefunction Psi(r_i, R_j) (include/icwf_exact.h):
+    the reference the ansatz converges to.  psi0 is [n_r][n_R] complex."""
+
+    def __init__(self, cfg, psi0, bo=None, device=0, stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("the ICWF library needs a GPU; none is visible")
+        L = lib()
+        self.cfg = cfg
+        self.n_r, self.n_R, self.n_bo = cfg.n_r, cfg.n_R, cfg.n_bo
+        nbytes = L.icwf_exact_workspace_bytes(byref(cfg))
+        if nbytes == 0:
+            raise ICWFError(EINVAL, "invalid configuration")
+        dev = torch.device("cuda", device) if isinstance(device, int) else torch.device(device)
+        self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
+        aligned = (self.ws.data_ptr() + 255) & ~255
+        self.stream = stream if stream is not None else torch.cuda.current_stream(dev)
+        p0 = np.ascontiguousarray(psi0, dtype=np.complex128)
+        if p0.shape != (cfg.n_r, cfg.n_R):
+            raise ValueError(f"psi0 must be [{cfg.n_r}][{cfg.n_R}]")
+        keep = [_f64(p0), _f64(bo)]
+        handle = c_void_p()
+        st = L.icwf_exact_create(byref(cfg), _ptr(keep[0]), _ptr(keep[1]), c_void_p(aligned), c_size_t(nbytes),
+                                 c_void_p(self.stream.cuda_stream), byref(handle))
+        if st != OK:
+            raise ICWFError(st, L.icwf_last_error(None).decode())
+        self.h = handle
+
+    def _check(self, st):
+        if st != OK:
+            raise ICWFError(st, lib().icwf_last_error(None).decode())
+        return st
+
+    def step(self, n=1):
+        self._check(lib().icwf_exact_step(self.h, int(n)))
+
+    def observables(self):
+        nr, nR, nb = self.n_r, self.n_R, self.n_bo
+        out = dict(rho_r=np.zeros(nr), rho_R=np.zeros(nR), pop=np.zeros(max(nb, 1)), D=np.zeros(max(nb * nb, 1)))
+        o = Obs()
+        for k, v in out.items():
+            setattr(o, k, _ptr(v))
+        self._check(lib().icwf_exact_observables(self.h, byref(o)))
+        res = dict(t=o.t, step=o.step, norm=o.norm, rho_r=out["rho_r"], rho_R=out["rho_R"])
+        if nb:
+            res["pop"] = out["pop"][:nb]
+            res["D"] = out["D"][:nb * nb].reshape(nb, nb)
+        return res
+
+    def psi(self):
+        p = np.zeros((self.n_r, self.n_R), np.complex128)
+        self._check(lib().icwf_exact_get_psi(self.h, _ptr(p.view(np.float64))))
+        return p
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().icwf_exact_destroy(self.h)
             self.h = None
 
     def __del__(self):

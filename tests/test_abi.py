@@ -26,6 +26,7 @@ def declared_entry_points(header=None):
 def test_header_and_binding_agree():
     assert declared_entry_points("icwf.h") == sorted(icwf.EXPORTS)
     assert declared_entry_points("icwf_serve.h") == sorted(icwf.SERVE_EXPORTS)
+    assert declared_entry_points("icwf_exact.h") == sorted(icwf.EXACT_EXPORTS)
 
 
 def test_library_exports_every_declared_symbol():
@@ -108,3 +109,18 @@ def test_too_small_workspace_and_missing_inputs():
                        ctypes.c_size_t(need), None, ctypes.byref(h))
     assert st == icwf.EINVAL          # misaligned workspace
     assert icwf.status_string(icwf.ESOLVE) == "ICWF_ESOLVE"
+
+
+def test_exact_workspace_and_invalid_configs():
+    """The grid propagator's footprint is four n_r n_R complex128 arrays plus
+    small tables; an invalid configuration sizes to 0 and fails creation."""
+    cfg = _cfg(n_r=512, n_R=256, n_bo=0)
+    ex = icwf.lib().icwf_exact_workspace_bytes(ctypes.byref(cfg))
+    assert 4 * 16 * 512 * 256 <= ex < 4 * 16 * 512 * 256 + 64 * 1024
+    bad = _cfg(n_r=500)
+    assert icwf.lib().icwf_exact_workspace_bytes(ctypes.byref(bad)) == 0
+    h = ctypes.c_void_p()
+    one = (ctypes.c_double * 8)()
+    st = icwf.lib().icwf_exact_create(ctypes.byref(bad), one, None, ctypes.c_void_p(256), ctypes.c_size_t(1 << 40),
+                                      None, ctypes.byref(h))
+    assert st == icwf.EINVAL

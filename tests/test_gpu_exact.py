@@ -1,0 +1,101 @@
+"""Grid propagation of the full wavefunction (include/icwf_exact.h, through the
+C ABI) against the oracle's brute-force 2D split-operator propagator.
+
+Bars: the state after the steps within 1e-12 of the oracle's, relative to its
+largest entry (FFTs of different radix and order: a few roundings per
+transform and step); norm, rho_r and rho_R within 1e-12 relative; BO
+populations within 1e-12 of the norm and D within 1e-12 of norm x max rho_R
+(the scales that bound their roundings)."""
+
+import numpy as np
+import pytest
+
+from oracle import exact2d
+from paper_1805_11169_amd import icwf, inputs
+
+from oracle_runs import rel_max, setup_for
+
+pytestmark = pytest.mark.gpu
+
+
+def _correlated_start(wl, seed):
+    """A correlated, moving wavepacket on the grid (not a product)."""
+    rng = np.random.default_rng(seed)
+    r = wl.r_min + (wl.r_max - wl.r_min) / wl.n_r * np.arange(wl.n_r)
+    R = wl.R_min + (wl.R_max - wl.R_min) / wl.n_R * np.arange(wl.n_R)
+    lr, lR = wl.r_max - wl.r_min, wl.R_max - wl.R_min
+    r0, R0 = wl.r_min + lr * rng.uniform(0.4, 0.6), wl.R_min + lR * rng.uniform(0.4, 0.6)
+    x, y = (r[:, None] - r0) / (0.08 * lr), (R[None, :] - R0) / (0.08 * lR)
+    k = 0.2 * np.pi * wl.n_r / lr
+    return np.exp(-0.5 * (x * x + y * y - 1.2 * x * y) + 1j * k * r[:, None]).astype(np.complex128)
+
+
+def _compare(wl, psi0, steps, bo=None, n_bo=0):
+    setup = setup_for(wl)
+    cfg = icwf.config_from_workload(wl)
+    cfg.n_bo = n_bo
+    ex = icwf.ExactPropagator(cfg, psi0, bo=bo)
+    ex.step(steps)
+    got, obs = ex.psi(), ex.observables()
+    ex.close()
+    ref = exact2d.propagate(psi0, setup.Wtab, setup.hr, setup.hR, wl.m_r, wl.m_R, wl.dt, steps)
+    ref_obs = exact2d.observables(ref, setup.hr, setup.hR, bo)
+    assert rel_max(got, ref) < 1e-12
+    assert obs["step"] == steps and abs(obs["t"] - steps * wl.dt) < 1e-12
+    assert abs(obs["norm"] - ref_obs["norm"]) < 1e-12 * ref_obs["norm"]
+    for key in ("rho_r", "rho_R"):
+        assert rel_max(obs[key], ref_obs[key]) < 1e-12, key
+    if n_bo:
+        # populations are parts of the norm, and |chi_n(R_j)|^2 <= rho_R(j)
+        # (Cauchy-Schwarz): the scales their roundings are bounded by, also
+        # where the populations themselves are tiny
+        nrm = ref_obs["norm"]
+        assert np.max(np.abs(obs["pop"] - ref_obs["pop"])) < 1e-12 * nrm
+        assert np.max(np.abs(obs["D"] - ref_obs["D"])) < 1e-12 * nrm * np.max(ref_obs["rho_R"])
+    return got
+
+
+@pytest.mark.parametrize("name,kw", [
+    ("shin_metiu_64x32", dict(n_r=64, n_R=32, model=inputs.MODEL_SHIN_METIU, seed=31)),
+    ("cavity_32x64", dict(n_r=32, n_R=64, model=inputs.MODEL_CAVITY, r_box=(-30.0, 30.0), R_box=(-20.0, 20.0),
+                          seed=32)),
+    ("shin_metiu_128x128", dict(n_r=128, n_R=128, model=inputs.MODEL_SHIN_METIU, seed=33)),
+])
+def test_small_grids_twenty_steps(name, kw):
+    wl = inputs.gaussian_basis(4, **kw)
+    print(f"[case] exact {name}: 20 steps", flush=True)
+    r = wl.r_min + (wl.r_max - wl.r_min) / wl.n_r * np.arange(wl.n_r)
+    R = wl.R_min + (wl.R_max - wl.R_min) / wl.n_R * np.arange(wl.n_R)
+    n_bo = 3
+    bo = inputs.bo_states(wl.model, wl.model_params, r, (wl.r_max - wl.r_min) / wl.n_r, wl.m_r, R, n_bo)
+    _compare(wl, _correlated_start(wl, kw["seed"]), 20, bo=bo, n_bo=n_bo)
+
+
+def test_shin_metiu_parity_grid_from_the_product_start():
+    """512 x 256, Psi_0 = phi_e(r) chi_0(R) (the product start the trajectories
+    are sampled from), 10 steps, three BO states."""
+    wl = inputs.preset("sm_n64", n_bo=3)
+    print(f"[case] exact {wl.name} grid {wl.n_r}x{wl.n_R}: 10 steps", flush=True)
+    psi0 = np.outer(wl.extra["phi_e"], wl.extra["chi0"]).astype(np.complex128)
+    _compare(wl, psi0, 10, bo=wl.bo, n_bo=3)
+
+
+def test_large_grid_three_steps():
+    """4096 x 512 (the largest grid; 4096-point transforms in LDS)."""
+    wl = inputs.gaussian_basis(4, n_r=4096, n_R=512, r_box=(-75.0, 75.0), R_box=(-9.0, 9.0),
+                               model=inputs.MODEL_SHIN_METIU, seed=34)
+    print(f"[case] exact {wl.n_r}x{wl.n_R}: 3 steps", flush=True)
+    _compare(wl, _correlated_start(wl, 34), 3)
+
+
+def test_zero_steps_and_norm_conservation():
+    wl = inputs.gaussian_basis(4, n_r=64, n_R=64, model=inputs.MODEL_SHIN_METIU, seed=35)
+    psi0 = _correlated_start(wl, 35)
+    cfg = icwf.config_from_workload(wl)
+    ex = icwf.ExactPropagator(cfg, psi0)
+    assert np.array_equal(ex.psi(), psi0)
+    n0 = ex.observables()["norm"]
+    ex.step(200)
+    n1 = ex.observables()["norm"]
+    ex.close()
+    assert abs(n1 - n0) < 1e-12 * n0

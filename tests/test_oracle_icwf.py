@@ -56,6 +56,41 @@ def test_exact2d_coupled_oscillators_follow_classical_normal_modes():
     assert 3.5 < errs[0] / errs[1] < 4.5
 
 
+def test_exact2d_observables_equal_the_ansatz_formulas(rng):
+    """On Psi = sum_a C_a psi1^a psi2^a (Eq. 7 on the grid) the grid sums of
+    the exact propagator's observables equal the overlap-based formulas of
+    the ansatz, an independent way of writing the same integrals."""
+    n_r, n_R, N, n_bo = 32, 16, 5, 3
+    r, hr = grid.points(-6, 6, n_r)
+    R, hR = grid.points(-3, 3, n_R)
+    psi1 = rng.standard_normal((N, n_r)) + 1j * rng.standard_normal((N, n_r))
+    psi2 = rng.standard_normal((N, n_R)) + 1j * rng.standard_normal((N, n_R))
+    C = rng.standard_normal(N) + 1j * rng.standard_normal(N)
+    Psi = np.einsum("a,ai,aj->ij", C, psi1, psi2)
+    basis = np.linalg.qr(rng.standard_normal((n_r, n_r)))[0] / np.sqrt(hr)
+    bo_states = np.stack([basis[:, :n_bo].T * (1 + 0.1 * j) for j in range(n_R)])
+    got = exact2d.observables(Psi, hr, hR, bo_states)
+    S = (hr * np.conj(psi1) @ psi1.T) * (hR * np.conj(psi2) @ psi2.T)
+    rho_r, rho_R = observables.densities(C, psi1, psi2, hr, hR)
+    chi = observables.bo_projections(C, psi1, psi2, bo_states, hr)
+    P, D = observables.populations(chi, hR)
+    ref = dict(norm=observables.norm(C, S), rho_r=rho_r, rho_R=rho_R, pop=P, D=D)
+    for key, v in ref.items():
+        assert np.max(np.abs(got[key] - v)) < 1e-12 * np.max(np.abs(v)), key
+
+
+def test_exact2d_populations_over_a_complete_basis_sum_to_the_norm(rng):
+    n_r, n_R = 32, 16
+    r, hr = grid.points(-6, 6, n_r)
+    R, hR = grid.points(-3, 3, n_R)
+    Psi = rng.standard_normal((n_r, n_R)) + 1j * rng.standard_normal((n_r, n_R))
+    # a different orthonormal basis of the r grid at every R_j
+    bo_states = np.stack([np.linalg.qr(rng.standard_normal((n_r, n_r)))[0].T / np.sqrt(hr) for _ in range(n_R)])
+    got = exact2d.observables(Psi, hr, hR, bo_states)
+    assert abs(np.sum(got["pop"]) - got["norm"]) < 1e-12 * got["norm"]
+    assert abs(np.sum(got["rho_R"]) * hR - got["norm"]) < 1e-12 * got["norm"]
+
+
 # --------------------------------------------------------------------------- product-state recovery
 
 def _harmonic_product_run(dt, T=2.0, N=12, seed=3):

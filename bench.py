@@ -15,8 +15,11 @@ of the dominant kernel (the two-body contraction, timed live with HIP events
 on the stream it runs on), the serving mix (served sims/s, p50 / p99
 time-to-result under Poisson arrivals, the speedup over running the same
 simulations one by one in FP64), the propagation's HBM rate on the
-N = 4096, 4096 x 512 workload (whose CWFs do not fit the Infinity Cache), and
-the FP64 oracle timed on a bounded sample on the host cores.
+N = 4096, 4096 x 512 workload (whose CWFs do not fit the Infinity Cache), the
+step time of the exact grid propagation of the full wavefunction at
+512 x 256 and 4096 x 512 (the reference ICWF converges to; skipped with
+--no-large-propagation), and the FP64 oracle timed on a bounded sample on the
+host cores.
 """
 
 import argparse
@@ -100,6 +103,34 @@ def large_propagation():
     gbs = prop_bytes / (ms / 1e3 / n) / 1e9
     return {"workload": wl.name, "n_traj": wl.n_traj, "n_r": wl.n_r, "n_R": wl.n_R, "bytes_per_step": prop_bytes,
             "avg_launch_ms": ms / n, "achieved_gbs": gbs, "peak_gbs": HBM_PEAK_GBS, "frac": gbs / HBM_PEAK_GBS}
+
+
+def exact_grid(steps=50):
+    """The grid propagation of the full wavefunction (include/icwf_exact.h)
+    from the product start, per step at 512 x 256 and 4096 x 512: HIP events on
+    the stream it runs on; algorithmic bytes = read + write Psi once per step."""
+    import numpy as np
+    import torch
+    from paper_1805_11169_amd import icwf, inputs
+    out = {}
+    for nr, nR in ((512, 256), (4096, 512)):
+        wl = inputs.shin_metiu(1, n_r=nr, n_R=nR, n_bo=0)
+        psi0 = np.outer(wl.extra["phi_e"], wl.extra["chi0"]).astype(np.complex128)
+        ex = icwf.ExactPropagator(icwf.config_from_workload(wl), psi0)
+        ex.step(5)
+        s = ex.stream
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(s)
+        ex.step(steps)
+        b.record(s)
+        b.synchronize()
+        ms = a.elapsed_time(b) / steps
+        norm = ex.observables()["norm"]
+        ex.close()
+        nbytes = 2.0 * nr * nR * 16
+        out[f"{nr}x{nR}"] = {"ms_per_step": ms, "bytes_per_step": nbytes, "achieved_gbs": nbytes / (ms / 1e3) / 1e9,
+                             "peak_gbs": HBM_PEAK_GBS, "norm_after": norm}
+    return out
 
 
 def algorithmic_counts(N, nr, nR):
@@ -236,6 +267,8 @@ def main():
     }
     if not args.no_large_propagation and args.workload != "sm_n4096_large":
         line["propagation_4096x512"] = large_propagation()
+    if not args.no_large_propagation and args.workload != "sm_n4096_large":
+        line["exact_grid"] = exact_grid()
     if not args.no_serving:
         from paper_1805_11169_amd import serving
         line["serving"] = serving.measure(n_sims=args.serve_sims, n_steps=args.serve_steps,

@@ -403,6 +403,7 @@ struct GemmBatch {
     int npairs;
     double alpha;
     int trans_a, herm;
+    int lower_a, lower_b;  // op(A) / B lower triangular: the reduction skips the chunks that are zero
 };
 
 constexpr int kGT = 64, kGKC = 16, kGLD = kGKC + 1;
@@ -441,8 +442,12 @@ __global__ void __launch_bounds__(256, 2) k_cgemm(GemmBatch g, const int32_t *__
             re[a][c] = dbl4{0, 0, 0, 0};
             im[a][c] = dbl4{0, 0, 0, 0};
         }
-    const int kbeg = g.herm ? j0 : 0;
-    const int nch = (g.K - kbeg) / kGKC;
+    // B lower triangular (or the X^H X of herm): B[k][j] = 0 for k < j, so the
+    // tile's columns j >= j0 need k >= j0; op(A) lower triangular: rows i < i0 + 64
+    // need k < i0 + 64.  Only exact zeros are skipped.
+    const int kbeg = (g.herm || g.lower_b) ? j0 : 0;
+    const int kend = g.lower_a ? min(g.K, i0 + kGT) : g.K;
+    const int nch = kend > kbeg ? (kend - kbeg) / kGKC : 0;
     // staging: element e = t + 256 m (m < 4); op(A) as [i][k] (64 x 16), B as
     // [k][j] (16 x 64); held as plain doubles (an array of double2 would be
     // placed in scratch memory)
@@ -819,6 +824,8 @@ void launch_cholesky(const Dims &d, const Bufs &b, double2 *A0, double2 *A1, dou
             g.O[f] = b.Tinv[f] + (size_t)h * Np;
         }
         g.alpha = 1.0;
+        g.lower_a = 0;
+        g.lower_b = 1;                                     // A' lower triangular
         hipLaunchKernelGGL(k_cgemm, grid, dim3(256), 0, s, g, b.flags);
         for (int f = 0; f < 2; ++f) {                      // X_DA = -D' T
             g.A[f] = b.Xinv[f] + (size_t)h * Np + h;
@@ -826,6 +833,8 @@ void launch_cholesky(const Dims &d, const Bufs &b, double2 *A0, double2 *A1, dou
             g.O[f] = b.Xinv[f] + (size_t)h * Np;
         }
         g.alpha = -1.0;
+        g.lower_a = 1;                                     // D' lower triangular
+        g.lower_b = 0;
         hipLaunchKernelGGL(k_cgemm, grid, dim3(256), 0, s, g, b.flags);
     }
     // (L L^H)^-1 = X^H X: upper tiles, mirrored

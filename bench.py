@@ -74,6 +74,8 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-steps", type=int, default=2)
     p.add_argument("--no-serving", action="store_true", help="skip the serving-mix leg")
+    p.add_argument("--exact-grid-only", action="store_true",
+                   help="time only the exact grid propagation (512 x 256 and 4096 x 512) and print its JSON")
     p.add_argument("--no-large-propagation", action="store_true",
                    help="skip the propagation measurement on the N = 4096, 4096 x 512 workload")
     p.add_argument("--serve-sims", type=int, default=32)
@@ -169,6 +171,9 @@ def main():
 
     from paper_1805_11169_amd import icwf, inputs
 
+    if args.exact_grid_only:
+        print(json.dumps({"exact_grid": exact_grid()}), flush=True)
+        return
     if args.copy_calibration_bytes:
         n = args.copy_calibration_bytes // 4
         src = torch.ones(n, dtype=torch.float32, device="cuda:0")

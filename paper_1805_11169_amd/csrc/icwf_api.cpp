@@ -770,8 +770,8 @@ icwf::ExactBufs carve_exact(const icwf_config &c, char *base, size_t *total, dou
     e.tmp = L.take<double2>(nr * nR);
     e.half = L.take<double2>(nr * nR);
     e.kinT = L.take<double2>(nr * nR);
-    e.tw_r = L.take<double2>(nr / 2);
-    e.tw_R = L.take<double2>(nR / 2);
+    e.tw_r = L.take<double2>(nr);
+    e.tw_R = L.take<double2>(nR);
     *bo = L.take<double>(std::max<size_t>(1, nR * nbo * nr));
     *chi = L.take<double2>(std::max<size_t>(1, nbo * nR));
     *out = L.take<double>(obs_len(c.n_r, c.n_R, c.n_bo));
@@ -813,7 +813,7 @@ icwf_status icwf_exact_create(const icwf_config *cfg, const double *psi0, const 
 
     const double hr = (cfg->r_max - cfg->r_min) / nr, hR = (cfg->R_max - cfg->R_min) / nR, dt = cfg->dt;
     // half-step phase of the full interaction W = V_1 + V_2 + W_c on the grid
-    std::vector<double2> half(np), kinT(np), tw_r(nr / 2), tw_R(nR / 2);
+    std::vector<double2> half(np), kinT(np), tw_r(nr), tw_R(nR);
     for (int i = 0; i < nr; ++i) {
         const double r = cfg->r_min + i * hr;
         for (int j = 0; j < nR; ++j) {
@@ -836,8 +836,8 @@ icwf_status icwf_exact_create(const icwf_config *cfg, const double *psi0, const 
             kinT[(size_t)kR * nr + kr] = make_double2(std::cos(ph) * inv, std::sin(ph) * inv);
         }
     }
-    for (int k = 0; k < nr / 2; ++k) tw_r[k] = make_double2(std::cos(-2.0 * M_PI * k / nr), std::sin(-2.0 * M_PI * k / nr));
-    for (int k = 0; k < nR / 2; ++k) tw_R[k] = make_double2(std::cos(-2.0 * M_PI * k / nR), std::sin(-2.0 * M_PI * k / nR));
+    for (int k = 0; k < nr; ++k) tw_r[k] = make_double2(std::cos(-2.0 * M_PI * k / nr), std::sin(-2.0 * M_PI * k / nr));
+    for (int k = 0; k < nR; ++k) tw_R[k] = make_double2(std::cos(-2.0 * M_PI * k / nR), std::sin(-2.0 * M_PI * k / nR));
 
     icwf_exact *x = new icwf_exact();
     x->cfg = *cfg;

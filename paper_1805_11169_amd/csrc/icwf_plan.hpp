@@ -159,7 +159,7 @@ void launch_grid_observables(const double2 *Psi, int nr, int nR, double hr, doub
 //   Psi <- e^{-i W dt/2} IFFT2[ e^{-i T dt} FFT2[ e^{-i W dt/2} Psi ] ].
 // psi [nr][nR] in place, tmp [nR][nr] scratch, half [nr][nR] = e^{-i W dt/2},
 // kinT [nR][nr] = e^{-i (k_r^2/2m_r + k_R^2/2m_R) dt} / (nr nR) (transposed),
-// tw_r [nr/2], tw_R [nR/2] = e^{-2 pi i k/n}.  nr, nR powers of two in [32, 4096].
+// tw_r [nr], tw_R [nR] = e^{-2 pi i k/n}.  nr, nR powers of two in [32, 4096].
 struct ExactBufs {
     double2 *psi, *tmp, *half, *kinT, *tw_r, *tw_R;
 };

@@ -7,8 +7,9 @@
 // This is the reference the ansatz of Eq. 7 converges to as N grows; it
 // stores n_r n_R values where the method stores N (n_r + n_R).
 //
-// Three passes per step, one work-group per grid row, each row transformed
-// in LDS by a radix-2 Stockham FFT (autosort: no bit reversal):
+// Three passes per step, one work-group per grid row (n/4 threads, 64 to
+// 1024), each row transformed
+// in LDS by a radix-4 Stockham FFT (autosort: no bit reversal):
 //   1. rows i of Psi [n_r][n_R]: multiply by the half-step potential phase,
 //      FFT along R, write transposed into tmp [n_R][n_r];
 //   2. rows k_R of tmp: FFT along r, multiply by the kinetic phase (which
@@ -26,28 +27,57 @@
 namespace icwf {
 namespace {
 
-constexpr int kExactThreads = 256;
+// Threads per work-group for n = 2^L points: one radix-4 butterfly each
+// (n / 4), at least one wave and at most 1024.
+template <int L>
+constexpr int exact_threads() {
+    return (1 << L) / 4 < 64 ? 64 : ((1 << L) / 4 > 1024 ? 1024 : (1 << L) / 4);
+}
 
 // In-LDS FFT of n = 2^LOG2N points, starting in a, unscaled in both
-// directions.  Pass s (Ns = 2^s) combines pairs of length-Ns transforms:
-// butterfly j reads a[j] and a[j + n/2], multiplies the second by
-// e^{-/+ 2 pi i (j mod Ns) / (2 Ns)} and writes the sum and difference to
-// b[(j div Ns) 2 Ns + j mod Ns] and Ns further on.  tw[k] = e^{-2 pi i k / n},
-// k < n/2.  Returns the buffer holding the result; every thread has passed a
+// directions: Stockham autosort, radix 4 (one radix-2 pass first when LOG2N
+// is odd).  A radix-4 pass with Ns points per finished sub-transform combines
+// four of them: butterfly j reads a[j + r n/4] (r < 4), multiplies element r
+// by e^{-/+ 2 pi i r (j mod Ns) / (4 Ns)}, takes the 4-point DFT and writes
+// output s to b[(j div Ns) 4 Ns + j mod Ns + s Ns].  tw[m] = e^{-2 pi i m / n},
+// m < n.  Returns the buffer holding the result; every thread has passed a
 // barrier after the last write.
 template <int LOG2N>
 __device__ double2 *lds_fft(double2 *a, double2 *b, const double2 *__restrict__ tw, bool inverse) {
-    constexpr int n = 1 << LOG2N, h = n / 2;
-    for (int ns = 1; ns < n; ns <<= 1) {
-        const int stride = h / ns;
-        for (int j = threadIdx.x; j < h; j += kExactThreads) {
+    constexpr int n = 1 << LOG2N, q = n / 4, nt = exact_threads<LOG2N>();
+    int ns = 1;
+    if (LOG2N & 1) {                 // Ns = 1: no twiddles
+        for (int j = threadIdx.x; j < n / 2; j += nt) {
+            const double2 v0 = a[j], v1 = a[j + n / 2];
+            b[2 * j] = cadd(v0, v1);
+            b[2 * j + 1] = csub(v0, v1);
+        }
+        __syncthreads();
+        double2 *t = a;
+        a = b;
+        b = t;
+        ns = 2;
+    }
+    for (; ns < n; ns <<= 2) {
+        const int stride = q / ns;   // n / (4 Ns)
+        for (int j = threadIdx.x; j < q; j += nt) {
             const int k = j & (ns - 1);
-            double2 w = tw[k * stride];
-            if (inverse) w.y = -w.y;
-            const double2 v0 = a[j], v1 = cmul(a[j + h], w);
-            const int o = ((j - k) << 1) + k;
-            b[o] = cadd(v0, v1);
-            b[o + ns] = csub(v0, v1);
+            double2 w1 = tw[k * stride], w2 = tw[2 * k * stride], w3 = tw[3 * k * stride];
+            if (inverse) {
+                w1.y = -w1.y;
+                w2.y = -w2.y;
+                w3.y = -w3.y;
+            }
+            const double2 v0 = a[j], v1 = cmul(a[j + q], w1), v2 = cmul(a[j + 2 * q], w2),
+                          v3 = cmul(a[j + 3 * q], w3);
+            const double2 a0 = cadd(v0, v2), a1 = csub(v0, v2), a2 = cadd(v1, v3), d = csub(v1, v3);
+            // -i d (forward) or +i d (inverse)
+            const double2 a3 = inverse ? make_double2(-d.y, d.x) : make_double2(d.y, -d.x);
+            const int o = ((j - k) << 2) + k;
+            b[o] = cadd(a0, a2);
+            b[o + ns] = cadd(a1, a3);
+            b[o + 2 * ns] = csub(a0, a2);
+            b[o + 3 * ns] = csub(a1, a3);
         }
         __syncthreads();
         double2 *t = a;
@@ -60,64 +90,64 @@ __device__ double2 *lds_fft(double2 *a, double2 *b, const double2 *__restrict__ 
 // Pass 1: row i of psi (n = n_R points) -> FFT_R(half_i o psi_i), stored as
 // column i of tmp [n_R][n_r].
 template <int LOG2N>
-__global__ void __launch_bounds__(kExactThreads) k_exact_rows_fwd(const double2 *__restrict__ psi,
+__global__ void __launch_bounds__(exact_threads<LOG2N>()) k_exact_rows_fwd(const double2 *__restrict__ psi,
                                                                   const double2 *__restrict__ half,
                                                                   const double2 *__restrict__ tw,
                                                                   double2 *__restrict__ tmp, int nr) {
-    constexpr int n = 1 << LOG2N;
+    constexpr int n = 1 << LOG2N, nt = exact_threads<LOG2N>();
     __shared__ double2 buf[2][n];
     const size_t row = (size_t)blockIdx.x * n;
-    for (int j = threadIdx.x; j < n; j += kExactThreads) buf[0][j] = cmul(half[row + j], psi[row + j]);
+    for (int j = threadIdx.x; j < n; j += nt) buf[0][j] = cmul(half[row + j], psi[row + j]);
     __syncthreads();
     const double2 *res = lds_fft<LOG2N>(buf[0], buf[1], tw, false);
-    for (int k = threadIdx.x; k < n; k += kExactThreads) tmp[(size_t)k * nr + blockIdx.x] = res[k];
+    for (int k = threadIdx.x; k < n; k += nt) tmp[(size_t)k * nr + blockIdx.x] = res[k];
 }
 
 // Pass 2: row k_R of tmp (n = n_r points) -> IFFT_r(kin o FFT_r(row)), stored
 // as column k_R of psi [n_r][n_R].
 template <int LOG2N>
-__global__ void __launch_bounds__(kExactThreads) k_exact_cols(const double2 *__restrict__ tmp,
+__global__ void __launch_bounds__(exact_threads<LOG2N>()) k_exact_cols(const double2 *__restrict__ tmp,
                                                               const double2 *__restrict__ kinT,
                                                               const double2 *__restrict__ tw,
                                                               double2 *__restrict__ psi, int nR) {
-    constexpr int n = 1 << LOG2N;
+    constexpr int n = 1 << LOG2N, nt = exact_threads<LOG2N>();
     __shared__ double2 buf[2][n];
     const size_t row = (size_t)blockIdx.x * n;
-    for (int i = threadIdx.x; i < n; i += kExactThreads) buf[0][i] = tmp[row + i];
+    for (int i = threadIdx.x; i < n; i += nt) buf[0][i] = tmp[row + i];
     __syncthreads();
     double2 *f = lds_fft<LOG2N>(buf[0], buf[1], tw, false);
     double2 *g = (f == buf[0]) ? buf[1] : buf[0];
-    for (int k = threadIdx.x; k < n; k += kExactThreads) f[k] = cmul(kinT[row + k], f[k]);
+    for (int k = threadIdx.x; k < n; k += nt) f[k] = cmul(kinT[row + k], f[k]);
     __syncthreads();
     const double2 *res = lds_fft<LOG2N>(f, g, tw, true);
-    for (int i = threadIdx.x; i < n; i += kExactThreads) psi[(size_t)i * nR + blockIdx.x] = res[i];
+    for (int i = threadIdx.x; i < n; i += nt) psi[(size_t)i * nR + blockIdx.x] = res[i];
 }
 
 // Pass 3: row i of psi (n = n_R points) -> half_i o IFFT_R(psi_i), in place.
 template <int LOG2N>
-__global__ void __launch_bounds__(kExactThreads) k_exact_rows_inv(double2 *__restrict__ psi,
+__global__ void __launch_bounds__(exact_threads<LOG2N>()) k_exact_rows_inv(double2 *__restrict__ psi,
                                                                   const double2 *__restrict__ half,
                                                                   const double2 *__restrict__ tw) {
-    constexpr int n = 1 << LOG2N;
+    constexpr int n = 1 << LOG2N, nt = exact_threads<LOG2N>();
     __shared__ double2 buf[2][n];
     const size_t row = (size_t)blockIdx.x * n;
-    for (int j = threadIdx.x; j < n; j += kExactThreads) buf[0][j] = psi[row + j];
+    for (int j = threadIdx.x; j < n; j += nt) buf[0][j] = psi[row + j];
     __syncthreads();
     const double2 *res = lds_fft<LOG2N>(buf[0], buf[1], tw, true);
-    for (int j = threadIdx.x; j < n; j += kExactThreads) psi[row + j] = cmul(half[row + j], res[j]);
+    for (int j = threadIdx.x; j < n; j += nt) psi[row + j] = cmul(half[row + j], res[j]);
 }
 
 template <int L>
 void pass_rows_fwd(int nr, const ExactBufs &e, hipStream_t s) {
-    hipLaunchKernelGGL(k_exact_rows_fwd<L>, dim3(nr), dim3(kExactThreads), 0, s, e.psi, e.half, e.tw_R, e.tmp, nr);
+    hipLaunchKernelGGL(k_exact_rows_fwd<L>, dim3(nr), dim3(exact_threads<L>()), 0, s, e.psi, e.half, e.tw_R, e.tmp, nr);
 }
 template <int L>
 void pass_cols(int nR, const ExactBufs &e, hipStream_t s) {
-    hipLaunchKernelGGL(k_exact_cols<L>, dim3(nR), dim3(kExactThreads), 0, s, e.tmp, e.kinT, e.tw_r, e.psi, nR);
+    hipLaunchKernelGGL(k_exact_cols<L>, dim3(nR), dim3(exact_threads<L>()), 0, s, e.tmp, e.kinT, e.tw_r, e.psi, nR);
 }
 template <int L>
 void pass_rows_inv(int nr, const ExactBufs &e, hipStream_t s) {
-    hipLaunchKernelGGL(k_exact_rows_inv<L>, dim3(nr), dim3(kExactThreads), 0, s, e.psi, e.half, e.tw_R);
+    hipLaunchKernelGGL(k_exact_rows_inv<L>, dim3(nr), dim3(exact_threads<L>()), 0, s, e.psi, e.half, e.tw_R);
 }
 
 // n = 2^lg for lg in [5, 12] (grid sizes 32 ... 4096, checked by the caller).

@@ -39,6 +39,7 @@ class Setup:
     m_R: float
     dt: float
     eps: float = 1e-8
+    propagator: str = "strang"     # or "cn" (Crank-Nicolson, oracle.propagate)
 
     def __post_init__(self):
         self.r, self.hr = grid.points(self.r_min, self.r_max, self.n_r)
@@ -91,7 +92,7 @@ def step(setup, st):
     R_new = st.R_traj + setup.dt * v_R
     p1, p2 = propagate.propagate_cwfs(st.psi1, st.psi2, setup.model, setup.r, setup.R,
                                       setup.hr, setup.hR, setup.m_r, setup.m_R,
-                                      st.r_traj, st.R_traj, setup.dt)
+                                      st.r_traj, st.R_traj, setup.dt, setup.propagator)
     S1, (Kminus, Knew) = _couplings(setup, p1, p2, [(st.r_traj, st.R_traj), (r_new, R_new)])
     C_new, fac1 = coeffs.rk4_step(st.C, st.S, st.K, S1, Kminus, setup.eps, setup.dt, st.fac)
     out = ((r_new < setup.r_min) | (r_new >= setup.r_max)

@@ -32,6 +32,26 @@ def strang_step(psi, V, k, m, dt):
     return half * out
 
 
+def crank_nicolson_step(psi, V, h, m, dt):
+    """One Crank-Nicolson step of the same equation on the periodic grid,
+    (1 + i dt/2 H) psi_new = (1 - i dt/2 H) psi, with H = -(1/2m) D2 + V and D2
+    the periodic three-point second difference (f_{i-1} - 2 f_i + f_{i+1}) / h^2:
+    the Cayley transform of a Hermitian H, unitary for any dt.  The other
+    propagator the survey's reading allows; dense solves, small grids only.
+
+    psi: (N, n) complex; V: (N, n) real, one potential per row."""
+    psi = np.atleast_2d(psi)
+    V = np.broadcast_to(V, psi.shape)
+    n = psi.shape[-1]
+    eye = np.eye(n)
+    D2 = (np.roll(eye, 1, axis=1) + np.roll(eye, -1, axis=1) - 2.0 * eye) / (h * h)
+    H = -D2 / (2.0 * m) + V[:, :, None] * eye[None, :, :]
+    A = eye[None] + 0.5j * dt * H
+    B = eye[None] - 0.5j * dt * H
+    rhs = np.einsum("aij,aj->ai", B, psi)
+    return np.linalg.solve(A, rhs[:, :, None])[:, :, 0]
+
+
 def electronic_potentials(model, r, R_traj):
     """V_1^a(r_i) = W(r_i, R^a) for every trajectory a: shape (N, n_r)."""
     return model.W(r[None, :], np.asarray(R_traj)[:, None])
@@ -42,10 +62,13 @@ def nuclear_potentials(model, R, r_traj):
     return model.W(np.asarray(r_traj)[:, None], R[None, :])
 
 
-def propagate_cwfs(psi1, psi2, model, r, R, hr, hR, m_r, m_R, r_traj, R_traj, dt):
-    """Advance all CWFs by dt, conditioning frozen at (r_traj, R_traj) (Eqs. 5-6, eta dropped)."""
+def propagate_cwfs(psi1, psi2, model, r, R, hr, hR, m_r, m_R, r_traj, R_traj, dt, propagator="strang"):
+    """Advance all CWFs by dt, conditioning frozen at (r_traj, R_traj) (Eqs. 5-6, eta dropped),
+    by the split operator ("strang") or Crank-Nicolson ("cn")."""
+    V1 = electronic_potentials(model, r, R_traj)
+    V2 = nuclear_potentials(model, R, r_traj)
+    if propagator == "cn":
+        return crank_nicolson_step(psi1, V1, hr, m_r, dt), crank_nicolson_step(psi2, V2, hR, m_R, dt)
     kr = grid.wavenumbers(r.size, hr)
     kR = grid.wavenumbers(R.size, hR)
-    p1 = strang_step(psi1, electronic_potentials(model, r, R_traj), kr, m_r, dt)
-    p2 = strang_step(psi2, nuclear_potentials(model, R, r_traj), kR, m_R, dt)
-    return p1, p2
+    return strang_step(psi1, V1, kr, m_r, dt), strang_step(psi2, V2, kR, m_R, dt)

@@ -128,3 +128,49 @@ def test_cavity_model_parts():
     assert cross == pytest.approx(0.05 * x * q, rel=1e-14)
     assert cav.W(0.0, q) - cav.W(0.0, 0.0) == pytest.approx(0.5 * 0.01 * q * q, rel=1e-14)
     assert erf(1.0) > 0  # scipy present
+
+
+# --------------------------------------------------------------------------- Crank-Nicolson
+
+@pytest.mark.parametrize("m,h,dt", [(1.0, 0.3, 0.1), (1836.0, 0.07, 0.1), (0.5, 0.1, 0.4)])
+def test_crank_nicolson_plane_waves_closed_form(m, h, dt):
+    """e^{i k x_j} is an eigenvector of the periodic three-point second
+    difference with eigenvalue -4 sin^2(k h/2)/h^2; with a constant V0 one CN
+    step multiplies it by (1 - i w dt/2) / (1 + i w dt/2),
+    w = 2 sin^2(k h / 2) / (m h^2) + V0."""
+    n, V0 = 64, -0.37
+    x = h * np.arange(n)
+    for q in (0, 1, 5, n // 2 - 1, n // 2):
+        kq = 2 * math.pi * q / (n * h)
+        psi = np.exp(1j * kq * x)
+        w = 2 * math.sin(kq * h / 2) ** 2 / (m * h * h) + V0
+        got = propagate.crank_nicolson_step(psi[None, :], np.full((1, n), V0), h, m, dt)[0]
+        ref = (1 - 0.5j * w * dt) / (1 + 0.5j * w * dt) * psi
+        assert np.max(np.abs(got - ref)) < 1e-13, q
+
+
+def test_crank_nicolson_is_unitary_for_any_potential(rng):
+    n, h, m, dt = 128, 0.2, 1.0, 0.3
+    V = 3.0 * rng.standard_normal((3, n))
+    psi = rng.standard_normal((3, n)) + 1j * rng.standard_normal((3, n))
+    n0 = np.sum(np.abs(psi) ** 2, axis=1)
+    for _ in range(200):
+        psi = propagate.crank_nicolson_step(psi, V, h, m, dt)
+    assert np.max(np.abs(np.sum(np.abs(psi) ** 2, axis=1) / n0 - 1)) < 1e-12
+
+
+def test_crank_nicolson_harmonic_coherent_state_converges_in_h_and_dt():
+    """Centre a cos(t), width 1/(2 m w): CN with the three-point Laplacian is
+    second order in h and in dt; halving both quarters the error."""
+    def run(n, dt, T=3.0, a=2.0):
+        x, h = grid.points(-12, 12, n)
+        psi = (math.pi) ** -0.25 * np.exp(-(x - a) ** 2 / 2) + 0j
+        V = 0.5 * x * x
+        for _ in range(int(round(T / dt))):
+            psi = propagate.crank_nicolson_step(psi[None, :], V[None, :], h, 1.0, dt)[0]
+        rho = np.abs(psi) ** 2
+        mean = h * np.sum(x * rho)
+        return abs(mean - a * math.cos(T)) + abs(h * np.sum(x * x * rho) - mean * mean - 0.5)
+    e1, e2 = run(256, 0.025), run(512, 0.0125)     # coarser pairs are not yet asymptotic
+    assert e2 < 3e-3
+    assert 3.5 < e1 / e2 < 4.7

@@ -98,6 +98,17 @@ typedef enum {
                                    matrices of workspace                       */
 } icwf_solver;
 
+/* How every CWF advances over a step (Eqs. 5-6, conditioning frozen at the
+ * step start). */
+typedef enum {
+    ICWF_PROP_SPLIT = 0,          /* Strang split operator with the spectral kinetic
+                                     energy (the default; the paper gives no scheme)  */
+    ICWF_PROP_CRANK_NICOLSON = 1  /* (1 + i dt/2 H) psi' = (1 - i dt/2 H) psi with the
+                                     periodic three-point Laplacian, solved per CWF by
+                                     cyclic reduction; n_r, n_R <= 2048, else
+                                     ICWF_EINVAL                                       */
+} icwf_propagator;
+
 typedef struct {
     int32_t n_traj;          /* N: trajectories = basis size of Eq. 7 (the paper's M)   */
     int32_t n_r, n_R;        /* grid points: powers of two, 32 <= n <= 4096             */
@@ -111,6 +122,7 @@ typedef struct {
     int32_t precision;       /* icwf_precision                                          */
     int32_t n_bo;            /* BO states used by the populations (0: none)             */
     int32_t solver;          /* icwf_solver (0: automatic)                              */
+    int32_t propagator;      /* icwf_propagator (0: split operator)                     */
 } icwf_config;
 
 /* Observables at the current step (text around the Shin-Metiu figure of the

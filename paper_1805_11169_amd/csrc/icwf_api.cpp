@@ -122,6 +122,9 @@ const char *validate(const icwf_config *c) {
         return "unknown precision";
     if (c->n_bo < 0 || c->n_bo > c->n_r) return "n_bo must be in [0, n_r]";
     if (c->solver < ICWF_SOLVER_AUTO || c->solver > ICWF_SOLVER_INVERSE) return "unknown solver";
+    if (c->propagator != ICWF_PROP_SPLIT && c->propagator != ICWF_PROP_CRANK_NICOLSON) return "unknown propagator";
+    if (c->propagator == ICWF_PROP_CRANK_NICOLSON && (c->n_r > 2048 || c->n_R > 2048))
+        return "the Crank-Nicolson propagator takes grids of at most 2048 points";
     if (c->solver == ICWF_SOLVER_INVERSE && !icwf::use_sinv(icwf::padded(c->n_traj), c->precision, c->solver))
         return "the explicit-inverse solver needs the padded N (next multiple of 64) to be a power of two";
     for (int i = 0; i < 8; ++i)
@@ -410,6 +413,7 @@ icwf_status icwf_create(const icwf_config *cfg, const double *r0, const double *
     d.n_bo = nbo;
     d.prec = cfg->precision;
     d.sinv = icwf::use_sinv(icwf::padded(N), cfg->precision, cfg->solver) ? 1 : 0;
+    d.propagator = cfg->propagator;
     d.r_min = cfg->r_min;
     d.hr = (cfg->r_max - cfg->r_min) / nr;
     d.R_min = cfg->R_min;

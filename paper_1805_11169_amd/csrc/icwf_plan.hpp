@@ -15,6 +15,7 @@ struct Dims {
     int lr_rank;                          // rank of the FP64 part of the mixed contraction
     int fp32_residual;                    // mixed form: the residual left to FP32 is not negligible
     int sinv;                             // RK4 stages through explicit inverses of S + eps I
+    int propagator;                       // 0 split operator, 1 Crank-Nicolson
     int wc_grid;                          // work-groups of the persistent two-body contraction
     int prop_grid[2];                     // work-groups of the persistent propagation, per species
     double r_min, hr, R_min, hR, m_r, m_R, dt, eps;
@@ -104,6 +105,9 @@ inline bool use_sinv(int Np, int precision, int solver) {
 // Split-operator step of every CWF of one species; species 1 = electronic
 // (conditioned on R^a), 2 = nuclear (conditioned on r^a).
 void launch_propagate(const Dims &d, const Bufs &b, int species, hipStream_t s);
+// The same step by Crank-Nicolson (grids up to 2048 points); launch_propagate
+// hands over to it when d.propagator == 1.
+void launch_propagate_cn(const Dims &d, const Bufs &b, int species, hipStream_t s);
 
 // Work-groups of the persistent propagation for grid size n and N trajectories:
 // as many as fit the device's ncu compute units at once, at most one per CWF group.

@@ -533,6 +533,10 @@ int propagate_grid(int n, int N, int ncu) {
 }
 
 void launch_propagate(const Dims &d, const Bufs &b, int species, hipStream_t s) {
+    if (d.propagator == 1) {
+        launch_propagate_cn(d, b, species, s);
+        return;
+    }
     const int n = species == 1 ? d.nr : d.nR;
     const int T = threads_for(n);
     const int ngroups = padded(d.N) / (T / (n / kPts));   // padded rows hold zero CWFs

@@ -19,6 +19,7 @@ OK, EINVAL, ENOMEM, EDEVICE, ENONFINITE, ENODE, ESOLVE, ESTATE, ETIMEDOUT = 0, -
 MODEL_SHIN_METIU, MODEL_CAVITY = 1, 2
 PREC_FP64, PREC_MIXED, PREC_SEPARABLE = 0, 1, 2
 SOLVER_AUTO, SOLVER_TRIANGULAR, SOLVER_INVERSE = 0, 1, 2
+PROP_SPLIT, PROP_CRANK_NICOLSON = 0, 1
 
 # the entry points include/icwf.h declares
 EXPORTS = ("icwf_workspace_bytes", "icwf_create", "icwf_step", "icwf_sync", "icwf_observables",
@@ -38,7 +39,8 @@ class Config(ctypes.Structure):
                 ("r_min", c_double), ("r_max", c_double), ("R_min", c_double), ("R_max", c_double),
                 ("m_r", c_double), ("m_R", c_double), ("dt", c_double),
                 ("model", c_int32), ("model_params", c_double * 8), ("tikhonov_eps", c_double),
-                ("precision", c_int32), ("n_bo", c_int32), ("solver", c_int32)]
+                ("precision", c_int32), ("n_bo", c_int32), ("solver", c_int32),
+                ("propagator", c_int32)]
 
 
 _DP = POINTER(c_double)
@@ -168,7 +170,7 @@ def _f64(a, n=None):
 
 
 def make_config(n_traj, n_r, n_R, r_box, R_box, m_r, m_R, dt, model, model_params, eps=1e-8,
-                precision=PREC_FP64, n_bo=0, solver=SOLVER_AUTO):
+                precision=PREC_FP64, n_bo=0, solver=SOLVER_AUTO, propagator=PROP_SPLIT):
     c = Config()
     c.n_traj, c.n_r, c.n_R = int(n_traj), int(n_r), int(n_R)
     c.r_min, c.r_max = float(r_box[0]), float(r_box[1])
@@ -182,13 +184,14 @@ def make_config(n_traj, n_r, n_R, r_box, R_box, m_r, m_R, dt, model, model_param
     c.precision = int(precision)
     c.n_bo = int(n_bo)
     c.solver = int(solver)
+    c.propagator = int(propagator)
     return c
 
 
-def config_from_workload(wl, precision=PREC_FP64, eps=None, solver=SOLVER_AUTO):
+def config_from_workload(wl, precision=PREC_FP64, eps=None, solver=SOLVER_AUTO, propagator=PROP_SPLIT):
     return make_config(wl.n_traj, wl.n_r, wl.n_R, (wl.r_min, wl.r_max), (wl.R_min, wl.R_max), wl.m_r, wl.m_R,
                        wl.dt, wl.model, wl.model_params, wl.eps if eps is None else eps, precision, wl.n_bo,
-                       solver)
+                       solver, propagator)
 
 
 def workspace_bytes(cfg):
@@ -222,8 +225,8 @@ class Simulation:
         self.h = handle
 
     @classmethod
-    def from_workload(cls, wl, precision=PREC_FP64, C0=None, solver=SOLVER_AUTO, **kw):
-        cfg = config_from_workload(wl, precision, solver=solver)
+    def from_workload(cls, wl, precision=PREC_FP64, C0=None, solver=SOLVER_AUTO, propagator=PROP_SPLIT, **kw):
+        cfg = config_from_workload(wl, precision, solver=solver, propagator=propagator)
         return cls(cfg, wl.r0, wl.R0, wl.psi1, wl.psi2, C0=C0, b0=None if C0 is not None else wl.b0,
                    bo=wl.bo, **kw)
 

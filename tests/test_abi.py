@@ -76,7 +76,8 @@ def test_workspace_holds_the_explicit_inverses_only_where_they_are_used():
                                  dict(r_box=(1, 1)), dict(m_r=0.0), dict(dt=-0.1), dict(eps=-1.0),
                                  dict(model=7), dict(precision=3), dict(n_bo=-1), dict(n_bo=1000),
                                  dict(model_params=[19.0, 0.0, 3.1, 4.0]), dict(solver=3), dict(solver=-1),
-                                 dict(n_traj=150, solver=icwf.SOLVER_INVERSE)])
+                                 dict(n_traj=150, solver=icwf.SOLVER_INVERSE), dict(propagator=2),
+                                 dict(n_r=4096, propagator=icwf.PROP_CRANK_NICOLSON)])
 def test_invalid_configs_are_rejected_on_the_host(bad):
     cfg = _cfg(**bad)
     assert icwf.workspace_bytes(cfg) == 0

@@ -1,0 +1,98 @@
+"""The Crank-Nicolson propagator (icwf_config.propagator) against the oracle's
+ICWF step with its Crank-Nicolson CWF step, through the C ABI.
+
+Bars as for the split operator: CWFs, positions, S and K after one step at
+1e-12 relative (the oracle solves each CWF's system densely, the GPU by
+cyclic reduction); C at 1e-10 in the S norm; observables after 10 and 20
+steps at 1e-10 relative."""
+
+import numpy as np
+import pytest
+
+from oracle import icwf as oicwf
+from paper_1805_11169_amd import icwf, inputs
+
+from oracle_runs import init_for, rel_max, s_norm_diff, setup_for
+
+pytestmark = pytest.mark.gpu
+
+CN = icwf.PROP_CRANK_NICOLSON
+
+CASES = {
+    "sm_ragged": dict(N=37, n_r=128, n_R=64, model=inputs.MODEL_SHIN_METIU, seed=1),
+    "cavity": dict(N=20, n_r=128, n_R=64, model=inputs.MODEL_CAVITY, r_box=(-30.0, 30.0),
+                   R_box=(-20.0, 20.0), seed=2),
+    "sm_two_tiles": dict(N=130, n_r=256, n_R=128, model=inputs.MODEL_SHIN_METIU, seed=3),
+}
+
+
+@pytest.fixture(scope="module", params=sorted(CASES))
+def case(request):
+    kw = dict(CASES[request.param])
+    wl = inputs.gaussian_basis(kw.pop("N"), **kw)
+    print(f"[case] crank-nicolson {request.param}: N={wl.n_traj} grid={wl.n_r}x{wl.n_R}", flush=True)
+    setup = setup_for(wl)
+    setup.propagator = "cn"
+    return wl, setup, init_for(setup, wl)
+
+
+def test_one_step(case):
+    wl, setup, st0 = case
+    sim = icwf.Simulation.from_workload(wl, C0=wl.extra["C0"], propagator=CN)
+    sim.step(1)
+    got = sim.state()
+    S, K, _ = sim.matrices()
+    sim.close()
+    ref = oicwf.step(setup, st0)
+    assert rel_max(got["psi1"], ref.psi1) < 1e-12
+    assert rel_max(got["psi2"], ref.psi2) < 1e-12
+    assert np.max(np.abs(got["r"] - ref.r_traj)) < 1e-12 * max(1.0, np.max(np.abs(ref.r_traj)))
+    assert np.max(np.abs(got["R"] - ref.R_traj)) < 1e-12 * max(1.0, np.max(np.abs(ref.R_traj)))
+    assert rel_max(S, ref.S) < 1e-12
+    assert rel_max(K, ref.K) < 1e-12
+    assert s_norm_diff(got["C"], ref.C, ref.S) < 1e-10 * np.sqrt(abs(np.conj(ref.C) @ ref.S @ ref.C))
+
+
+def test_ten_steps_observables(case):
+    wl, setup, st0 = case
+    sim = icwf.Simulation.from_workload(wl, C0=wl.extra["C0"], propagator=CN)
+    sim.step(10)
+    o = sim.observables()
+    sim.close()
+    _, hist = oicwf.run(setup, st0, 10)
+    ref = hist[-1]
+    assert abs(o["norm"] - ref["norm"]) < 1e-10 * abs(ref["norm"])
+    assert rel_max(o["rho_r"], ref["rho_r"]) < 1e-10
+    assert rel_max(o["rho_R"], ref["rho_R"]) < 1e-10
+
+
+def test_parity_workload_twenty_steps():
+    """Shin-Metiu N = 64, 512 x 256, product start, three BO states."""
+    wl = inputs.preset("sm_n64")
+    print(f"[case] crank-nicolson {wl.name}: 20 steps", flush=True)
+    setup = setup_for(wl)
+    setup.propagator = "cn"
+    _, hist = oicwf.run(setup, init_for(setup, wl), 20, 20, wl.bo)
+    ref = hist[-1]
+    sim = icwf.Simulation.from_workload(wl, propagator=CN)
+    sim.step(20)
+    o = sim.observables()
+    sim.close()
+    assert abs(o["norm"] - ref["norm"]) < 1e-10
+    for key in ("rho_r", "rho_R", "pop", "D"):
+        assert rel_max(o[key], ref[key]) < 1e-10, key
+
+
+def test_split_and_crank_nicolson_agree_to_discretisation_order():
+    """Both propagators approximate the same CWF equation: on the parity
+    workload after 20 steps their observables differ by the three-point
+    Laplacian's O(h^2) error, well below 1e-2 and not zero."""
+    wl = inputs.preset("sm_n64")
+    out = []
+    for prop in (icwf.PROP_SPLIT, CN):
+        sim = icwf.Simulation.from_workload(wl, propagator=prop)
+        sim.step(20)
+        out.append(sim.observables())
+        sim.close()
+    d = rel_max(out[1]["rho_R"], out[0]["rho_R"])
+    assert 1e-9 < d < 1e-2

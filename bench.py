@@ -71,6 +71,8 @@ def parse():
     p.add_argument("--warmup", type=int, default=3)
     p.add_argument("--precision", choices=["fp64", "mixed", "separable"], default="fp64")
     p.add_argument("--workload", default="sm_n1024")
+    p.add_argument("--propagator", choices=["split", "cn"], default="split",
+                   help="CWF propagator: split operator (default) or Crank-Nicolson")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-steps", type=int, default=2)
     p.add_argument("--no-serving", action="store_true", help="skip the serving-mix leg")
@@ -186,7 +188,8 @@ def main():
     wl = inputs.preset(args.workload, n_bo=0)
     prec = {"fp64": icwf.PREC_FP64, "mixed": icwf.PREC_MIXED, "separable": icwf.PREC_SEPARABLE}[args.precision]
     N, nr, nR = wl.n_traj, wl.n_r, wl.n_R
-    sim = icwf.Simulation.from_workload(wl, precision=prec, device=0)
+    prop = icwf.PROP_CRANK_NICOLSON if args.propagator == "cn" else icwf.PROP_SPLIT
+    sim = icwf.Simulation.from_workload(wl, precision=prec, device=0, propagator=prop)
     stream = sim.stream
 
     sim.step(args.warmup)
@@ -256,7 +259,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl.name, "hamiltonian": {1: "shin_metiu", 2: "cavity"}[wl.model], "n_traj": N,
                    "n_r": nr, "n_R": nR,
-                   "dt": wl.dt, "precision": args.precision, "contraction_rank": rank,
+                   "dt": wl.dt, "precision": args.precision, "propagator": args.propagator, "contraction_rank": rank,
                    "timing": "kernel-by-kernel with HIP events"},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK[args.precision], "unit": "TFLOP/s",
                      "frac": achieved / PEAK[args.precision],

@@ -73,6 +73,14 @@ def test_fp64_with_explicit_inverses_matches_oracle(c1):
         assert w[key] < 1e-10, key
 
 
+def test_mixed_with_explicit_inverses_within_1e5(c1):
+    wl, ref = c1
+    gpu = _gpu_history(wl, icwf.PREC_MIXED, icwf.SOLVER_INVERSE)
+    w = _compare(gpu, ref)
+    for key in ("rho_r", "rho_R", "pop", "D", "norm"):
+        assert w[key] < 1e-5, key
+
+
 def test_mixed_within_1e5(c1):
     wl, ref = c1
     gpu = _gpu_history(wl, icwf.PREC_MIXED)

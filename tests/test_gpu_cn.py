@@ -96,3 +96,22 @@ def test_split_and_crank_nicolson_agree_to_discretisation_order():
         sim.close()
     d = rel_max(out[1]["rho_R"], out[0]["rho_R"])
     assert 1e-9 < d < 1e-2
+
+
+def test_mixed_form_with_crank_nicolson():
+    """The mixed form reads the FP32 copy of psi1 that the Crank-Nicolson
+    kernel writes: the parity workload over 20 steps within the mixed bar
+    (1e-5) of the FP64 oracle with the same propagator."""
+    wl = inputs.preset("sm_n64")
+    print(f"[case] crank-nicolson mixed {wl.name}: 20 steps", flush=True)
+    setup = setup_for(wl)
+    setup.propagator = "cn"
+    _, hist = oicwf.run(setup, init_for(setup, wl), 20, 20, wl.bo)
+    ref = hist[-1]
+    sim = icwf.Simulation.from_workload(wl, precision=icwf.PREC_MIXED, propagator=CN)
+    sim.step(20)
+    o = sim.observables()
+    sim.close()
+    assert abs(o["norm"] - ref["norm"]) < 1e-5
+    for key in ("rho_r", "rho_R", "pop", "D"):
+        assert rel_max(o[key], ref[key]) < 1e-5, key

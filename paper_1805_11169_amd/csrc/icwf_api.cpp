@@ -102,6 +102,7 @@ Bufs carve(const icwf_config &c, char *base, size_t *total) {
     b.bo = L.take<double>(std::max<size_t>(1, nR * nbo * nr));
     b.obs_psi = L.take<double2>(nr * nR);
     b.obs_chi = L.take<double2>(std::max<size_t>(1, nbo * nR));
+    b.obs_part = L.take<double>(icwf::kRhoSlices * nR);
     b.obs_out = L.take<double>(obs_len(c.n_r, c.n_R, c.n_bo));
     *total = (L.off + 255) & ~size_t(255);
     return b;
@@ -757,6 +758,7 @@ struct icwf_exact {
     icwf::ExactBufs e{};
     double *bo = nullptr;
     double2 *chi = nullptr;
+    double *part = nullptr;
     double *out = nullptr;
     double hr = 0, hR = 0;
     int64_t step = 0;
@@ -765,7 +767,7 @@ struct icwf_exact {
 namespace {
 
 icwf::ExactBufs carve_exact(const icwf_config &c, char *base, size_t *total, double **bo, double2 **chi,
-                            double **out) {
+                            double **part, double **out) {
     Layout L;
     L.base = base;
     const size_t nr = c.n_r, nR = c.n_R, nbo = c.n_bo;
@@ -778,6 +780,7 @@ icwf::ExactBufs carve_exact(const icwf_config &c, char *base, size_t *total, dou
     e.tw_R = L.take<double2>(nR);
     *bo = L.take<double>(std::max<size_t>(1, nR * nbo * nr));
     *chi = L.take<double2>(std::max<size_t>(1, nbo * nR));
+    *part = L.take<double>(icwf::kRhoSlices * nR);
     *out = L.take<double>(obs_len(c.n_r, c.n_R, c.n_bo));
     *total = (L.off + 255) & ~size_t(255);
     return e;
@@ -790,10 +793,9 @@ extern "C" {
 size_t icwf_exact_workspace_bytes(const icwf_config *cfg) {
     if (validate(cfg)) return 0;
     size_t total = 0;
-    double *bo;
+    double *bo, *part, *out;
     double2 *chi;
-    double *out;
-    carve_exact(*cfg, nullptr, &total, &bo, &chi, &out);
+    carve_exact(*cfg, nullptr, &total, &bo, &chi, &part, &out);
     return total;
 }
 
@@ -849,7 +851,7 @@ icwf_status icwf_exact_create(const icwf_config *cfg, const double *psi0, const 
     x->hr = hr;
     x->hR = hR;
     size_t total = 0;
-    x->e = carve_exact(*cfg, reinterpret_cast<char *>(workspace), &total, &x->bo, &x->chi, &x->out);
+    x->e = carve_exact(*cfg, reinterpret_cast<char *>(workspace), &total, &x->bo, &x->chi, &x->part, &x->out);
     const hipStream_t st = x->stream;
     auto copy = [&](void *dst, const void *src, size_t bytes) {
         return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st) == hipSuccess;
@@ -879,7 +881,7 @@ icwf_status icwf_exact_step(icwf_exact *x, int64_t n_steps) {
 icwf_status icwf_exact_observables(icwf_exact *x, icwf_obs *o) {
     if (!x || !o) return fail(nullptr, ICWF_EINVAL, "NULL argument");
     const int nr = x->cfg.n_r, nR = x->cfg.n_R, nbo = x->cfg.n_bo;
-    icwf::launch_grid_observables(x->e.psi, nr, nR, x->hr, x->hR, nbo, x->bo, x->chi, x->out, x->stream);
+    icwf::launch_grid_observables(x->e.psi, nr, nR, x->hr, x->hR, nbo, x->bo, x->chi, x->part, x->out, x->stream);
     std::vector<double> buf(obs_len(nr, nR, nbo));
     if (hipMemcpyAsync(buf.data(), x->out, sizeof(double) * buf.size(), hipMemcpyDeviceToHost, x->stream) != hipSuccess ||
         hipStreamSynchronize(x->stream) != hipSuccess)

@@ -80,6 +80,7 @@ struct Bufs {
     double *bo;                           // [nR][n_bo][nr] BO states
     double2 *obs_psi;                     // [nr][nR] Psi on the grid (observables)
     double2 *obs_chi;                     // [n_bo][nR]
+    double *obs_part;                     // [kRhoSlices][nR] partial sums of rho_R
     double *obs_out;                      // packed observables
     int32_t *flags;                       // kNumFlags status flags
     int32_t *wc_queue;                    // [1 + wc_split_tiles(Np)] tile counter of the persistent two-body
@@ -154,9 +155,11 @@ void launch_observables(const Dims &d, const Bufs &b, hipStream_t s);
 
 // Observables of a wavefunction given on the grid, Psi [nr][nR] complex128:
 // out = [norm, rho_r[nr], rho_R[nR], pop[n_bo], D[n_bo][n_bo]]; bo is
-// [nR][n_bo][nr] (real BO states), chi [n_bo][nR] scratch.
+// [nR][n_bo][nr] (real BO states), chi [n_bo][nR] and part [kRhoSlices][nR]
+// scratch.
+constexpr int kRhoSlices = 32;   // row slices of the rho_R reduction (nr >= 32)
 void launch_grid_observables(const double2 *Psi, int nr, int nR, double hr, double hR, int n_bo, const double *bo,
-                             double2 *chi, double *out, hipStream_t s);
+                             double2 *chi, double *part, double *out, hipStream_t s);
 
 // One Strang step of the full two-dimensional wavefunction (Eqs. 1-2 on the
 // product grid; the reference the ansatz converges to):

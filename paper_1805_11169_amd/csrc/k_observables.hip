@@ -142,21 +142,32 @@ __global__ void k_obs_rho_r(const double2 *__restrict__ Psi, int nr, int nR, dou
     if (lane == 0) rho[i] = hR * acc;
 }
 
-// rho_R[j] = hr sum_i |Psi_ij|^2: 64 columns per block, four row slices
-// reduced in LDS in a fixed order.
-__global__ void k_obs_rho_R(const double2 *__restrict__ Psi, int nr, int nR, double hr, double *__restrict__ rho) {
-    __shared__ double part[4][64];
+// rho_R[j] = hr sum_i |Psi_ij|^2 in two passes, so that tall grids fill the
+// device: block (x, y) sums rows y nr/S ... (y + 1) nr/S - 1 of 64 columns
+// (four row slices reduced in LDS in a fixed order) into part[y][j]; then
+// the S partial sums of each column are added in order.
+__global__ void k_obs_rho_R_part(const double2 *__restrict__ Psi, int nr, int nR, double *__restrict__ part) {
+    __shared__ double red[4][64];
     const int c = threadIdx.x & 63, sl = threadIdx.x >> 6;
     const int j = blockIdx.x * 64 + c;
+    const int rows = nr / kRhoSlices, i0 = blockIdx.y * rows;
     double acc = 0.0;
     if (j < nR)
-        for (int i = sl; i < nr; i += 4) {
+        for (int i = i0 + sl; i < i0 + rows; i += 4) {
             const double2 p = Psi[(size_t)i * nR + j];
             acc += p.x * p.x + p.y * p.y;
         }
-    part[sl][c] = acc;
+    red[sl][c] = acc;
     __syncthreads();
-    if (sl == 0 && j < nR) rho[j] = hr * (((part[0][c] + part[1][c]) + part[2][c]) + part[3][c]);
+    if (sl == 0 && j < nR) part[(size_t)blockIdx.y * nR + j] = ((red[0][c] + red[1][c]) + red[2][c]) + red[3][c];
+}
+
+__global__ void k_obs_rho_R_sum(const double *__restrict__ part, int nR, double hr, double *__restrict__ rho) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= nR) return;
+    double acc = 0.0;
+    for (int s = 0; s < kRhoSlices; ++s) acc += part[(size_t)s * nR + j];
+    rho[j] = hr * acc;
 }
 
 // out[0] = hr sum_i rho_r[i]; one block.
@@ -223,10 +234,11 @@ __global__ void k_obs_pop(const double2 *__restrict__ chi, int nR, int n_bo, dou
 }  // namespace
 
 void launch_grid_observables(const double2 *Psi, int nr, int nR, double hr, double hR, int n_bo, const double *bo,
-                             double2 *chi, double *out, hipStream_t s) {
+                             double2 *chi, double *part, double *out, hipStream_t s) {
     double *rho_r = out + 1, *rho_R = out + 1 + nr;
     hipLaunchKernelGGL(k_obs_rho_r, dim3((nr + 3) / 4), dim3(256), 0, s, Psi, nr, nR, hR, rho_r);
-    hipLaunchKernelGGL(k_obs_rho_R, dim3((nR + 63) / 64), dim3(256), 0, s, Psi, nr, nR, hr, rho_R);
+    hipLaunchKernelGGL(k_obs_rho_R_part, dim3((nR + 63) / 64, kRhoSlices), dim3(256), 0, s, Psi, nr, nR, part);
+    hipLaunchKernelGGL(k_obs_rho_R_sum, dim3((nR + 255) / 256), dim3(256), 0, s, part, nR, hr, rho_R);
     hipLaunchKernelGGL(k_obs_norm, dim3(1), dim3(256), 0, s, rho_r, nr, hr, out);
     if (n_bo > 0) {
         hipLaunchKernelGGL(k_obs_chi, dim3(nR, n_bo), dim3(64), 0, s, bo, Psi, nr, nR, n_bo, hr, chi);
@@ -239,7 +251,7 @@ void launch_observables(const Dims &d, const Bufs &b, hipStream_t s) {
     const int Np = padded(d.N);
     const dim3 tiles((d.nR + kOT - 1) / kOT, (d.nr + kOT - 1) / kOT);
     hipLaunchKernelGGL(k_obs_psi, tiles, dim3(256), 0, s, b.psi1, b.psi2, b.C, d.nr, d.nR, Np, b.obs_psi);
-    launch_grid_observables(b.obs_psi, d.nr, d.nR, d.hr, d.hR, d.n_bo, b.bo, b.obs_chi, b.obs_out, s);
+    launch_grid_observables(b.obs_psi, d.nr, d.nR, d.hr, d.hR, d.n_bo, b.bo, b.obs_chi, b.obs_part, b.obs_out, s);
 }
 
 }  // namespace icwf

@@ -117,7 +117,7 @@ def test_exact_workspace_and_invalid_configs():
     small tables; an invalid configuration sizes to 0 and fails creation."""
     cfg = _cfg(n_r=512, n_R=256, n_bo=0)
     ex = icwf.lib().icwf_exact_workspace_bytes(ctypes.byref(cfg))
-    assert 4 * 16 * 512 * 256 <= ex < 4 * 16 * 512 * 256 + 64 * 1024
+    assert 4 * 16 * 512 * 256 <= ex < 4 * 16 * 512 * 256 + 256 * 1024
     bad = _cfg(n_r=500)
     assert icwf.lib().icwf_exact_workspace_bytes(ctypes.byref(bad)) == 0
     h = ctypes.c_void_p()

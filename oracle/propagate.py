@@ -37,7 +37,8 @@ def crank_nicolson_step(psi, V, h, m, dt):
     (1 + i dt/2 H) psi_new = (1 - i dt/2 H) psi, with H = -(1/2m) D2 + V and D2
     the periodic three-point second difference (f_{i-1} - 2 f_i + f_{i+1}) / h^2:
     the Cayley transform of a Hermitian H, unitary for any dt.  The other
-    propagator the survey's reading allows; dense solves, small grids only.
+    standard propagator for these equations (the paper names none); dense
+    solves, small grids only.
 
     psi: (N, n) complex; V: (N, n) real, one potential per row."""
     psi = np.atleast_2d(psi)

@@ -42,12 +42,13 @@ constexpr int exact_threads() {
 // output s to b[(j div Ns) 4 Ns + j mod Ns + s Ns].  tw[m] = e^{-2 pi i m / n},
 // m < n.  Returns the buffer holding the result; every thread has passed a
 // barrier after the last write.
-template <int LOG2N>
-__device__ double2 *lds_fft(double2 *a, double2 *b, const double2 *__restrict__ tw, bool inverse) {
-    constexpr int n = 1 << LOG2N, q = n / 4, nt = exact_threads<LOG2N>();
+template <int LOG2N, int NT = exact_threads<LOG2N>()>
+__device__ double2 *lds_fft(double2 *a, double2 *b, const double2 *__restrict__ tw, bool inverse,
+                            int tid = threadIdx.x) {
+    constexpr int n = 1 << LOG2N, q = n / 4, nt = NT;
     int ns = 1;
     if (LOG2N & 1) {                 // Ns = 1: no twiddles
-        for (int j = threadIdx.x; j < n / 2; j += nt) {
+        for (int j = tid; j < n / 2; j += nt) {
             const double2 v0 = a[j], v1 = a[j + n / 2];
             b[2 * j] = cadd(v0, v1);
             b[2 * j + 1] = csub(v0, v1);
@@ -60,7 +61,7 @@ __device__ double2 *lds_fft(double2 *a, double2 *b, const double2 *__restrict__ 
     }
     for (; ns < n; ns <<= 2) {
         const int stride = q / ns;   // n / (4 Ns)
-        for (int j = threadIdx.x; j < q; j += nt) {
+        for (int j = tid; j < q; j += nt) {
             const int k = j & (ns - 1);
             double2 w1 = tw[k * stride], w2 = tw[2 * k * stride], w3 = tw[3 * k * stride];
             if (inverse) {
@@ -87,20 +88,39 @@ __device__ double2 *lds_fft(double2 *a, double2 *b, const double2 *__restrict__ 
     return a;
 }
 
-// Pass 1: row i of psi (n = n_R points) -> FFT_R(half_i o psi_i), stored as
-// column i of tmp [n_R][n_r].
+// Pass 1: rows i of psi (n = n_R points) -> FFT_R(half_i o psi_i), stored as
+// columns i of tmp [n_R][n_r].  A work-group takes fwd_rows<LOG2N> rows (a
+// group of n/4 threads per row), so that each column of tmp receives that
+// many consecutive values at once: up to a whole 128-byte line per write.
+template <int L>
+constexpr int fwd_rows() {
+    return (1 << L) * 8 <= 4096 ? 8 : 4096 / (1 << L);     // <= 128 KB of LDS
+}
+template <int L>
+constexpr int fwd_group() {
+    return (1 << L) / 4;
+}
 template <int LOG2N>
-__global__ void __launch_bounds__(exact_threads<LOG2N>()) k_exact_rows_fwd(const double2 *__restrict__ psi,
-                                                                  const double2 *__restrict__ half,
-                                                                  const double2 *__restrict__ tw,
-                                                                  double2 *__restrict__ tmp, int nr) {
-    constexpr int n = 1 << LOG2N, nt = exact_threads<LOG2N>();
-    __shared__ double2 buf[2][n];
-    const size_t row = (size_t)blockIdx.x * n;
-    for (int j = threadIdx.x; j < n; j += nt) buf[0][j] = cmul(half[row + j], psi[row + j]);
+__global__ void __launch_bounds__(fwd_rows<LOG2N>() * fwd_group<LOG2N>()) k_exact_rows_fwd(
+    const double2 *__restrict__ psi, const double2 *__restrict__ half, const double2 *__restrict__ tw,
+    double2 *__restrict__ tmp, int nr) {
+    constexpr int n = 1 << LOG2N, RW = fwd_rows<LOG2N>(), G = fwd_group<LOG2N>(), nt = RW * G;
+    __shared__ double2 buf[2][RW][n];
+    const int r = threadIdx.x / G, tid = threadIdx.x - r * G;
+    const size_t i0 = (size_t)blockIdx.x * RW;
+    for (int e = threadIdx.x; e < RW * n; e += nt) {
+        const int rr = e / n, j = e - rr * n;
+        const size_t g = (i0 + rr) * n + j;
+        buf[0][rr][j] = cmul(half[g], psi[g]);
+    }
     __syncthreads();
-    const double2 *res = lds_fft<LOG2N>(buf[0], buf[1], tw, false);
-    for (int k = threadIdx.x; k < n; k += nt) tmp[(size_t)k * nr + blockIdx.x] = res[k];
+    const double2 *res = lds_fft<LOG2N, G>(buf[0][r], buf[1][r], tw, false, tid);
+    // every row's result sits in the same buffer (the passes are the same)
+    const int sel = (res == buf[0][r]) ? 0 : 1;
+    for (int e = threadIdx.x; e < RW * n; e += nt) {
+        const int k = e / RW, rr = e - k * RW;
+        tmp[(size_t)k * nr + i0 + rr] = buf[sel][rr][k];
+    }
 }
 
 // Pass 2: row k_R of tmp (n = n_r points) -> IFFT_r(kin o FFT_r(row)), stored
@@ -139,7 +159,8 @@ __global__ void __launch_bounds__(exact_threads<LOG2N>()) k_exact_rows_inv(doubl
 
 template <int L>
 void pass_rows_fwd(int nr, const ExactBufs &e, hipStream_t s) {
-    hipLaunchKernelGGL(k_exact_rows_fwd<L>, dim3(nr), dim3(exact_threads<L>()), 0, s, e.psi, e.half, e.tw_R, e.tmp, nr);
+    hipLaunchKernelGGL(k_exact_rows_fwd<L>, dim3(nr / fwd_rows<L>()), dim3(fwd_rows<L>() * fwd_group<L>()), 0, s,
+                       e.psi, e.half, e.tw_R, e.tmp, nr);
 }
 template <int L>
 void pass_cols(int nR, const ExactBufs &e, hipStream_t s) {

@@ -15,6 +15,14 @@ One step t_k -> t_k+1 = t_k + dt (the paper gives no integrator; reading taken):
 
 K^- uses the conditioning of the step just taken (the CWFs moved under it);
 K_k+1 uses the new positions, which condition the next step.
+
+Heun trajectories (Setup.trajectories = "heun"; the paper fixes the velocity
+field of Eqs. 10-11, not how it is integrated): (b) gives only the predictor
+x~ = x_k + dt v_k; after (c)-(e) the velocity field of the new state
+(C_k+1, psi_k+1) is evaluated at x~, and the trajectories take the trapezoid
+x_k+1 = x_k + dt/2 (v_k + v(x~, t_k+1)).  The CWF propagation keeps the
+conditioning frozen at x_k, K^- is unchanged, and K_k+1 is formed at the
+corrected positions.
 """
 
 from dataclasses import dataclass, field
@@ -40,6 +48,7 @@ class Setup:
     dt: float
     eps: float = 1e-8
     propagator: str = "strang"     # or "cn" (Crank-Nicolson, oracle.propagate)
+    trajectories: str = "euler"    # or "heun" (predictor x_k + dt v_k, trapezoid corrector)
 
     def __post_init__(self):
         self.r, self.hr = grid.points(self.r_min, self.r_max, self.n_r)
@@ -83,22 +92,35 @@ def init(setup, r0, R0, psi1, psi2, C0=None, b0=None):
     return State(psi1, psi2, C, r0, R0, S, K, fac)
 
 
+def _velocities(setup, C, psi1, psi2, r_traj, R_traj):
+    return velocity.velocities(C, psi1, psi2, setup.r_min, setup.hr, setup.R_min, setup.hR,
+                               setup.m_r, setup.m_R, r_traj, R_traj)
+
+
 def step(setup, st):
     """Advance the state by one step (a)-(e) above; returns the new State."""
-    v_r, v_R, psi_at = velocity.velocities(st.C, st.psi1, st.psi2, setup.r_min, setup.hr,
-                                           setup.R_min, setup.hR, setup.m_r, setup.m_R,
-                                           st.r_traj, st.R_traj)
+    v_r, v_R, psi_at = _velocities(setup, st.C, st.psi1, st.psi2, st.r_traj, st.R_traj)
     r_new = st.r_traj + setup.dt * v_r
     R_new = st.R_traj + setup.dt * v_R
     p1, p2 = propagate.propagate_cwfs(st.psi1, st.psi2, setup.model, setup.r, setup.R,
                                       setup.hr, setup.hR, setup.m_r, setup.m_R,
                                       st.r_traj, st.R_traj, setup.dt, setup.propagator)
-    S1, (Kminus, Knew) = _couplings(setup, p1, p2, [(st.r_traj, st.R_traj), (r_new, R_new)])
-    C_new, fac1 = coeffs.rk4_step(st.C, st.S, st.K, S1, Kminus, setup.eps, setup.dt, st.fac)
+    min_psi = float(np.min(np.abs(psi_at)))
+    if setup.trajectories == "heun":
+        S1, (Kminus,) = _couplings(setup, p1, p2, [(st.r_traj, st.R_traj)])
+        C_new, fac1 = coeffs.rk4_step(st.C, st.S, st.K, S1, Kminus, setup.eps, setup.dt, st.fac)
+        w_r, w_R, psi_pred = _velocities(setup, C_new, p1, p2, r_new, R_new)
+        r_new = st.r_traj + 0.5 * setup.dt * (v_r + w_r)
+        R_new = st.R_traj + 0.5 * setup.dt * (v_R + w_R)
+        _, (Knew,) = _couplings(setup, p1, p2, [(r_new, R_new)])
+        min_psi = min(min_psi, float(np.min(np.abs(psi_pred))))
+    else:
+        S1, (Kminus, Knew) = _couplings(setup, p1, p2, [(st.r_traj, st.R_traj), (r_new, R_new)])
+        C_new, fac1 = coeffs.rk4_step(st.C, st.S, st.K, S1, Kminus, setup.eps, setup.dt, st.fac)
     out = ((r_new < setup.r_min) | (r_new >= setup.r_max)
            | (R_new < setup.R_min) | (R_new >= setup.R_max))
     return State(p1, p2, C_new, r_new, R_new, S1, Knew, fac1, st.t + setup.dt, st.step + 1,
-                 int(np.count_nonzero(out)), float(np.min(np.abs(psi_at))))
+                 int(np.count_nonzero(out)), min_psi)
 
 
 def observe(setup, st, bo=None):

@@ -87,8 +87,9 @@ def test_free_gaussian_velocity_field():
     assert v_R[0] == pytest.approx(ref_R, abs=1e-11)
 
 
-def _free_traj_error(dt, T=2.0):
+def _free_traj_error(dt, T=2.0, trajectories="euler"):
     st_ = _free_setup(dt)
+    st_.trajectories = trajectories
     p1 = free_gaussian(st_.r, 0.0, -2.0, 0.5, 1.0, 1.0)[None, :]
     p2 = free_gaussian(st_.R, 0.0, 1.0, -1.0, 0.5, 10.0)[None, :]
     state = icwf.init(st_, [-1.2], [1.3], p1, p2, C0=[1.0 + 0j])
@@ -107,6 +108,16 @@ def test_free_gaussian_trajectory_first_order():
     e1, e2 = _free_traj_error(0.1), _free_traj_error(0.05)
     assert e1 < 3e-2
     assert 1.8 < e1 / e2 < 2.2
+
+
+def test_free_gaussian_trajectory_heun_second_order():
+    """The same closed-form Bohmian paths with Heun trajectories (Euler
+    predictor, trapezoid corrector with the velocity field of the new state):
+    the error falls as dt^2."""
+    e1, e2 = _free_traj_error(0.1, trajectories="heun"), _free_traj_error(0.05, trajectories="heun")
+    assert e1 < 1e-3
+    assert 3.5 < e1 / e2 < 4.5
+    assert e1 < 0.1 * _free_traj_error(0.1)
 
 
 def test_node_raises():

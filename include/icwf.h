@@ -109,6 +109,16 @@ typedef enum {
                                      ICWF_EINVAL                                       */
 } icwf_propagator;
 
+/* How the trajectories follow the Bohmian velocity field of Eqs. 10-11 over a
+ * step (the paper fixes the field, not the integrator). */
+typedef enum {
+    ICWF_TRAJ_EULER = 0,  /* x_k+1 = x_k + dt v(x_k, t_k) (the default)                      */
+    ICWF_TRAJ_HEUN = 1    /* predictor x~ = x_k + dt v(x_k, t_k); after the CWFs and C have
+                             advanced, x_k+1 = x_k + dt/2 (v(x_k, t_k) + v(x~, t_k+1)), the
+                             field of the new state evaluated at x~; the CWF propagation
+                             stays conditioned on x_k; K_k+1 at the corrected positions   */
+} icwf_trajectories;
+
 typedef struct {
     int32_t n_traj;          /* N: trajectories = basis size of Eq. 7 (the paper's M)   */
     int32_t n_r, n_R;        /* grid points: powers of two, 32 <= n <= 4096             */
@@ -123,6 +133,7 @@ typedef struct {
     int32_t n_bo;            /* BO states used by the populations (0: none)             */
     int32_t solver;          /* icwf_solver (0: automatic)                              */
     int32_t propagator;      /* icwf_propagator (0: split operator)                     */
+    int32_t trajectories;    /* icwf_trajectories (0: explicit Euler)                   */
 } icwf_config;
 
 /* Observables at the current step (text around the Shin-Metiu figure of the

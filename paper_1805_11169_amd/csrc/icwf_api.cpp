@@ -124,6 +124,7 @@ const char *validate(const icwf_config *c) {
     if (c->n_bo < 0 || c->n_bo > c->n_r) return "n_bo must be in [0, n_r]";
     if (c->solver < ICWF_SOLVER_AUTO || c->solver > ICWF_SOLVER_INVERSE) return "unknown solver";
     if (c->propagator != ICWF_PROP_SPLIT && c->propagator != ICWF_PROP_CRANK_NICOLSON) return "unknown propagator";
+    if (c->trajectories != ICWF_TRAJ_EULER && c->trajectories != ICWF_TRAJ_HEUN) return "unknown trajectory integrator";
     if (c->propagator == ICWF_PROP_CRANK_NICOLSON && (c->n_r > 2048 || c->n_R > 2048))
         return "the Crank-Nicolson propagator takes grids of at most 2048 points";
     if (c->solver == ICWF_SOLVER_INVERSE && !icwf::use_sinv(icwf::padded(c->n_traj), c->precision, c->solver))
@@ -191,7 +192,8 @@ int cross_approximation(std::vector<double> &W, int n, int m, double tol, int km
     return k;
 }
 
-// Relative size of the residual the mixed form leaves to FP32.
+// Largest relative residual the mixed form leaves to FP32 (more terms are
+// taken where they fill the FP64 part's last block of 16).
 constexpr double kMixedSplitTol = 1e-4;
 // Residual the separable form accepts: a few roundings of the table itself.
 constexpr double kSeparableTol = 4.0 * 2.220446049250313e-16;
@@ -203,6 +205,13 @@ struct Timer {
 };
 
 }  // namespace
+
+namespace icwf {
+icwf_status set_create_error(icwf_status st, const char *msg) {
+    g_create_error = msg ? msg : "";
+    return st;
+}
+}  // namespace icwf
 
 struct icwf_sim {
     icwf_config cfg{};
@@ -280,7 +289,8 @@ void enqueue_step(icwf_sim *s, int parity, hipStream_t st, hipStream_t side) {
     if (s->Np < kOverlapMinN) side = st;
     const Dims &d = s->d;
     const Bufs &b = s->b;
-    timed(s, "velocity", st, [&] { icwf::launch_velocity(d, b, true, st); });
+    const bool heun = d.traj == ICWF_TRAJ_HEUN;
+    timed(s, "velocity", st, [&] { icwf::launch_velocity(d, b, icwf::kVelocityEuler, st); });
     timed(s, "propagate", st, [&] {
         icwf::launch_propagate(d, b, 1, st);
         icwf::launch_propagate(d, b, 2, st);
@@ -295,9 +305,10 @@ void enqueue_step(icwf_sim *s, int parity, hipStream_t st, hipStream_t side) {
     const bool roomy = d.prec != ICWF_PREC_SEPARABLE && (size_t)d.nr * d.nR >= 256 * (size_t)s->Np;
     const hipStream_t ss = fork && ((d.prec == ICWF_PREC_FP64 && !d.sinv) || roomy) ? side : st;
     auto single_species = [&] {
+        // with Heun trajectories the integrals at x_k+1 wait for the corrector
         timed(s, "zgemm", ss, [&] {
-            icwf::launch_cond_kets(d, b, ss);
-            icwf::launch_single_species(d, b, true, ss);
+            icwf::launch_cond_kets(d, b, ss, !heun);
+            icwf::launch_single_species(d, b, !heun, ss);
         });
     };
     if (ss == st) single_species();
@@ -314,8 +325,19 @@ void enqueue_step(icwf_sim *s, int parity, hipStream_t st, hipStream_t side) {
     if (fork) (void)hipEventRecord(s->ev_join, side);
     timed(s, "wc_contract", st, [&] { icwf::launch_wc(d, b, st); });
     if (fork) (void)hipStreamWaitEvent(st, s->ev_join, 0);
-    timed(s, "assemble", st, [&] { icwf::launch_assemble(d, b, parity, icwf::kAssembleK, st); });
+    timed(s, "assemble", st, [&] {
+        icwf::launch_assemble(d, b, parity, heun ? icwf::kAssembleKminus : icwf::kAssembleK, st);
+    });
     timed(s, "rk4", st, [&] { icwf::launch_rk4(d, b, parity, st); });
+    if (heun) {
+        // corrector at the advanced state, then K_k+1 at the corrected positions
+        timed(s, "velocity", st, [&] { icwf::launch_velocity(d, b, icwf::kVelocityHeun, st); });
+        timed(s, "zgemm", st, [&] {
+            icwf::launch_cond_kets_next(d, b, st);
+            icwf::launch_single_species_next(d, b, st);
+        });
+        timed(s, "assemble", st, [&] { icwf::launch_assemble(d, b, parity, icwf::kAssembleKnext, st); });
+    }
 }
 
 icwf_status device_status(icwf_sim *s) {
@@ -415,6 +437,7 @@ icwf_status icwf_create(const icwf_config *cfg, const double *r0, const double *
     d.prec = cfg->precision;
     d.sinv = icwf::use_sinv(icwf::padded(N), cfg->precision, cfg->solver) ? 1 : 0;
     d.propagator = cfg->propagator;
+    d.traj = cfg->trajectories;
     d.r_min = cfg->r_min;
     d.hr = (cfg->r_max - cfg->r_min) / nr;
     d.R_min = cfg->R_min;
@@ -475,12 +498,23 @@ icwf_status icwf_create(const icwf_config *cfg, const double *r0, const double *
     if (cfg->precision == ICWF_PREC_MIXED) {
         std::vector<double> res = wc;
         d.lr_rank = cross_approximation(res, nr, nR, kMixedSplitTol, icwf::kLowRankMax, lr_u, lr_v);
-        double wmax = 0.0, rmax = 0.0;
-        for (size_t e = 0; e < res.size(); ++e) {
-            wc32[e] = static_cast<float>(res[e]);
-            wmax = std::max(wmax, std::fabs(wc[e]));
-            rmax = std::max(rmax, std::fabs(res[e]));
+        auto maxabs = [](const std::vector<double> &v) {
+            double m = 0.0;
+            for (double x : v) m = std::max(m, std::fabs(x));
+            return m;
+        };
+        const double wmax = maxabs(wc);
+        double rmax = maxabs(res);
+        // the FP64 part runs in blocks of 16 terms, so terms up to the next
+        // multiple of 16 cost nothing: take them (down to the table's rounding),
+        // which leaves a smaller residual, and so a smaller FP32 error, to the
+        // matrix-core pass
+        const int fill = std::min(icwf::kLowRankMax, (d.lr_rank + 15) / 16 * 16);
+        if (d.lr_rank > 0 && fill > d.lr_rank && rmax > kSeparableTol * wmax) {
+            d.lr_rank += cross_approximation(res, nr, nR, kSeparableTol * wmax / rmax, fill - d.lr_rank, lr_u, lr_v);
+            rmax = maxabs(res);
         }
+        for (size_t e = 0; e < res.size(); ++e) wc32[e] = static_cast<float>(res[e]);
         // a residual at the table's own rounding level (an exactly separable
         // coupling, such as the cavity's lambda q x) leaves the FP32 pass
         // nothing to add: the FP64 rank-K part is then the whole contraction
@@ -664,7 +698,7 @@ icwf_status icwf_get_matrices(icwf_sim *s, double *S, double *K, double *Wc) {
 icwf_status icwf_velocities(icwf_sim *s, double *v_r, double *v_R, double *psi_at) {
     if (!s) return fail(nullptr, ICWF_EINVAL, "sim is NULL");
     if (s->status != ICWF_OK) return fail(s, ICWF_ESTATE, "the simulation stopped on an earlier error");
-    icwf::launch_velocity(s->d, s->b, false, s->stream);
+    icwf::launch_velocity(s->d, s->b, icwf::kVelocityOnly, s->stream);
     HIP_OK(hipGetLastError(), s);
     icwf_status st = device_status(s);
     const Dims &d = s->d;

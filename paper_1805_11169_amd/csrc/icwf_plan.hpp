@@ -6,6 +6,7 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include "../../include/icwf.h"
 #include "icwf_device.hpp"
 
 namespace icwf {
@@ -16,6 +17,7 @@ struct Dims {
     int fp32_residual;                    // mixed form: the residual left to FP32 is not negligible
     int sinv;                             // RK4 stages through explicit inverses of S + eps I
     int propagator;                       // 0 split operator, 1 Crank-Nicolson
+    int traj;                             // 0 explicit Euler trajectories, 1 Heun
     int wc_grid;                          // work-groups of the persistent two-body contraction
     int prop_grid[2];                     // work-groups of the persistent propagation, per species
     double r_min, hr, R_min, hR, m_r, m_R, dt, eps;
@@ -114,16 +116,27 @@ void launch_propagate_cn(const Dims &d, const Bufs &b, int species, hipStream_t 
 // as many as fit the device's ncu compute units at once, at most one per CWF group.
 int propagate_grid(int n, int N, int ncu);
 
-// Periodic-sinc tables at the current positions, velocity contraction and
-// reduction; writes v_r, v_R, psi_at, r_new, R_new (x + dt v), the constant
-// potential phases cphase of the CWFs conditioned on r, R, and the flags.
-void launch_velocity(const Dims &d, const Bufs &b, bool update_positions, hipStream_t s);
+// Periodic-sinc tables at the positions, velocity contraction and reduction
+// (v_r, v_R, psi_at, min |Psi| and the flags).  mode kVelocityOnly: at r, R,
+// nothing else; kVelocityEuler: at r, R, and r_new, R_new = x + dt v plus the
+// constant potential phases cphase of the CWFs conditioned on r, R (the step's
+// first pass); kVelocityHeun: the field of the advanced state at the
+// predictor r_new, R_new, then r = r_new = r + dt/2 (v_r + v), the same for R
+// (v_r, v_R keep the first pass's values; the out-of-box count is redone).
+enum VelocityMode { kVelocityOnly = 0, kVelocityEuler = 1, kVelocityHeun = 2 };
+void launch_velocity(const Dims &d, const Bufs &b, VelocityMode mode, hipStream_t s);
 
-// Conditioned kets G = W_c(., x) psi for the two conditionings x_k, x_k+1.
-void launch_cond_kets(const Dims &d, const Bufs &b, hipStream_t s);
+// Conditioned kets G = W_c(., x) psi: G1a, G2a at x_k = (r, R) and, with
+// `next`, G1b, G2b at x_k+1 = (r_new, R_new).
+void launch_cond_kets(const Dims &d, const Bufs &b, hipStream_t s, bool next = true);
+// G1b, G2b alone, at (r_new, R_new).
+void launch_cond_kets_next(const Dims &d, const Bufs &b, hipStream_t s);
 
-// Batched h * conj(X) Y^T complex products: S1, S2, E1a, E1b, E2a, E2b.
+// Batched h * conj(X) Y^T complex products: S1, S2, E1a, E2a and, with
+// both_conditionings, E1b, E2b.
 void launch_single_species(const Dims &d, const Bufs &b, bool both_conditionings, hipStream_t s);
+// E1b, E2b alone.
+void launch_single_species_next(const Dims &d, const Bufs &b, hipStream_t s);
 
 // Two-body contraction Wc (upper pair tiles), FP64 or FP32 matrix cores.
 void launch_wc(const Dims &d, const Bufs &b, hipStream_t s);
@@ -131,8 +144,16 @@ void launch_wc(const Dims &d, const Bufs &b, hipStream_t s);
 // The step's matrices from the single-species and two-body blocks:
 //   kAssembleS: S_next and the regularised midpoint / endpoint S + eps I;
 //   kAssembleK: K_minus, K_next and the midpoint K;
-//   kAssembleInitial: S_0, K_0 and S_0 + eps I (start of the run).
-enum AssemblePart { kAssembleS = 1, kAssembleK = 2, kAssembleInitial = 3 };
+//   kAssembleInitial: S_0, K_0 and S_0 + eps I (start of the run);
+//   kAssembleKminus: K_minus and the midpoint K only (Heun trajectories);
+//   kAssembleKnext: K_next only, at (r_new, R_new) (Heun, after the corrector).
+enum AssemblePart {
+    kAssembleS = 1,
+    kAssembleK = 2,
+    kAssembleInitial = 3,
+    kAssembleKminus = 2 | 4,
+    kAssembleKnext = 2 | 8
+};
 void launch_assemble(const Dims &d, const Bufs &b, int parity, AssemblePart part, hipStream_t s);
 
 // In-place lower Cholesky of `count` matrices (A0, A1), each Np x Np, and the
@@ -177,5 +198,9 @@ void launch_psi1_f32(const Dims &d, const Bufs &b, hipStream_t s);
 
 // Fill n int32 with a value (graph-safe replacement for a memset).
 void launch_fill_i32(int32_t *p, int n, int32_t v, hipStream_t s);
+
+// Records the message icwf_last_error(NULL) returns (calls without a
+// handle) and passes the status through.
+icwf_status set_create_error(icwf_status st, const char *msg);
 
 }  // namespace icwf

@@ -551,14 +551,24 @@ __global__ void __launch_bounds__(256, 2) k_wc_sep(const double2 *__restrict__ p
 
 }  // namespace
 
-void launch_cond_kets(const Dims &d, const Bufs &b, hipStream_t s) {
+void launch_cond_kets(const Dims &d, const Bufs &b, hipStream_t s, bool next) {
     const int Np = padded(d.N);
     size_t tot = (size_t)Np * d.nr;
     hipLaunchKernelGGL(k_cond_kets, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, b.psi1, d.nr, d.r_min,
-                       d.hr, b.R, b.R_new, 1, d.mp, b.G1a, b.G1b, Np, b.flags);
+                       d.hr, b.R, b.R_new, 1, d.mp, b.G1a, next ? b.G1b : nullptr, Np, b.flags);
     tot = (size_t)Np * d.nR;
     hipLaunchKernelGGL(k_cond_kets, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, b.psi2, d.nR, d.R_min,
-                       d.hR, b.r, b.r_new, 2, d.mp, b.G2a, b.G2b, Np, b.flags);
+                       d.hR, b.r, b.r_new, 2, d.mp, b.G2a, next ? b.G2b : nullptr, Np, b.flags);
+}
+
+void launch_cond_kets_next(const Dims &d, const Bufs &b, hipStream_t s) {
+    const int Np = padded(d.N);
+    size_t tot = (size_t)Np * d.nr;
+    hipLaunchKernelGGL(k_cond_kets, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, b.psi1, d.nr, d.r_min,
+                       d.hr, b.R_new, b.R_new, 1, d.mp, b.G1b, nullptr, Np, b.flags);
+    tot = (size_t)Np * d.nR;
+    hipLaunchKernelGGL(k_cond_kets, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, b.psi2, d.nR, d.R_min,
+                       d.hR, b.r_new, b.r_new, 2, d.mp, b.G2b, nullptr, Np, b.flags);
 }
 
 void launch_single_species(const Dims &d, const Bufs &b, bool both, hipStream_t s) {
@@ -582,6 +592,22 @@ void launch_single_species(const Dims &d, const Bufs &b, bool both, hipStream_t 
         add(b.psi2, b.G2b, b.E2b, d.nR, d.hR);
     }
     hipLaunchKernelGGL(k_zgemm, dim3(Np / kZT, Np / kZT, c), dim3(256), 0, s, zb, Np, b.flags);
+}
+
+void launch_single_species_next(const Dims &d, const Bufs &b, hipStream_t s) {
+    const int Np = padded(d.N);
+    ZBatch zb{};
+    zb.X[0] = b.psi1;
+    zb.Y[0] = b.G1b;
+    zb.out[0] = b.E1b;
+    zb.K[0] = d.nr;
+    zb.scale[0] = d.hr;
+    zb.X[1] = b.psi2;
+    zb.Y[1] = b.G2b;
+    zb.out[1] = b.E2b;
+    zb.K[1] = d.nR;
+    zb.scale[1] = d.hR;
+    hipLaunchKernelGGL(k_zgemm, dim3(Np / kZT, Np / kZT, 2), dim3(256), 0, s, zb, Np, b.flags);
 }
 
 void launch_wc(const Dims &d, const Bufs &b, hipStream_t s) {

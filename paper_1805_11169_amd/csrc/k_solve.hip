@@ -75,17 +75,19 @@ __global__ void k_assemble(const double2 *__restrict__ S1, const double2 *__rest
         ca = model_v1(mp, r[a]) + model_v2(mp, R[a]);
         cn = model_v1(mp, r_new[a]) + model_v2(mp, R_new[a]);
     }
-    const double2 km = csub(csub(csub(w, cmul(E1a[idx], s2)), cmul(s1, E2a[idx])), cscale(S, ca));
-    if (part == kAssembleInitial) {
-        // start of the run: K_0 = K(psi_0, x_0) -> the slot of parity 0
-        Knext[idx] = km;
-        return;
+    if (part != kAssembleKnext) {
+        const double2 km = csub(csub(csub(w, cmul(E1a[idx], s2)), cmul(s1, E2a[idx])), cscale(S, ca));
+        if (part == kAssembleInitial) {
+            // start of the run: K_0 = K(psi_0, x_0) -> the slot of parity 0
+            Knext[idx] = km;
+            return;
+        }
+        Kminus[idx] = km;
+        const double2 kc = Kcur[idx];
+        Kmid[idx] = make_double2(0.5 * (kc.x + km.x), 0.5 * (kc.y + km.y));
     }
-    const double2 kn = csub(csub(csub(w, cmul(E1b[idx], s2)), cmul(s1, E2b[idx])), cscale(S, cn));
-    Kminus[idx] = km;
-    Knext[idx] = kn;
-    const double2 kc = Kcur[idx];
-    Kmid[idx] = make_double2(0.5 * (kc.x + km.x), 0.5 * (kc.y + km.y));
+    if (part != kAssembleKminus)
+        Knext[idx] = csub(csub(csub(w, cmul(E1b[idx], s2)), cmul(s1, E2b[idx])), cscale(S, cn));
 }
 
 // ------------------------------------------------------------------ Cholesky
@@ -647,7 +649,7 @@ __device__ inline void stage_update(int ii, double2 u, int stage, double dt, int
             const double2 cn = cadd(c, cscale(cadd(Cacc[ii], k), dt / 6.0));
             C[ii] = cn;
             bad = !(isfinite(cn.x) && isfinite(cn.y));
-            if (ii < N) {
+            if (ii < N && r) {   // r == nullptr: Heun trajectories, positions set by the corrector
                 r[ii] = r_new[ii];
                 R[ii] = R_new[ii];
             }
@@ -861,6 +863,8 @@ void launch_rk4(const Dims &d, const Bufs &b, int parity, hipStream_t s) {
     const double2 *Ls[4] = {b.L[cur], b.Lmid, b.Lmid, b.L[nxt]};
     const double2 *Xs[4] = {b.Linv[cur], b.Linvmid, b.Linvmid, b.Linv[nxt]};
     const double2 *Ss[4] = {b.Sinv[cur], b.Sinvmid, b.Sinvmid, b.Sinv[nxt]};
+    // with Heun trajectories the last stage leaves x_k in place for the corrector
+    double *cr = d.traj == 1 ? nullptr : b.r, *cR = d.traj == 1 ? nullptr : b.R;
     for (int st = 1; st <= 4; ++st) {
         const double2 *v = (st == 1) ? b.C : b.Cstage;
         hipLaunchKernelGGL(k_matvec, dim3(Np / 4), dim3(256), 0, s, Ks[st - 1], v, b.rhs, Np, b.flags);
@@ -872,13 +876,13 @@ void launch_rk4(const Dims &d, const Bufs &b, int parity, hipStream_t s) {
             hipLaunchKernelGGL(k_rk_resid, dim3(Np / 4), dim3(256), 0, s, Sa, Sb, d.eps, b.y, b.rhs, b.xsol, Np,
                                b.flags);
             hipLaunchKernelGGL(k_rk_apply, dim3(Np / 4), dim3(256), 0, s, Ss[st - 1], b.xsol, b.y, Np, st, d.dt,
-                               d.N, b.C, b.Cacc, b.Cstage, b.r, b.R, b.r_new, b.R_new, b.flags);
+                               d.N, b.C, b.Cacc, b.Cstage, cr, cR, b.r_new, b.R_new, b.flags);
             continue;
         }
         hipLaunchKernelGGL(k_rk_fwd, dim3(nblk), dim3(256), 0, s, b.rhs, Ls[st - 1], Xs[st - 1], b.y, Np,
                            b.solve_sync, b.flags);
         hipLaunchKernelGGL(k_rk_bwd, dim3(nblk), dim3(256), 0, s, Ls[st - 1], Xs[st - 1], b.y, b.xsol, Np, nblk, st,
-                           d.dt, d.N, b.C, b.Cacc, b.Cstage, b.r, b.R, b.r_new, b.R_new, b.solve_sync, b.flags);
+                           d.dt, d.N, b.C, b.Cacc, b.Cstage, cr, cR, b.r_new, b.R_new, b.solve_sync, b.flags);
     }
 }
 

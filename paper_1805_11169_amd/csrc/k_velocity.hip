@@ -18,6 +18,9 @@
 //    through LDS, followed in registers by the b-sums with C over the tile.
 // 3. k_vel_finish: sums the tile partials, forms v, updates x, raises flags,
 //    and writes the per-CWF constant potential phases the propagation uses.
+//    With Heun trajectories a second pass after the coefficient update
+//    evaluates the field of the new state at the Euler predictor and applies
+//    the trapezoid corrector x_k + dt/2 (v_k + v~).
 #include "icwf_plan.hpp"
 #include "icwf_expi.hpp"
 
@@ -240,10 +243,10 @@ __global__ void __launch_bounds__(256) k_vel_gemm(const double *__restrict__ Sr,
 __device__ inline unsigned long long dbits(double x) { return (unsigned long long)__double_as_longlong(x); }
 
 __global__ void k_vel_finish(const double2 *__restrict__ part, int N, int Np, double m_r, double m_R, double dt,
-                             const double *__restrict__ r, const double *__restrict__ R, double *__restrict__ r_new,
+                             double *__restrict__ r, double *__restrict__ R, double *__restrict__ r_new,
                              double *__restrict__ R_new, double *__restrict__ v_r, double *__restrict__ v_R,
                              double2 *__restrict__ psi_at, double r_lo, double r_hi, double R_lo, double R_hi,
-                             ModelParams mp, double2 *__restrict__ cphase, int update, int32_t *__restrict__ flags,
+                             ModelParams mp, double2 *__restrict__ cphase, int mode, int32_t *__restrict__ flags,
                              unsigned long long *__restrict__ min_bits) {
     if (flags[kFlagHalt]) return;
     const int a = blockIdx.x * blockDim.x + threadIdx.x;
@@ -252,8 +255,10 @@ __global__ void k_vel_finish(const double2 *__restrict__ part, int N, int Np, do
     // constant on the grid of each CWF conditioned on this trajectory (V_2 at
     // R^a for the electronic CWF, V_1 at r^a for the nuclear one), at the
     // positions the propagation of this step conditions on
-    cphase[a] = expi(-0.5 * dt * model_v2(mp, R[a]));
-    cphase[Np + a] = expi(-0.5 * dt * model_v1(mp, r[a]));
+    if (mode == kVelocityEuler) {
+        cphase[a] = expi(-0.5 * dt * model_v2(mp, R[a]));
+        cphase[Np + a] = expi(-0.5 * dt * model_v1(mp, r[a]));
+    }
     const int ntile = Np / kVB;
     double2 ps = make_double2(0, 0), nr = make_double2(0, 0), nR = make_double2(0, 0);
     for (int t = 0; t < ntile; ++t) {
@@ -276,9 +281,23 @@ __global__ void k_vel_finish(const double2 *__restrict__ part, int N, int Np, do
     // Im(n / Psi) = (n.y Psi.x - n.x Psi.y) / |Psi|^2
     const double vr = (nr.y * ps.x - nr.x * ps.y) / mag2 / m_r;
     const double vR = (nR.y * ps.x - nR.x * ps.y) / mag2 / m_R;
+    if (mode == kVelocityHeun) {
+        // trapezoid corrector: the first pass's v (at x_k) and this field at the predictor
+        const double xr = r[a] + 0.5 * dt * (v_r[a] + vr), xR = R[a] + 0.5 * dt * (v_R[a] + vR);
+        r[a] = xr;
+        R[a] = xR;
+        r_new[a] = xr;
+        R_new[a] = xR;
+        if (!isfinite(xr) || !isfinite(xR)) {
+            atomicOr(&flags[kFlagNonfinite], 1);
+            atomicOr(&flags[kFlagHalt], 1);
+        }
+        if (xr < r_lo || xr >= r_hi || xR < R_lo || xR >= R_hi) atomicAdd(&flags[kFlagOut], 1);
+        return;
+    }
     v_r[a] = vr;
     v_R[a] = vR;
-    if (update) {
+    if (mode == kVelocityEuler) {
         const double xr = r[a] + dt * vr, xR = R[a] + dt * vR;
         r_new[a] = xr;
         R_new[a] = xR;
@@ -290,28 +309,32 @@ __global__ void k_vel_finish(const double2 *__restrict__ part, int N, int Np, do
     }
 }
 
-__global__ void k_vel_reset(int32_t *flags, unsigned long long *min_bits) {
+__global__ void k_vel_reset(int32_t *flags, unsigned long long *min_bits, int keep_min) {
     if (threadIdx.x == 0) {
         flags[kFlagOut] = 0;
-        *min_bits = 0x7ff0000000000000ULL;   // +inf
+        if (!keep_min) *min_bits = 0x7ff0000000000000ULL;   // +inf
     }
 }
 
 }  // namespace
 
-void launch_velocity(const Dims &d, const Bufs &b, bool update, hipStream_t s) {
+void launch_velocity(const Dims &d, const Bufs &b, VelocityMode mode, hipStream_t s) {
     const int Np = padded(d.N);
-    hipLaunchKernelGGL(k_sinc, dim3(Np), dim3(256), 0, s, b.r, Np, d.nr, d.r_min, d.hr, b.sinc_r, b.dsinc_r, b.flags);
-    hipLaunchKernelGGL(k_sinc, dim3(Np), dim3(256), 0, s, b.R, Np, d.nR, d.R_min, d.hR, b.sinc_R, b.dsinc_R,
+    // the corrector evaluates the field at the predictor positions
+    const double *pr = mode == kVelocityHeun ? b.r_new : b.r;
+    const double *pR = mode == kVelocityHeun ? b.R_new : b.R;
+    hipLaunchKernelGGL(k_sinc, dim3(Np), dim3(256), 0, s, pr, Np, d.nr, d.r_min, d.hr, b.sinc_r, b.dsinc_r, b.flags);
+    hipLaunchKernelGGL(k_sinc, dim3(Np), dim3(256), 0, s, pR, Np, d.nR, d.R_min, d.hR, b.sinc_R, b.dsinc_R,
                        b.flags);
     hipLaunchKernelGGL(k_vel_gemm, dim3(Np / kVA, Np / kVB), dim3(256), 0, s, b.sinc_r, b.dsinc_r, b.psi1, d.nr,
                        b.sinc_R, b.dsinc_R, b.psi2, d.nR, b.C, Np, b.vpart, b.flags);
     unsigned long long *min_bits = reinterpret_cast<unsigned long long *>(b.scal);
-    hipLaunchKernelGGL(k_vel_reset, dim3(1), dim3(64), 0, s, b.flags, min_bits);
+    // min |Psi| over the step's evaluations: the corrector keeps the first pass's minimum
+    hipLaunchKernelGGL(k_vel_reset, dim3(1), dim3(64), 0, s, b.flags, min_bits, mode == kVelocityHeun ? 1 : 0);
     const double r_hi = d.r_min + d.hr * d.nr, R_hi = d.R_min + d.hR * d.nR;
     hipLaunchKernelGGL(k_vel_finish, dim3((d.N + 255) / 256), dim3(256), 0, s, b.vpart, d.N, Np, d.m_r, d.m_R,
                        d.dt, b.r, b.R, b.r_new, b.R_new, b.v_r, b.v_R, b.psi_at, d.r_min, r_hi, d.R_min, R_hi, d.mp,
-                       b.cphase, update ? 1 : 0, b.flags, min_bits);
+                       b.cphase, (int)mode, b.flags, min_bits);
 }
 
 }  // namespace icwf

@@ -20,6 +20,7 @@ MODEL_SHIN_METIU, MODEL_CAVITY = 1, 2
 PREC_FP64, PREC_MIXED, PREC_SEPARABLE = 0, 1, 2
 SOLVER_AUTO, SOLVER_TRIANGULAR, SOLVER_INVERSE = 0, 1, 2
 PROP_SPLIT, PROP_CRANK_NICOLSON = 0, 1
+TRAJ_EULER, TRAJ_HEUN = 0, 1
 
 # the entry points include/icwf.h declares
 EXPORTS = ("icwf_workspace_bytes", "icwf_create", "icwf_step", "icwf_sync", "icwf_observables",
@@ -32,6 +33,9 @@ SERVE_EXPORTS = ("icwf_server_create", "icwf_server_submit", "icwf_server_wait",
 # the entry points include/icwf_exact.h declares
 EXACT_EXPORTS = ("icwf_exact_workspace_bytes", "icwf_exact_create", "icwf_exact_step", "icwf_exact_observables",
                  "icwf_exact_get_psi", "icwf_exact_destroy")
+# the entry points include/icwf_bo.h declares
+BO_EXPORTS = ("icwf_bo_workspace_bytes", "icwf_bo_states")
+BO_MAX_STATES = 8
 
 
 class Config(ctypes.Structure):
@@ -40,7 +44,7 @@ class Config(ctypes.Structure):
                 ("m_r", c_double), ("m_R", c_double), ("dt", c_double),
                 ("model", c_int32), ("model_params", c_double * 8), ("tikhonov_eps", c_double),
                 ("precision", c_int32), ("n_bo", c_int32), ("solver", c_int32),
-                ("propagator", c_int32)]
+                ("propagator", c_int32), ("trajectories", c_int32)]
 
 
 _DP = POINTER(c_double)
@@ -68,6 +72,11 @@ class ServerStats(ctypes.Structure):
     _fields_ = [("submitted", c_int64), ("admitted", c_int64), ("completed", c_int64), ("failed", c_int64),
                 ("active", c_int32), ("pending", c_int32), ("arena_bytes", c_size_t),
                 ("arena_in_use", c_size_t), ("arena_peak", c_size_t), ("peak_active", c_int32)]
+
+
+class BoInfo(ctypes.Structure):
+    _fields_ = [("tol", c_double), ("max_iter", c_int32), ("iterations", c_int32), ("max_residual", c_double),
+                ("unconverged", c_int32)]
 
 
 class ICWFError(RuntimeError):
@@ -145,6 +154,11 @@ def lib():
         L.icwf_exact_get_psi.restype = c_int32
         L.icwf_exact_destroy.argtypes = [c_void_p]
         L.icwf_exact_destroy.restype = None
+        L.icwf_bo_workspace_bytes.argtypes = [POINTER(Config), c_int32, c_int32]
+        L.icwf_bo_workspace_bytes.restype = c_size_t
+        L.icwf_bo_states.argtypes = [POINTER(Config), _DP, c_int32, c_int32, _DP, _DP, c_void_p, c_size_t, c_void_p,
+                                     POINTER(BoInfo)]
+        L.icwf_bo_states.restype = c_int32
         _lib = L
     return _lib
 
@@ -170,7 +184,7 @@ def _f64(a, n=None):
 
 
 def make_config(n_traj, n_r, n_R, r_box, R_box, m_r, m_R, dt, model, model_params, eps=1e-8,
-                precision=PREC_FP64, n_bo=0, solver=SOLVER_AUTO, propagator=PROP_SPLIT):
+                precision=PREC_FP64, n_bo=0, solver=SOLVER_AUTO, propagator=PROP_SPLIT, trajectories=TRAJ_EULER):
     c = Config()
     c.n_traj, c.n_r, c.n_R = int(n_traj), int(n_r), int(n_R)
     c.r_min, c.r_max = float(r_box[0]), float(r_box[1])
@@ -185,17 +199,52 @@ def make_config(n_traj, n_r, n_R, r_box, R_box, m_r, m_R, dt, model, model_param
     c.n_bo = int(n_bo)
     c.solver = int(solver)
     c.propagator = int(propagator)
+    c.trajectories = int(trajectories)
     return c
 
 
-def config_from_workload(wl, precision=PREC_FP64, eps=None, solver=SOLVER_AUTO, propagator=PROP_SPLIT):
+def config_from_workload(wl, precision=PREC_FP64, eps=None, solver=SOLVER_AUTO, propagator=PROP_SPLIT,
+                         trajectories=TRAJ_EULER):
     return make_config(wl.n_traj, wl.n_r, wl.n_R, (wl.r_min, wl.r_max), (wl.R_min, wl.R_max), wl.m_r, wl.m_R,
                        wl.dt, wl.model, wl.model_params, wl.eps if eps is None else eps, precision, wl.n_bo,
-                       solver, propagator)
+                       solver, propagator, trajectories)
 
 
 def workspace_bytes(cfg):
     return int(lib().icwf_workspace_bytes(byref(cfg)))
+
+
+def bo_workspace_bytes(cfg, n_values, n_states):
+    return int(lib().icwf_bo_workspace_bytes(byref(cfg), int(n_values), int(n_states)))
+
+
+def bo_states(cfg, R_values, n_states, tol=0.0, max_iter=0, device=0, check=True):
+    """The n_states lowest eigenpairs of h_e(R_j) for every R_j (include/icwf_bo.h):
+    returns (states [n_values][n_states][n_r], energies [n_values][n_states],
+    info dict with iterations, max_residual, unconverged, status)."""
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("the ICWF library needs a GPU; none is visible")
+    L = lib()
+    Rv = np.ascontiguousarray(R_values, dtype=np.float64)
+    nv = Rv.size
+    nbytes = L.icwf_bo_workspace_bytes(byref(cfg), nv, int(n_states))
+    if nbytes == 0:
+        raise ICWFError(EINVAL, "invalid arguments to icwf_bo_states")
+    dev = torch.device("cuda", device) if isinstance(device, int) else torch.device(device)
+    ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
+    aligned = (ws.data_ptr() + 255) & ~255
+    stream = torch.cuda.current_stream(dev)
+    states = np.zeros((nv, int(n_states), cfg.n_r))
+    energies = np.zeros((nv, int(n_states)))
+    info = BoInfo(float(tol), int(max_iter), 0, 0.0, 0)
+    st = L.icwf_bo_states(byref(cfg), _ptr(Rv), nv, int(n_states), _ptr(states), _ptr(energies), c_void_p(aligned),
+                          c_size_t(nbytes), c_void_p(stream.cuda_stream), byref(info))
+    del ws
+    out = dict(iterations=info.iterations, max_residual=info.max_residual, unconverged=info.unconverged, status=st)
+    if check and st != OK:
+        raise ICWFError(st, L.icwf_last_error(None).decode())
+    return states, energies, out
 
 
 class Simulation:
@@ -225,8 +274,9 @@ class Simulation:
         self.h = handle
 
     @classmethod
-    def from_workload(cls, wl, precision=PREC_FP64, C0=None, solver=SOLVER_AUTO, propagator=PROP_SPLIT, **kw):
-        cfg = config_from_workload(wl, precision, solver=solver, propagator=propagator)
+    def from_workload(cls, wl, precision=PREC_FP64, C0=None, solver=SOLVER_AUTO, propagator=PROP_SPLIT,
+                      trajectories=TRAJ_EULER, **kw):
+        cfg = config_from_workload(wl, precision, solver=solver, propagator=propagator, trajectories=trajectories)
         return cls(cfg, wl.r0, wl.R0, wl.psi1, wl.psi2, C0=C0, b0=None if C0 is not None else wl.b0,
                    bo=wl.bo, **kw)
 
@@ -447,11 +497,6 @@ class Server:
 
     def clock(self):
         return lib().icwf_server_clock(self.h)
-
-    def contraction_rank(self):
-        k = c_int32()
-        self._check(lib().icwf_contraction_rank(self.h, byref(k)))
-        return k.value
 
     def close(self):
         if getattr(self, "h", None):

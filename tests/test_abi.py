@@ -27,6 +27,7 @@ def test_header_and_binding_agree():
     assert declared_entry_points("icwf.h") == sorted(icwf.EXPORTS)
     assert declared_entry_points("icwf_serve.h") == sorted(icwf.SERVE_EXPORTS)
     assert declared_entry_points("icwf_exact.h") == sorted(icwf.EXACT_EXPORTS)
+    assert declared_entry_points("icwf_bo.h") == sorted(icwf.BO_EXPORTS)
 
 
 def test_library_exports_every_declared_symbol():
@@ -125,3 +126,14 @@ def test_exact_workspace_and_invalid_configs():
     st = icwf.lib().icwf_exact_create(ctypes.byref(bad), one, None, ctypes.c_void_p(256), ctypes.c_size_t(1 << 40),
                                       None, ctypes.byref(h))
     assert st == icwf.EINVAL
+
+
+def test_bo_workspace_and_argument_checks():
+    cfg = _cfg(n_r=512)
+    one = icwf.bo_workspace_bytes(cfg, 1, 3)
+    many = icwf.bo_workspace_bytes(cfg, 256, 3)
+    assert 0 < one < many
+    assert icwf.bo_workspace_bytes(cfg, 256, 0) == 0
+    assert icwf.bo_workspace_bytes(cfg, 256, icwf.BO_MAX_STATES + 1) == 0
+    assert icwf.bo_workspace_bytes(_cfg(n_r=32), 4, 9) == 0      # more than n_r / 4 states
+    assert icwf.bo_workspace_bytes(cfg, 0, 3) == 0

@@ -4,8 +4,15 @@ mixed.
 
 FP64 bar (also for the separable form, which is FP64 throughout): observables
 (norm, reduced densities, BO populations, decoherence) within 1e-10 of the
-oracle, relative to each array's largest entry.  Mixed bar: the same
-observables within 1e-5."""
+oracle, relative to each array's largest entry, and the trajectory positions
+r^a, R^a within 1e-9 of the largest |r^a|, |R^a| (at least 1).  Positions
+integrate the velocities Im(grad Psi / Psi) / m over 200 steps, and the
+coefficient solve amplifies rounding differences by up to 1/(2 sqrt(eps)) per
+solve: the oracle run against itself with the upper instead of the lower
+Cholesky factor already differs by 3.1e-11 of max |r| (4.3e-10 absolute) at
+step 200, where its observables differ by 1.4e-11; the GPU path, which
+reorders almost every sum, sits at about ten times that.  Mixed bar: the same
+observables and positions within 1e-5."""
 
 import numpy as np
 import pytest
@@ -30,8 +37,8 @@ def c1():
     return wl, hist
 
 
-def _gpu_history(wl, precision, solver=icwf.SOLVER_AUTO):
-    sim = icwf.Simulation.from_workload(wl, precision=precision, solver=solver)
+def _gpu_history(wl, precision, solver=icwf.SOLVER_AUTO, trajectories=icwf.TRAJ_EULER):
+    sim = icwf.Simulation.from_workload(wl, precision=precision, solver=solver, trajectories=trajectories)
     out = []
     for _ in range(STEPS // EVERY):
         sim.step(EVERY)
@@ -47,8 +54,9 @@ def _compare(gpu, ref):
         for key in ("rho_r", "rho_R", "pop", "D"):
             worst[key] = max(worst.get(key, 0.0), rel_max(g[key], o[key]))
         worst["norm"] = max(worst.get("norm", 0.0), abs(g["norm"] - o["norm"]))
-        worst["r"] = max(worst.get("r", 0.0), float(np.max(np.abs(g["r"] - o["r"]))))
-        worst["R"] = max(worst.get("R", 0.0), float(np.max(np.abs(g["R"] - o["R"]))))
+        for key in ("r", "R"):
+            scale = max(1.0, float(np.max(np.abs(o[key]))))
+            worst[key] = max(worst.get(key, 0.0), float(np.max(np.abs(g[key] - o[key]))) / scale)
     print("[worst]", {k: f"{v:.2e}" for k, v in worst.items()}, flush=True)
     return worst
 
@@ -59,6 +67,8 @@ def test_fp64_matches_oracle(c1):
     w = _compare(gpu, ref)
     for key in ("rho_r", "rho_R", "pop", "D", "norm"):
         assert w[key] < 1e-10, key
+    for key in ("r", "R"):
+        assert w[key] < 1e-9, key
     assert gpu[-1]["n_out_of_box"] == ref[-1]["n_out_of_box"]
 
 
@@ -71,13 +81,15 @@ def test_fp64_with_explicit_inverses_matches_oracle(c1):
     w = _compare(gpu, ref)
     for key in ("rho_r", "rho_R", "pop", "D", "norm"):
         assert w[key] < 1e-10, key
+    for key in ("r", "R"):
+        assert w[key] < 1e-9, key
 
 
 def test_mixed_with_explicit_inverses_within_1e5(c1):
     wl, ref = c1
     gpu = _gpu_history(wl, icwf.PREC_MIXED, icwf.SOLVER_INVERSE)
     w = _compare(gpu, ref)
-    for key in ("rho_r", "rho_R", "pop", "D", "norm"):
+    for key in ("rho_r", "rho_R", "pop", "D", "norm", "r", "R"):
         assert w[key] < 1e-5, key
 
 
@@ -85,7 +97,7 @@ def test_mixed_within_1e5(c1):
     wl, ref = c1
     gpu = _gpu_history(wl, icwf.PREC_MIXED)
     w = _compare(gpu, ref)
-    for key in ("rho_r", "rho_R", "pop", "D", "norm"):
+    for key in ("rho_r", "rho_R", "pop", "D", "norm", "r", "R"):
         assert w[key] < 1e-5, key
 
 
@@ -101,3 +113,29 @@ def test_separable_matches_oracle(c1):
     w = _compare(gpu, ref)
     for key in ("rho_r", "rho_R", "pop", "D", "norm"):
         assert w[key] < 1e-10, key
+    for key in ("r", "R"):
+        assert w[key] < 1e-9, key
+
+
+def test_fp64_heun_trajectories_match_the_oracle():
+    """The parity workload with Heun trajectories (predictor-corrector) against
+    the oracle's Heun integrator over 200 steps: observables at the FP64 bar
+    of 1e-10; positions within 3e-7 of max |x|.  With this integrator one
+    trajectory of the ensemble (index 56, near r = -8) is far more sensitive:
+    the oracle run against itself with the upper instead of the lower
+    Cholesky factor already moves it by 2.7e-8 of max |r| at step 150 (every
+    other trajectory and all observables stay at the 1e-11 level), and the
+    bar is ten times that."""
+    wl = inputs.preset("sm_n64")
+    setup = setup_for(wl)
+    setup.trajectories = "heun"
+    print(f"[case] shin_metiu N={wl.n_traj} {wl.n_r}x{wl.n_R} Heun trajectories, oracle run of {STEPS} steps",
+          flush=True)
+    _, ref = oicwf.run(setup, init_for(setup, wl), STEPS, EVERY, wl.bo)
+    gpu = _gpu_history(wl, icwf.PREC_FP64, trajectories=icwf.TRAJ_HEUN)
+    w = _compare(gpu, ref)
+    for key in ("rho_r", "rho_R", "pop", "D", "norm"):
+        assert w[key] < 1e-10, key
+    for key in ("r", "R"):
+        assert w[key] < 3e-7, key
+    assert gpu[-1]["n_out_of_box"] == ref[-1]["n_out_of_box"]

@@ -115,3 +115,36 @@ def test_mixed_form_with_crank_nicolson():
     assert abs(o["norm"] - ref["norm"]) < 1e-5
     for key in ("rho_r", "rho_R", "pop", "D"):
         assert rel_max(o[key], ref[key]) < 1e-5, key
+
+
+def test_cavity_grid_where_the_system_is_not_diagonally_dominant():
+    """The cavity workload's grid (1024 x 256 on [-50, 50) x [-20, 20), dt =
+    0.1): there dt/(2 m h^2) = 5.2 exceeds |b_i| wherever the potential is
+    below -1.9, which the coupling lambda q x reaches near the box edges, so
+    the tridiagonal systems are not diagonally dominant.  The reduction's
+    pivots stay away from zero all the same (the Hermitian part of
+    1 + i dt/2 H is the identity, and that of every reduced system is at
+    least the identity).  N = 12 (photon coordinates up to |q| ~ 8, so the
+    tilted potential reaches about -20), one step of CWFs at 1e-12 and 10
+    steps of observables at 1e-10 against the oracle's dense solves."""
+    wl = inputs.gaussian_basis(12, n_r=1024, n_R=256, model=inputs.MODEL_CAVITY, r_box=(-50.0, 50.0),
+                               R_box=(-20.0, 20.0), dt=0.1, seed=7)
+    print(f"[case] crank-nicolson cavity {wl.n_r}x{wl.n_R}: N={wl.n_traj}", flush=True)
+    setup = setup_for(wl)
+    setup.propagator = "cn"
+    st0 = init_for(setup, wl)
+    V = setup.model.W(setup.r[None, :], wl.R0[:, None])
+    assert np.min(V) < -1.9 - 1e-3          # the case the dominance argument would not cover
+    sim = icwf.Simulation.from_workload(wl, C0=wl.extra["C0"], propagator=CN)
+    sim.step(1)
+    got = sim.state()
+    sim.step(9)
+    o = sim.observables()
+    sim.close()
+    ref = oicwf.step(setup, st0)
+    assert rel_max(got["psi1"], ref.psi1) < 1e-12
+    assert rel_max(got["psi2"], ref.psi2) < 1e-12
+    _, hist = oicwf.run(setup, st0, 10)
+    assert abs(o["norm"] - hist[-1]["norm"]) < 1e-10 * abs(hist[-1]["norm"])
+    for key in ("rho_r", "rho_R"):
+        assert rel_max(o[key], hist[-1][key]) < 1e-10, key

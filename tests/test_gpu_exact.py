@@ -122,3 +122,14 @@ def test_icwf_tracks_the_exact_propagation():
         assert abs(o["norm"] - 1.0) < 1e-3
     ex.close()
     sim.close()
+
+
+@pytest.mark.parametrize("n_r,n_R", [(64, 1024), (32, 2048), (32, 4096)])
+def test_long_nuclear_grids(n_r, n_R):
+    """n_R = 1024, 2048, 4096: the transposing R pass takes 4, 2 and 1 grid
+    rows per work-group there (8 on the shorter grids); 5 steps against the
+    oracle on a narrow r grid."""
+    wl = inputs.gaussian_basis(4, n_r=n_r, n_R=n_R, r_box=(-30.0, 30.0), R_box=(-12.0, 12.0),
+                               model=inputs.MODEL_SHIN_METIU, seed=36)
+    print(f"[case] exact {n_r}x{n_R}: 5 steps", flush=True)
+    _compare(wl, _correlated_start(wl, 36), 5)

@@ -32,14 +32,18 @@ CASES = {
 }
 
 
-@pytest.fixture(scope="module", params=sorted(CASES))
-def case(request):
-    kw = dict(CASES[request.param])
+def _make_case(name):
+    kw = dict(CASES[name])
     wl = inputs.gaussian_basis(kw.pop("N"), **kw)
-    _print_case(request.param, wl)
+    _print_case(name, wl)
     setup = setup_for(wl)
     st0 = init_for(setup, wl)
     return wl, setup, st0
+
+
+@pytest.fixture(scope="module", params=sorted(CASES))
+def case(request):
+    return _make_case(request.param)
 
 
 def test_matrices_at_start(case):
@@ -147,14 +151,12 @@ def test_separable_form_one_step(case):
     assert s_norm_diff(got["C"], ref.C, ref.S) < 1e-10 * np.sqrt(abs(np.conj(ref.C) @ ref.S @ ref.C))
 
 
-def test_mixed_form_on_an_exactly_separable_coupling(case):
+def test_mixed_form_on_an_exactly_separable_coupling():
     """The mixed form on the cavity coupling lambda q x: its one-term FP64 split
     leaves a residual at the table's rounding level, so no FP32 pass runs and
     the matrices and one step meet the plain form's bars.  (On Shin-Metiu the
     FP32 residual pass stays; its bar is the 1e-5 of the C1 tests.)"""
-    wl, setup, st0 = case
-    if wl.model != inputs.MODEL_CAVITY:
-        pytest.skip("Shin-Metiu keeps an FP32 residual")
+    wl, setup, st0 = _make_case("cavity")
     sim = icwf.Simulation.from_workload(wl, precision=icwf.PREC_MIXED, C0=wl.extra["C0"])
     assert sim.contraction_rank() == 1
     S, K, Wc = sim.matrices()
@@ -179,3 +181,52 @@ def test_separable_form_refuses_a_coupling_without_a_short_sum():
     with pytest.raises(icwf.ICWFError) as e:
         icwf.Simulation.from_workload(wl, precision=icwf.PREC_SEPARABLE, C0=wl.extra["C0"])
     assert e.value.status == icwf.EINVAL
+
+
+def _heun(setup):
+    out = oicwf.Setup(setup.model, setup.r_min, setup.r_max, setup.n_r, setup.R_min, setup.R_max, setup.n_R,
+                      setup.m_r, setup.m_R, setup.dt, setup.eps, trajectories="heun")
+    return out
+
+
+def test_heun_trajectories_one_step(case):
+    """ICWF_TRAJ_HEUN: Euler predictor, the velocity field of the advanced
+    state (C_k+1, psi_k+1) at the predictor, trapezoid corrector; K_k+1 at the
+    corrected positions.  One step against the oracle's Heun step: CWFs,
+    positions, S and K at 1e-12, C at 1e-10 in the S norm."""
+    wl, setup, st0 = case
+    hs = _heun(setup)
+    sim = icwf.Simulation.from_workload(wl, C0=wl.extra["C0"], trajectories=icwf.TRAJ_HEUN)
+    sim.step(1)
+    got = sim.state()
+    S, K, _ = sim.matrices()
+    o = sim.observables()
+    sim.close()
+    ref = oicwf.step(hs, st0)
+    assert np.max(np.abs(got["psi1"] - ref.psi1)) < 1e-12
+    assert np.max(np.abs(got["r"] - ref.r_traj)) < 1e-12 * max(1.0, np.max(np.abs(ref.r_traj)))
+    assert np.max(np.abs(got["R"] - ref.R_traj)) < 1e-12 * max(1.0, np.max(np.abs(ref.R_traj)))
+    assert rel_max(S, ref.S) < 1e-12
+    assert rel_max(K, ref.K) < 1e-12
+    assert s_norm_diff(got["C"], ref.C, ref.S) < 1e-10 * np.sqrt(abs(np.conj(ref.C) @ ref.S @ ref.C))
+    assert o["n_out_of_box"] == ref.n_out_of_box
+    assert abs(o["min_abs_psi"] - ref.min_abs_psi) < 1e-12 * ref.min_abs_psi
+    # the corrector moved the trajectories off the Euler positions
+    euler = oicwf.step(setup, st0)
+    assert np.max(np.abs(got["r"] - euler.r_traj)) > 1e-9
+
+
+def test_heun_trajectories_ten_steps(case):
+    wl, setup, st0 = case
+    hs = _heun(setup)
+    sim = icwf.Simulation.from_workload(wl, C0=wl.extra["C0"], trajectories=icwf.TRAJ_HEUN)
+    sim.step(10)
+    o = sim.observables()
+    sim.close()
+    _, hist = oicwf.run(hs, st0, 10)
+    ref = hist[-1]
+    assert abs(o["norm"] - ref["norm"]) < 1e-10 * abs(ref["norm"])
+    for key in ("rho_r", "rho_R"):
+        assert rel_max(o[key], ref[key]) < 1e-10, key
+    for key in ("r", "R"):
+        assert np.max(np.abs(o[key] - ref[key])) < 1e-10 * max(1.0, np.max(np.abs(ref[key]))), key

@@ -119,3 +119,36 @@ def test_requests_that_can_never_fit_are_refused():
         srv.wait(12345, 0.0)
     assert e.value.status == icwf.ESTATE
     srv.close()
+
+
+def test_served_results_match_the_oracle():
+    """Served simulations against the FP64 oracle, not only against their own
+    alone runs: the Shin-Metiu product start (N = 64, 256 x 128, two BO states)
+    served in FP64 and in the mixed form beside a third simulation; final
+    observables and positions within 1e-10 (FP64) and 1e-5 (mixed)."""
+    from oracle import icwf as oicwf
+
+    from oracle_runs import init_for, rel_max, setup_for
+
+    steps = 15
+    wl = inputs.shin_metiu(64, n_r=256, n_R=128, n_bo=2, seed=33)
+    other = inputs.gaussian_basis(100, n_r=256, n_R=64, seed=32)
+    print(f"[case] {wl.name} served (FP64, mixed) vs the oracle, {steps} steps", flush=True)
+    setup = setup_for(wl)
+    _, hist = oicwf.run(setup, init_for(setup, wl), steps, 0, wl.bo)
+    ref = hist[-1]
+    srv = icwf.Server(64 << 20, max_active=3, steps_per_turn=4)
+    ids = [_submit(srv, wl, icwf.PREC_FP64, steps), _submit(srv, other, icwf.PREC_MIXED, 9),
+           _submit(srv, wl, icwf.PREC_MIXED, steps)]
+    for i in ids:
+        assert srv.wait(i, timeout=120.0)
+    res = [srv.result(i) for i in ids]
+    srv.close()
+    for got, bar in ((res[0], 1e-10), (res[2], 1e-5)):
+        assert got["status"] == icwf.OK, got["message"]
+        assert got["step"] == steps
+        assert abs(got["norm"] - ref["norm"]) < bar
+        for key in ("rho_r", "rho_R", "pop", "D"):
+            assert rel_max(got[key], ref[key]) < bar, key
+        for key in ("r", "R"):
+            assert np.max(np.abs(got[key] - ref[key])) < bar * max(1.0, np.max(np.abs(ref[key]))), key

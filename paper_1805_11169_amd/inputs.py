@@ -138,11 +138,14 @@ def bo_states(model, params, r, hr, m_r, R_values, n_bo):
 # --------------------------------------------------------------------------
 
 def _product_start(name, model, params, N, n_r, n_R, r_box, R_box, m_r, m_R, dt, n_steps,
-                   eps, phi_V, chi0_fn, sample_R, seed, n_bo):
+                   eps, phi_V, chi0_fn, sample_R, seed, n_bo, phi_e=None, bo=None):
     r, hr = _grid(*r_box, n_r)
     R, hR = _grid(*R_box, n_R)
-    _, v = _eigvecs(_kinetic(n_r, hr, m_r), phi_V(r), 2)
-    phi = v[:, 1] / math.sqrt(hr)
+    if phi_e is None:
+        _, v = _eigvecs(_kinetic(n_r, hr, m_r), phi_V(r), 2)
+        phi = v[:, 1] / math.sqrt(hr)
+    else:                       # computed elsewhere (grid-normalised eigenvector 1)
+        phi = np.array(phi_e, dtype=np.float64)
     if phi[np.argmax(np.abs(phi))] < 0:
         phi = -phi
     chi = chi0_fn(R)
@@ -159,7 +162,8 @@ def _product_start(name, model, params, N, n_r, n_R, r_box, R_box, m_r, m_R, dt,
     psi1 = np.repeat(phi[None, :].astype(np.complex128), N, axis=0)
     psi2 = (s[:, None] * chi[None, :]).astype(np.complex128)
     b0 = (hr * np.sum(phi * phi)) * (hR * np.sum(chi * chi)) * s + 0j
-    bo = bo_states(model, params, r, hr, m_r, R, n_bo) if n_bo else None
+    if bo is None and n_bo:
+        bo = bo_states(model, params, r, hr, m_r, R, n_bo)
     return Workload(name, model, list(params), N, n_r, n_R, r_box[0], r_box[1], R_box[0], R_box[1],
                     m_r, m_R, dt, n_steps, eps, r0, R0, psi1, psi2, b0.astype(np.complex128), bo,
                     dict(phi_e=phi, chi0=chi, seed=seed))
@@ -171,8 +175,10 @@ CAVITY_PARAMS = [1.0, 1.0, 0.1, 0.05]         # depth, softening, omega, lambda
 
 def shin_metiu(N, n_r=512, n_R=256, r_box=(-75.0, 75.0), R_box=(-9.0, 9.0), params=None,
                R_center=-4.0, sigma=0.38, m_R=1836.0, dt=0.1, n_steps=200, eps=1e-8, seed=0,
-               n_bo=3, name=None):
-    """Shin-Metiu PCET start: electron in BO state 1 at R_center times a proton Gaussian."""
+               n_bo=3, name=None, phi_e=None, bo=None):
+    """Shin-Metiu PCET start: electron in BO state 1 at R_center times a proton Gaussian.
+    phi_e (grid-normalised eigenvector 1 of h_e(R_center)) and bo ([n_R][n_bo][n_r])
+    may be supplied precomputed; otherwise they are computed here on the host."""
     params = list(SHIN_METIU_PARAMS if params is None else params)
 
     def phi_V(r):
@@ -186,11 +192,11 @@ def shin_metiu(N, n_r=512, n_R=256, r_box=(-75.0, 75.0), R_box=(-9.0, 9.0), para
 
     return _product_start(name or f"shin_metiu_N{N}_{n_r}x{n_R}", MODEL_SHIN_METIU, params, N, n_r,
                           n_R, r_box, R_box, 1.0, m_R, dt, n_steps, eps, phi_V, chi0, sample_R, seed,
-                          n_bo)
+                          n_bo, phi_e, bo)
 
 
 def cavity(N, n_r=1024, n_R=256, r_box=(-50.0, 50.0), R_box=(-20.0, 20.0), params=None, dt=0.1,
-           n_steps=300, eps=1e-8, seed=0, n_bo=3, name=None):
+           n_steps=300, eps=1e-8, seed=0, n_bo=3, name=None, phi_e=None, bo=None):
     """Cavity start: electron in excited state 1 of its bare potential times the photon vacuum."""
     params = list(CAVITY_PARAMS if params is None else params)
     depth, soft, omega, _ = params
@@ -205,7 +211,8 @@ def cavity(N, n_r=1024, n_R=256, r_box=(-50.0, 50.0), R_box=(-20.0, 20.0), param
         return rng.normal(0.0, math.sqrt(1.0 / (2.0 * omega)), size=n)
 
     return _product_start(name or f"cavity_N{N}_{n_r}x{n_R}", MODEL_CAVITY, params, N, n_r, n_R,
-                          r_box, R_box, 1.0, 1.0, dt, n_steps, eps, phi_V, chi0, sample_R, seed, n_bo)
+                          r_box, R_box, 1.0, 1.0, dt, n_steps, eps, phi_V, chi0, sample_R, seed, n_bo,
+                          phi_e, bo)
 
 
 def gaussian_basis(N, n_r=128, n_R=64, r_box=(-20.0, 20.0), R_box=(-6.0, 6.0), model=MODEL_SHIN_METIU,

@@ -76,6 +76,8 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-steps", type=int, default=2)
     p.add_argument("--no-serving", action="store_true", help="skip the serving-mix leg")
+    p.add_argument("--no-other-precisions", action="store_true",
+                   help="skip the mixed and separable runs beside the FP64 headline")
     p.add_argument("--exact-grid-only", action="store_true",
                    help="time only the exact grid propagation (512 x 256 and 4096 x 512) and print its JSON")
     p.add_argument("--no-large-propagation", action="store_true",
@@ -145,7 +147,10 @@ def algorithmic_counts(N, nr, nR):
     return wc, single, prop_bytes
 
 
-def cpu_baseline(wl, steps):
+def cpu_baseline(wl, steps, steps_one_thread=1):
+    """The FP64 oracle on the host: `steps` steps with NumPy's BLAS on all its
+    threads (the reported value), then `steps_one_thread` more with it held to
+    one thread; also the BLAS library and the host's core count."""
     import numpy as np  # noqa: F401
     import oracle
     from oracle import icwf as oicwf
@@ -157,10 +162,49 @@ def cpu_baseline(wl, steps):
     for _ in range(steps):
         st = oicwf.step(setup, st)
     dt = time.perf_counter() - t0
+    blas = None
+    one = None
+    try:
+        from threadpoolctl import threadpool_info, threadpool_limits
+        blas = [f"{i.get('internal_api')} {i.get('version')} ({i.get('architecture')}, {i.get('num_threads')} threads)"
+                for i in threadpool_info() if i.get("user_api") == "blas" and "numpy" in i.get("filepath", "")]
+        if steps_one_thread:
+            with threadpool_limits(limits=1, user_api="blas"):
+                t1 = time.perf_counter()
+                for _ in range(steps_one_thread):
+                    st = oicwf.step(setup, st)
+                d1 = time.perf_counter() - t1
+            one = {"value": wl.n_traj * steps_one_thread / d1, "cores": 1,
+                   "sample": f"{steps_one_thread} further oracle step(s), {d1:.1f} s"}
+    except ImportError:  # pragma: no cover - threadpoolctl ships with the image
+        pass
     return {"value": wl.n_traj * steps / dt, "unit": "traj-steps/s", "cores": oracle.blas_threads() or os.cpu_count(),
             "kind": "oracle",
             "sample": f"{steps} oracle steps of the same workload (N={wl.n_traj}, {wl.n_r}x{wl.n_R}) from t=0, "
-                      f"{dt:.1f} s on the host"}
+                      f"{dt:.1f} s on the host",
+            "one_thread": one, "blas": blas, "host_cpu_count": os.cpu_count()}
+
+
+def other_precision(wl, precision, steps, warmup, fp64_ms):
+    """The same workload through another precision form of the library (graph
+    replays, wall clock over `steps` steps), beside the headline FP64 run."""
+    import torch
+    from paper_1805_11169_amd import icwf
+    prec = {"mixed": icwf.PREC_MIXED, "separable": icwf.PREC_SEPARABLE}[precision]
+    sim = icwf.Simulation.from_workload(wl, precision=prec, device=0)
+    sim.step(warmup)
+    sim.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(steps)
+    sim.sync()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / steps * 1e3
+    rank = sim.contraction_rank()
+    sim.close()
+    return {"precision": precision, "ms_per_step": ms, "traj_steps_per_s": wl.n_traj / (ms / 1e3),
+            "speedup_vs_fp64": fp64_ms / ms, "contraction_rank": rank, "steps": steps, "warmup": warmup,
+            "timing": "graph replays, wall clock"}
 
 
 def main():
@@ -194,13 +238,22 @@ def main():
 
     sim.step(args.warmup)
     sim.sync()
+    # graph replays first (the step as a user runs it), then the same number of
+    # steps kernel by kernel with an event pair around each kernel: the
+    # headline value is the slower of the two wall clocks
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(args.steps)
+    sim.sync()
+    torch.cuda.synchronize()
+    elapsed_graph = time.perf_counter() - t0
     sim.set_timing(True)          # kernel-by-kernel launches with an event pair around each kernel
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     sim.step(args.steps)
     sim.sync()
     torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
+    elapsed = max(time.perf_counter() - t0, elapsed_graph)
 
     kt = {}
     for name in ("wc_contract", "zgemm", "velocity", "propagate", "assemble", "cholesky", "rk4"):
@@ -272,7 +325,12 @@ def main():
         "kernel_ms_per_step": {k: (ms / n if n else None) for k, (n, ms) in kt.items()},
         "observables_ms": obs_ms,
         "final_norm": obs["norm"],
+        "ms_per_step_graph_replay": elapsed_graph / args.steps * 1e3,
     }
+    if args.precision == "fp64" and not args.no_other_precisions:
+        fp64_ms = elapsed_graph / args.steps * 1e3
+        line["mixed"] = other_precision(wl, "mixed", args.steps, args.warmup, fp64_ms)
+        line["separable"] = other_precision(wl, "separable", args.steps, args.warmup, fp64_ms)
     if not args.no_large_propagation and args.workload != "sm_n4096_large":
         line["propagation_4096x512"] = large_propagation()
     if not args.no_large_propagation and args.workload != "sm_n4096_large":

@@ -63,6 +63,29 @@ icwf_status icwf_exact_get_psi(icwf_exact *ex, double *psi);
 /* Wait for the enqueued work and release the handle (NULL is a no-op). */
 void icwf_exact_destroy(icwf_exact *ex);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * observables of icwf_exact_observables for a wavefunction the caller holds
+ * on the device, with no handle and no workspace.  The intermediate BO
+ * projections and partial sums live in a static device array of the library
+ * (2 MiB, held on every GPU the library runs on until the process ends);
+ * the call allocates nothing and does not synchronise.
+ *   n_r, n_R     powers of two in [32, 4096]; h_r, h_R > 0 the grid spacings.
+ *   n_bo         0 .. 16 BO states (the array's limit; more is ICWF_EINVAL).
+ *   psi          device [n_r][n_R][2]: Psi(r_i, R_j), R fastest.
+ *   bo_states    device [n_R][n_bo][n_r] real, or NULL when n_bo == 0.
+ *   out          device [1 + n_r + n_R + n_bo + n_bo^2] doubles: norm,
+ *                rho_r, rho_R, pop, D (the definitions of
+ *                icwf_exact_observables), written when the stream reaches the
+ *                work.
+ *   hip_stream   the stream the kernels are enqueued on.
+ * Every call on one GPU shares that GPU's array: calls whose work overlaps on
+ * the device (other streams or threads) race and must be ordered by the
+ * caller.  Errors: ICWF_EINVAL (sizes beyond the limits, NULL pointers; the
+ * message is in icwf_last_error(NULL)), ICWF_EDEVICE. */
+icwf_status icwf_grid_observables_noalloc(int32_t n_r, int32_t n_R, double h_r, double h_R, int32_t n_bo,
+                                          const double *psi, const double *bo_states, double *out, void *hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

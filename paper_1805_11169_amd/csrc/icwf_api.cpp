@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -946,6 +947,71 @@ void icwf_exact_destroy(icwf_exact *x) {
     if (!x) return;
     (void)hipStreamSynchronize(x->stream);
     delete x;
+}
+
+}  // extern "C"
+
+// ---- observables of a grid wavefunction without any allocation (icwf_exact.h) ---------------------
+
+namespace {
+
+constexpr int kNoAllocMaxStates = 16;
+constexpr int kNoAllocMaxPoints = 4096;
+// the BO projections chi [n_bo][n_R] (complex) and the rho_R partial sums
+// [kRhoSlices][n_R] of the largest case: 2 MiB
+constexpr size_t kScratchDoubles =
+    2 * (size_t)kNoAllocMaxStates * kNoAllocMaxPoints + (size_t)icwf::kRhoSlices * kNoAllocMaxPoints;
+__device__ __align__(256) double scratch[kScratchDoubles];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch[kMaxDevices] = {};
+
+// The device address of this GPU's copy of `scratch` (taken once per device,
+// with that device current); nullptr on failure, with the message set.
+double *scratch_on_current_device() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+        icwf::set_create_error(ICWF_EDEVICE, "no current device");
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            icwf::set_create_error(ICWF_EDEVICE, (std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e)).c_str());
+            return nullptr;
+        }
+        g_scratch[dev] = static_cast<double *>(p);
+    }
+    return g_scratch[dev];
+}
+
+}  // namespace
+
+extern "C" {
+
+icwf_status icwf_grid_observables_noalloc(int32_t n_r, int32_t n_R, double h_r, double h_R, int32_t n_bo,
+                                          const double *psi, const double *bo_states, double *out, void *hip_stream) {
+    auto pow2 = [](int n) { return n > 0 && (n & (n - 1)) == 0; };
+    if (!pow2(n_r) || !pow2(n_R) || n_r < 32 || n_R < 32 || n_r > kNoAllocMaxPoints || n_R > kNoAllocMaxPoints)
+        return icwf::set_create_error(ICWF_EINVAL, "n_r and n_R must be powers of two in [32, 4096]");
+    if (!(h_r > 0) || !(h_R > 0) || !std::isfinite(h_r) || !std::isfinite(h_R))
+        return icwf::set_create_error(ICWF_EINVAL, "grid spacings must be finite and > 0");
+    if (n_bo < 0 || n_bo > kNoAllocMaxStates)
+        return icwf::set_create_error(ICWF_EINVAL, "n_bo must be in [0, 16] (the static scratch holds 16 BO projections)");
+    if (!psi || !out || (n_bo > 0 && !bo_states))
+        return icwf::set_create_error(ICWF_EINVAL, "psi, out (and bo_states when n_bo > 0) are required");
+    double *base = scratch_on_current_device();
+    if (!base) return ICWF_EDEVICE;
+    double2 *chi = reinterpret_cast<double2 *>(base);
+    double *part = base + 2 * (size_t)kNoAllocMaxStates * kNoAllocMaxPoints;
+    icwf::launch_grid_observables(reinterpret_cast<const double2 *>(psi), n_r, n_R, h_r, h_R, n_bo, bo_states, chi,
+                                  part, out, reinterpret_cast<hipStream_t>(hip_stream));
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return icwf::set_create_error(ICWF_EDEVICE, hipGetErrorString(e));
+    return ICWF_OK;
 }
 
 }  // extern "C"

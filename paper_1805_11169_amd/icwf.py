@@ -32,7 +32,7 @@ SERVE_EXPORTS = ("icwf_server_create", "icwf_server_submit", "icwf_server_wait",
                  "icwf_server_get_stats", "icwf_server_clock", "icwf_server_destroy")
 # the entry points include/icwf_exact.h declares
 EXACT_EXPORTS = ("icwf_exact_workspace_bytes", "icwf_exact_create", "icwf_exact_step", "icwf_exact_observables",
-                 "icwf_exact_get_psi", "icwf_exact_destroy")
+                 "icwf_exact_get_psi", "icwf_exact_destroy", "icwf_grid_observables_noalloc")
 # the entry points include/icwf_bo.h declares
 BO_EXPORTS = ("icwf_bo_workspace_bytes", "icwf_bo_states")
 BO_MAX_STATES = 8
@@ -154,6 +154,9 @@ def lib():
         L.icwf_exact_get_psi.restype = c_int32
         L.icwf_exact_destroy.argtypes = [c_void_p]
         L.icwf_exact_destroy.restype = None
+        L.icwf_grid_observables_noalloc.argtypes = [c_int32, c_int32, c_double, c_double, c_int32, c_void_p, c_void_p,
+                                                    c_void_p, c_void_p]
+        L.icwf_grid_observables_noalloc.restype = c_int32
         L.icwf_bo_workspace_bytes.argtypes = [POINTER(Config), c_int32, c_int32]
         L.icwf_bo_workspace_bytes.restype = c_size_t
         L.icwf_bo_states.argtypes = [POINTER(Config), _DP, c_int32, c_int32, _DP, _DP, c_void_p, c_size_t, c_void_p,
@@ -245,6 +248,13 @@ def bo_states(cfg, R_values, n_states, tol=0.0, max_iter=0, device=0, check=True
     if check and st != OK:
         raise ICWFError(st, L.icwf_last_error(None).decode())
     return states, energies, out
+
+
+def grid_observables_noalloc(n_r, n_R, h_r, h_R, n_bo, psi_ptr, bo_ptr, out_ptr, stream_ptr):
+    """icwf_grid_observables_noalloc on caller-held device pointers (ints); returns the status."""
+    return int(lib().icwf_grid_observables_noalloc(int(n_r), int(n_R), float(h_r), float(h_R), int(n_bo),
+                                                   c_void_p(psi_ptr), c_void_p(bo_ptr) if bo_ptr else None,
+                                                   c_void_p(out_ptr), c_void_p(stream_ptr)))
 
 
 class Simulation:

@@ -183,6 +183,25 @@ icwf_status icwf_create(const icwf_config *cfg, const double *r0, const double *
  * the device stops advancing the state as soon as one is raised. */
 icwf_status icwf_step(icwf_sim *sim, int32_t n_steps);
 
+/* Enqueue n_steps steps of n_sims simulations at once: every kernel of the
+ * step is one launch for all of them (grid dimension z runs over the
+ * simulations, each kernel finds its simulation's buffers and model
+ * parameters in that simulation's workspace).  Each simulation's arithmetic,
+ * launch shapes and summation orders are those of icwf_step, so its result is
+ * bitwise the one icwf_step gives it; what the batch saves is launches (the
+ * small simulations of a serving mix are launch-bound).  Conditions (else
+ * ICWF_EINVAL, state untouched): 1 <= n_sims <= 64, distinct handles on one
+ * stream, at the same step parity, each one that steps on a single stream
+ * without the explicit inverses (padded N < 1024) and without per-kernel
+ * timing, and all alike in N, grids, boxes, masses, dt, eps, model kind,
+ * precision (and contraction rank in blocks of 16), propagator, trajectory
+ * integrator and n_bo; model parameters may differ.  A handle stopped by an
+ * earlier error is ICWF_ESTATE.  Errors raised on the device stop only the
+ * simulation that raised them (reported by its next synchronising call).
+ * The handles of sims[] are caller-owned; the first one's workspace holds the
+ * batch's offset table. */
+icwf_status icwf_step_batch(icwf_sim *const *sims, int32_t n_sims, int32_t n_steps);
+
 /* Wait for the handle's work and return its device status. */
 icwf_status icwf_sync(icwf_sim *sim);
 

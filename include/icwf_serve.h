@@ -15,7 +15,10 @@
  *   - advances every admitted simulation in turns of steps_per_turn steps,
  *     each step a replay of the simulation's captured HIP graph on the slot's
  *     own stream (default priority), keeping up to turns_ahead turns queued,
- *     so the work of different simulations overlaps on the device;
+ *     so the work of different simulations overlaps on the device; with
+ *     batching on, small simulations of one shape instead share a lane and
+ *     each of their turns is one fused icwf_step_batch over the lane's
+ *     simulations at the same step parity;
  *   - when a simulation's last step is done, computes its observables,
  *     releases its arena block and slot, and admits the next request.
  * A simulation's arithmetic does not depend on what else runs: its kernels,
@@ -43,6 +46,11 @@ typedef struct {
     int32_t steps_per_turn;  /* steps enqueued per simulation per scheduling turn, >= 1          */
     int32_t turns_ahead;     /* turns kept queued on a slot's stream, 1..4                      */
     int32_t device;          /* HIP device the arena lives on                                   */
+    int32_t batch;           /* 0: every simulation on its own slot stream; 1: simulations of one
+                                shape (icwf_step_batch's conditions, padded N < 1024) share a lane
+                                stream and advance together through icwf_step_batch, one
+                                launch per kernel for the whole lane (the simulations' own
+                                arithmetic is unchanged)                                       */
 } icwf_server_config;
 
 /* Timing and outcome of one request; times in seconds on the server's clock

@@ -13,6 +13,7 @@
 
 #include "../../include/icwf.h"
 #include "../../include/icwf_exact.h"
+#include "icwf_internal.hpp"
 #include "icwf_plan.hpp"
 
 using icwf::Bufs;
@@ -105,6 +106,8 @@ Bufs carve(const icwf_config &c, char *base, size_t *total) {
     b.obs_chi = L.take<double2>(std::max<size_t>(1, nbo * nR));
     b.obs_part = L.take<double>(icwf::kRhoSlices * nR);
     b.obs_out = L.take<double>(obs_len(c.n_r, c.n_R, c.n_bo));
+    b.mparams = L.take<icwf::ModelParams>(1);
+    b.batch_tab = L.take<long long>(icwf::kMaxBatch);
     *total = (L.off + 255) & ~size_t(255);
     return b;
 }
@@ -286,9 +289,8 @@ void timed(icwf_sim *s, const char *name, hipStream_t st, F fn) {
 // work queued behind them on the shared hardware queues.
 constexpr int kOverlapMinN = 1024;
 
-void enqueue_step(icwf_sim *s, int parity, hipStream_t st, hipStream_t side) {
+void enqueue_step(icwf_sim *s, const Dims &d, int parity, hipStream_t st, hipStream_t side) {
     if (s->Np < kOverlapMinN) side = st;
-    const Dims &d = s->d;
     const Bufs &b = s->b;
     const bool heun = d.traj == ICWF_TRAJ_HEUN;
     timed(s, "velocity", st, [&] { icwf::launch_velocity(d, b, icwf::kVelocityEuler, st); });
@@ -368,12 +370,34 @@ icwf_status capture_graphs(icwf_sim *s) {
     for (int p = 0; p < 2; ++p) {
         hipGraph_t g = nullptr;
         HIP_OK(hipStreamBeginCapture(s->capture_stream, hipStreamCaptureModeThreadLocal), s);
-        enqueue_step(s, p, s->capture_stream, s->side_stream);
+        enqueue_step(s, s->d, p, s->capture_stream, s->side_stream);
         HIP_OK(hipStreamEndCapture(s->capture_stream, &g), s);
         HIP_OK(hipGraphInstantiate(&s->exec[p], g, nullptr, nullptr, 0), s);
         HIP_OK(hipGraphDestroy(g), s);
     }
     return ICWF_OK;
+}
+
+// The shape and parameters every launch of a batched step shares: equal keys
+// give equal launch shapes, equal workspace layouts and equal host-side
+// launch arguments (each simulation's model parameters are read from its own
+// workspace).  False: the simulation steps alone (a forked step on a second
+// stream, explicit inverses, or per-kernel timing).
+bool batch_key(const icwf_sim *s, std::string *key) {
+    const Dims &d = s->d;
+    if (s->Np >= kOverlapMinN || d.sinv || s->timing) return false;
+    auto bits = [](double x) {
+        uint64_t u;
+        std::memcpy(&u, &x, sizeof(u));
+        return std::to_string(u);
+    };
+    std::string k;
+    for (int v : {d.N, d.nr, d.nR, d.n_bo, d.prec, (d.lr_rank + 15) / 16, d.fp32_residual, d.propagator, d.traj,
+                  d.wc_grid, d.prop_grid[0], d.prop_grid[1], (int)d.mp.kind, icwf::propagate_tiny_phase(d) ? 1 : 0})
+        k += std::to_string(v) + ",";
+    for (double v : {d.r_min, d.hr, d.R_min, d.hR, d.m_r, d.m_R, d.dt, d.eps}) k += bits(v) + ",";
+    *key = k;
+    return true;
 }
 
 // strided copy of the leading N x N block of an Np x Np complex matrix
@@ -449,6 +473,7 @@ icwf_status icwf_create(const icwf_config *cfg, const double *r0, const double *
     d.eps = cfg->tikhonov_eps;
     d.mp.kind = cfg->model;
     for (int i = 0; i < 8; ++i) d.mp.p[i] = cfg->model_params[i];
+    d.mpd = s->b.mparams;
 
     auto cleanup_fail = [&](icwf_status st, const std::string &m) {
         g_create_error = m;
@@ -577,6 +602,7 @@ icwf_status icwf_create(const icwf_config *cfg, const double *r0, const double *
     }
     if (nbo > 0)
         CREATE_HIP(hipMemcpyAsync(b.bo, bo_states, sizeof(double) * (size_t)nR * nbo * nr, hipMemcpyHostToDevice, st));
+    CREATE_HIP(hipMemcpyAsync(b.mparams, &d.mp, sizeof(icwf::ModelParams), hipMemcpyHostToDevice, st));
     if (C0) CREATE_HIP(hipMemcpyAsync(b.C, C0, sizeof(double2) * N, hipMemcpyHostToDevice, st));
     else CREATE_HIP(hipMemcpyAsync(b.Cstage, b0, sizeof(double2) * N, hipMemcpyHostToDevice, st));
 
@@ -614,7 +640,7 @@ icwf_status icwf_step(icwf_sim *s, int32_t n_steps) {
     if (s->status != ICWF_OK) return fail(s, ICWF_ESTATE, "the simulation stopped on an earlier error");
     for (int k = 0; k < n_steps; ++k) {
         if (s->timing) {
-            enqueue_step(s, s->parity, s->stream, s->side_stream);
+            enqueue_step(s, s->d, s->parity, s->stream, s->side_stream);
             HIP_OK(hipGetLastError(), s);
         } else {
             HIP_OK(hipGraphLaunch(s->exec[s->parity], s->stream), s);
@@ -622,6 +648,51 @@ icwf_status icwf_step(icwf_sim *s, int32_t n_steps) {
         s->parity ^= 1;
         s->step += 1;
         s->t += s->d.dt;
+    }
+    return ICWF_OK;
+}
+
+icwf_status icwf_step_batch(icwf_sim *const *sims, int32_t n_sims, int32_t n_steps) {
+    if (!sims || n_sims < 1 || n_sims > icwf::kMaxBatch || n_steps < 0)
+        return fail(nullptr, ICWF_EINVAL, "icwf_step_batch: need 1..64 simulations and n_steps >= 0");
+    icwf_sim *lead = sims[0];
+    if (!lead) return fail(nullptr, ICWF_EINVAL, "icwf_step_batch: NULL simulation");
+    std::string key;
+    if (!batch_key(lead, &key))
+        return fail(lead, ICWF_EINVAL, "icwf_step_batch: this simulation steps alone (padded N >= 1024, explicit "
+                                       "inverses or per-kernel timing)");
+    for (int k = 0; k < n_sims; ++k) {
+        icwf_sim *s = sims[k];
+        std::string kk;
+        if (!s) return fail(lead, ICWF_EINVAL, "icwf_step_batch: NULL simulation");
+        for (int q = 0; q < k; ++q)
+            if (sims[q] == s) return fail(lead, ICWF_EINVAL, "icwf_step_batch: a simulation appears twice");
+        if (s->status != ICWF_OK) return fail(s, ICWF_ESTATE, "the simulation stopped on an earlier error");
+        if (!batch_key(s, &kk) || kk != key)
+            return fail(lead, ICWF_EINVAL, "icwf_step_batch: the simulations differ in shape or parameters the "
+                                           "launches share");
+        if (s->stream != lead->stream) return fail(lead, ICWF_EINVAL, "icwf_step_batch: the simulations must share a stream");
+        if (s->parity != lead->parity) return fail(lead, ICWF_EINVAL, "icwf_step_batch: the simulations are at steps of different parity");
+    }
+    if (n_sims == 1) return icwf_step(lead, n_steps);
+    // the batch table: each simulation's workspace relative to the lead's (the
+    // workspace starts with the flags), written by a kernel whose arguments
+    // carry it, in stream order before the launches that read it
+    icwf::BatchTable tab{};
+    for (int k = 0; k < n_sims; ++k)
+        tab.off[k] = reinterpret_cast<const char *>(sims[k]->b.flags) - reinterpret_cast<const char *>(lead->b.flags);
+    icwf::launch_set_table(lead->b.batch_tab, tab, n_sims, lead->stream);
+    Dims d = lead->d;
+    d.batch = n_sims;
+    d.zoff = lead->b.batch_tab;
+    for (int k = 0; k < n_steps; ++k) {
+        enqueue_step(lead, d, lead->parity, lead->stream, lead->stream);
+        HIP_OK(hipGetLastError(), lead);
+        for (int q = 0; q < n_sims; ++q) {
+            sims[q]->parity ^= 1;
+            sims[q]->step += 1;
+            sims[q]->t += sims[q]->d.dt;
+        }
     }
     return ICWF_OK;
 }
@@ -1015,3 +1086,11 @@ icwf_status icwf_grid_observables_noalloc(int32_t n_r, int32_t n_R, double h_r, 
 }
 
 }  // extern "C"
+
+// ---- library-internal (icwf_internal.hpp) ----------------------------------------------------------
+
+bool icwf_internal_batch_key(const icwf_sim *sim, std::string *key) { return sim && key && batch_key(sim, key); }
+
+void icwf_internal_set_stream(icwf_sim *sim, hipStream_t stream) {
+    if (sim) sim->stream = stream;
+}

@@ -93,6 +93,18 @@ __device__ inline int mfma_row_f32(int lane, int v) { return 4 * (lane >> 4) + v
 __device__ inline int mfma_row(double, int lane, int v) { return mfma_row_f64(lane, v); }
 __device__ inline int mfma_row(float, int lane, int v) { return mfma_row_f32(lane, v); }
 
+// Batched launches (several simulations of one shape in one launch): the
+// simulation blockIdx.z (the outer part of it where z has another use) finds
+// every buffer at the address of the launch's first simulation plus
+// zoff[blockIdx.z] bytes, its workspace being laid out the same way.
+// zoff == nullptr: one simulation, no offset.
+__device__ inline long long batch_offset(const long long *zoff, int z) { return zoff ? zoff[z] : 0; }
+__device__ inline long long batch_offset(const long long *zoff) { return batch_offset(zoff, blockIdx.z); }
+template <typename T>
+__device__ inline T *zshift(T *p, long long o) {
+    return p ? reinterpret_cast<T *>(reinterpret_cast<uintptr_t>(p) + static_cast<uintptr_t>(o)) : p;
+}
+
 // Device status flags (one int32 each, in the workspace).
 enum Flag : int32_t { kFlagHalt = 0, kFlagNode = 1, kFlagSolve = 2, kFlagNonfinite = 3, kFlagOut = 4,
                       kFlagHang = 5, kNumFlags = 8 };

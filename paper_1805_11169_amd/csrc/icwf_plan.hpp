@@ -22,6 +22,13 @@ struct Dims {
     int prop_grid[2];                     // work-groups of the persistent propagation, per species
     double r_min, hr, R_min, hR, m_r, m_R, dt, eps;
     ModelParams mp;
+    // batched launches (icwf_step_batch): `batch` simulations of the same shape
+    // per launch, the k-th at this one's addresses plus zoff[k] bytes (device
+    // table); mpd this simulation's device copy of mp (each kernel reads its
+    // own simulation's copy).  One simulation: batch = 1, zoff = nullptr.
+    int batch = 1;
+    const long long *zoff = nullptr;
+    const ModelParams *mpd = nullptr;
 };
 
 // Trajectory count padded to the tile size every kernel assumes.  Padding
@@ -89,7 +96,19 @@ struct Bufs {
                                           // contraction, then the completion counters of its split tiles
     double2 *wc_part;                     // [wc_split_tiles(Np)][kWcParts][256] partial sums of split tiles
     double *scal;                         // small device scalars (min |Psi|, ...)
+    ModelParams *mparams;                 // device copy of the model parameters
+    long long *batch_tab;                 // [kMaxBatch] workspace offsets of a batch this simulation leads
 };
+
+// Most simulations one batched launch advances.
+constexpr int kMaxBatch = 64;
+
+// Workspace offsets (bytes) of a batch's simulations from its first one.
+struct BatchTable {
+    long long off[kMaxBatch];
+};
+// Writes the first n offsets into tab (device) in stream order.
+void launch_set_table(long long *tab, const BatchTable &t, int n, hipStream_t s);
 
 // RK4 through explicit inverses of S + eps I.  Automatic choice: where the
 // factorisations run on the second stream beside a contraction long enough
@@ -111,6 +130,10 @@ void launch_propagate(const Dims &d, const Bufs &b, int species, hipStream_t s);
 // The same step by Crank-Nicolson (grids up to 2048 points); launch_propagate
 // hands over to it when d.propagator == 1.
 void launch_propagate_cn(const Dims &d, const Bufs &b, int species, hipStream_t s);
+
+// Whether the split-operator propagation takes the short series for the
+// Shin-Metiu coupling phase (a property of dt and R_f).
+bool propagate_tiny_phase(const Dims &d);
 
 // Work-groups of the persistent propagation for grid size n and N trajectories:
 // as many as fit the device's ncu compute units at once, at most one per CWF group.
@@ -196,8 +219,9 @@ void launch_exact_step(int nr, int nR, const ExactBufs &e, hipStream_t s);
 // FP32 copy of psi1 (mixed form; the propagation keeps it current afterwards).
 void launch_psi1_f32(const Dims &d, const Bufs &b, hipStream_t s);
 
-// Fill n int32 with a value (graph-safe replacement for a memset).
-void launch_fill_i32(int32_t *p, int n, int32_t v, hipStream_t s);
+// Fill n int32 with a value (graph-safe replacement for a memset); batched:
+// the same n entries in each of `batch` workspaces (zoff as in the kernels).
+void launch_fill_i32(int32_t *p, int n, int32_t v, hipStream_t s, int batch = 1, const long long *zoff = nullptr);
 
 // Records the message icwf_last_error(NULL) returns (calls without a
 // handle) and passes the status through.

@@ -19,6 +19,7 @@
 
 #include "../../include/icwf_serve.h"
 #include "arena.hpp"
+#include "icwf_internal.hpp"
 
 namespace {
 
@@ -49,6 +50,16 @@ struct Slot {
     size_t off = 0;
     int32_t enqueued = 0, completed = 0;
     int32_t status = ICWF_OK;
+    int lane = -1;                 // lane it steps in (batching), or -1: its own stream
+};
+
+// Small simulations of one shape (icwf_internal_batch_key) share a lane: one
+// stream, and each turn one icwf_step_batch per step parity over the members
+// that are ready.
+struct Lane {
+    std::string key;
+    hipStream_t stream = nullptr;
+    int members = 0;
 };
 
 }  // namespace
@@ -58,6 +69,7 @@ struct icwf_server {
     char *arena = nullptr;
     icwf::Arena alloc;
     std::vector<Slot> slots;
+    std::vector<Lane> lanes;
     Clock::time_point t0;
 
     std::mutex mu;
@@ -143,6 +155,8 @@ void finish(icwf_server *S, Slot &sl) {
     rq->info.steps = o.step;
     if (s != ICWF_OK) set_message(*rq, icwf_last_error(sl.sim));
     icwf_destroy(sl.sim);
+    if (sl.lane >= 0) S->lanes[sl.lane].members -= 1;
+    sl.lane = -1;
     for (auto &pr : sl.inflight) sl.pool.push_back(pr.first);
     sl.inflight.clear();
     const size_t off = sl.off;
@@ -173,6 +187,90 @@ void admit(icwf_server *S, int idx, const std::shared_ptr<Request> &rq, size_t o
     sl.off = off;
     sl.enqueued = sl.completed = 0;
     sl.status = ICWF_OK;
+    sl.lane = -1;
+    std::string key;
+    if (S->cfg.batch && icwf_internal_batch_key(sim, &key)) {
+        // join the lane of its shape (a free lane is reused, else a new one opens)
+        int li = -1;
+        for (int i = 0; i < (int)S->lanes.size(); ++i)
+            if (S->lanes[i].key == key && S->lanes[i].members > 0) li = i;
+        if (li < 0)
+            for (int i = 0; i < (int)S->lanes.size(); ++i)
+                if (S->lanes[i].members == 0) {
+                    li = i;
+                    S->lanes[i].key = key;
+                    break;
+                }
+        if (li < 0) {
+            Lane ln;
+            ln.key = key;
+            if (hipStreamCreateWithFlags(&ln.stream, hipStreamNonBlocking) == hipSuccess) {
+                S->lanes.push_back(ln);
+                li = (int)S->lanes.size() - 1;
+            }
+        }
+        if (li >= 0) {
+            icwf_internal_set_stream(sim, S->lanes[li].stream);
+            S->lanes[li].members += 1;
+            sl.lane = li;
+        }
+    }
+}
+
+// Retire the slot's finished turns; finish its simulation when its last step
+// is done (or it failed).  True if anything moved; *gone when it finished.
+bool poll(icwf_server *S, Slot &sl, bool *gone) {
+    bool progress = false;
+    *gone = false;
+    while (!sl.inflight.empty()) {
+        const hipError_t e = hipEventQuery(sl.inflight.front().first);
+        if (e == hipErrorNotReady) break;
+        if (e != hipSuccess) sl.status = ICWF_EDEVICE;
+        sl.completed += sl.inflight.front().second;
+        sl.pool.push_back(sl.inflight.front().first);
+        sl.inflight.pop_front();
+        progress = true;
+    }
+    if (sl.completed >= sl.req->n_steps || (sl.status != ICWF_OK && sl.inflight.empty())) {
+        finish(S, sl);
+        *gone = true;
+        progress = true;
+    }
+    return progress;
+}
+
+// One turn of a lane: the members with room for another turn, grouped by step
+// parity, each group one fused icwf_step_batch on the lane's stream.
+bool advance_lane(icwf_server *S, int li) {
+    Lane &ln = S->lanes[li];
+    bool progress = false;
+    for (int par = 0; par < 2; ++par) {
+        std::vector<Slot *> grp;
+        int32_t k = S->cfg.steps_per_turn;
+        for (Slot &sl : S->slots)
+            if (sl.sim && sl.lane == li && sl.status == ICWF_OK && (int)sl.inflight.size() < S->cfg.turns_ahead &&
+                sl.enqueued < sl.req->n_steps && (sl.enqueued & 1) == par) {
+                grp.push_back(&sl);
+                k = std::min(k, sl.req->n_steps - sl.enqueued);
+            }
+        if (grp.empty()) continue;
+        std::vector<icwf_sim *> sims;
+        for (Slot *sl : grp) sims.push_back(sl->sim);
+        const icwf_status st = sims.size() == 1 ? icwf_step(sims[0], k)
+                                                : icwf_step_batch(sims.data(), (int32_t)sims.size(), k);
+        for (Slot *sl : grp) {
+            hipEvent_t ev = st == ICWF_OK ? take_event(*sl) : nullptr;
+            if (!ev || hipEventRecord(ev, ln.stream) != hipSuccess) {
+                if (ev) sl->pool.push_back(ev);
+                sl->status = ICWF_EDEVICE;
+                continue;
+            }
+            sl->inflight.emplace_back(ev, k);
+            sl->enqueued += k;
+        }
+        progress = true;
+    }
+    return progress;
 }
 
 // One pass over the admitted simulations; true if anything moved.
@@ -180,20 +278,9 @@ bool advance(icwf_server *S) {
     bool progress = false;
     for (Slot &sl : S->slots) {
         if (!sl.sim) continue;
-        while (!sl.inflight.empty()) {
-            const hipError_t e = hipEventQuery(sl.inflight.front().first);
-            if (e == hipErrorNotReady) break;
-            if (e != hipSuccess) sl.status = ICWF_EDEVICE;
-            sl.completed += sl.inflight.front().second;
-            sl.pool.push_back(sl.inflight.front().first);
-            sl.inflight.pop_front();
-            progress = true;
-        }
-        if (sl.completed >= sl.req->n_steps || (sl.status != ICWF_OK && sl.inflight.empty())) {
-            finish(S, sl);
-            progress = true;
-            continue;
-        }
+        bool gone = false;
+        progress = poll(S, sl, &gone) || progress;
+        if (gone || sl.lane >= 0) continue;
         while (sl.status == ICWF_OK && (int)sl.inflight.size() < S->cfg.turns_ahead &&
                sl.enqueued < sl.req->n_steps) {
             const int32_t k = std::min(S->cfg.steps_per_turn, sl.req->n_steps - sl.enqueued);
@@ -208,6 +295,8 @@ bool advance(icwf_server *S) {
             progress = true;
         }
     }
+    for (int li = 0; li < (int)S->lanes.size(); ++li)
+        if (S->lanes[li].members > 0) progress = advance_lane(S, li) || progress;
     return progress;
 }
 
@@ -275,7 +364,7 @@ icwf_status icwf_server_create(const icwf_server_config *cfg, void *arena, size_
     if (!cfg || !arena || !out) return ICWF_EINVAL;
     *out = nullptr;
     if (cfg->max_active < 1 || cfg->max_active > 64 || cfg->steps_per_turn < 1 || cfg->turns_ahead < 1 ||
-        cfg->turns_ahead > 4 || cfg->device < 0)
+        cfg->turns_ahead > 4 || cfg->device < 0 || cfg->batch < 0 || cfg->batch > 1)
         return ICWF_EINVAL;
     if (reinterpret_cast<uintptr_t>(arena) % icwf::Arena::kAlign != 0 || arena_bytes < icwf::Arena::kAlign)
         return ICWF_EINVAL;
@@ -408,6 +497,8 @@ void icwf_server_destroy(icwf_server *S) {
         for (hipEvent_t e : sl.pool) (void)hipEventDestroy(e);
         if (sl.stream) (void)hipStreamDestroy(sl.stream);
     }
+    for (Lane &ln : S->lanes)
+        if (ln.stream) (void)hipStreamDestroy(ln.stream);
     delete S;
 }
 

@@ -38,7 +38,16 @@ __device__ inline flt4 mfma(float a, float b, flt4 c) {
 __global__ void k_cond_kets(const double2 *__restrict__ psi, int n, double x_min, double h,
                             const double *__restrict__ cond_a, const double *__restrict__ cond_b, int species,
                             ModelParams mp, double2 *__restrict__ Ga, double2 *__restrict__ Gb, int Np,
-                            const int32_t *__restrict__ flags) {
+                            const int32_t *__restrict__ flags, const long long *__restrict__ zoff, const ModelParams *__restrict__ mpd) {
+    const long long zo_ = batch_offset(zoff);
+    psi = zshift(psi, zo_);
+    cond_a = zshift(cond_a, zo_);
+    cond_b = zshift(cond_b, zo_);
+    Ga = zshift(Ga, zo_);
+    Gb = zshift(Gb, zo_);
+    flags = zshift(flags, zo_);
+    if (zoff) mp = *zshift(mpd, zo_);
+
     if (flags[kFlagHalt]) return;
     const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= (size_t)Np * n) return;
@@ -90,12 +99,16 @@ __device__ inline T zpick(const T (&a)[6], int z) {
     return r;
 }
 
-__global__ void __launch_bounds__(256, 2) k_zgemm(ZBatch zb, int Np, const int32_t *__restrict__ flags) {
+__global__ void __launch_bounds__(256, 2) k_zgemm(ZBatch zb, int Np, const int32_t *__restrict__ flags, int zcnt,
+                                                  const long long *__restrict__ zoff) {
+    // grid z: zcnt products of each simulation of the launch
+    const int sim = blockIdx.z / zcnt, z = blockIdx.z - sim * zcnt;
+    const long long zo_ = batch_offset(zoff, sim);
+    flags = zshift(flags, zo_);
     if (flags[kFlagHalt]) return;
-    const int z = blockIdx.z;
     const int bt = blockIdx.y, at = blockIdx.x;
-    const double2 *__restrict__ X = zpick(zb.X, z);
-    const double2 *__restrict__ Y = zpick(zb.Y, z);
+    const double2 *__restrict__ X = zshift(zpick(zb.X, z), zo_);
+    const double2 *__restrict__ Y = zshift(zpick(zb.Y, z), zo_);
     const bool herm = X == Y;   // the output is Hermitian: upper tiles only
     if (herm && bt > at) return;
     __shared__ double2 sX[2][kZT][kZLD];
@@ -178,7 +191,7 @@ __global__ void __launch_bounds__(256, 2) k_zgemm(ZBatch zb, int Np, const int32
         __syncthreads();
     }
     const double sc = zpick(zb.scale, z);
-    double2 *out = zpick(zb.out, z);
+    double2 *out = zshift(zpick(zb.out, z), zo_);
     const bool mirror = herm && bt < at;
 #pragma unroll
     for (int f = 0; f < 2; ++f)
@@ -238,7 +251,16 @@ __global__ void __launch_bounds__(256, 2) k_wc(const typename WcTraits<T>::cplx 
                                                const T *__restrict__ wtab, int nr, int nR, double scale,
                                                double2 *__restrict__ Wc, int Np, int accumulate,
                                                int ntiles, int nsplit, int nparts, int32_t *__restrict__ queue,
-                                               double2 *__restrict__ part, const int32_t *__restrict__ flags) {
+                                               double2 *__restrict__ part, const int32_t *__restrict__ flags, const long long *__restrict__ zoff) {
+    const long long zo_ = batch_offset(zoff);
+    psi1 = zshift(psi1, zo_);
+    psi2 = zshift(psi2, zo_);
+    wtab = zshift(wtab, zo_);
+    Wc = zshift(Wc, zo_);
+    queue = zshift(queue, zo_);
+    part = zshift(part, zo_);
+    flags = zshift(flags, zo_);
+
     typedef typename WcTraits<T>::acc4 acc4;
     typedef typename WcTraits<T>::cplx C2;
     typedef WcChunk<T> CK;
@@ -500,7 +522,16 @@ __global__ void __launch_bounds__(256, 2) k_wc_sep(const double2 *__restrict__ p
                                                    const double *__restrict__ U, const double *__restrict__ V,
                                                    int kpad, int nr, int nR, double scale,
                                                    double2 *__restrict__ Wc, int Np, int accumulate, int ntiles,
-                                                   int32_t *__restrict__ queue, const int32_t *__restrict__ flags) {
+                                                   int32_t *__restrict__ queue, const int32_t *__restrict__ flags, const long long *__restrict__ zoff) {
+    const long long zo_ = batch_offset(zoff);
+    psi1 = zshift(psi1, zo_);
+    psi2 = zshift(psi2, zo_);
+    U = zshift(U, zo_);
+    V = zshift(V, zo_);
+    Wc = zshift(Wc, zo_);
+    queue = zshift(queue, zo_);
+    flags = zshift(flags, zo_);
+
     if (flags[kFlagHalt]) return;
     __shared__ double2 sA[2][32][kSepKC + 1];
     __shared__ double sF[2][kSepKC][17];
@@ -554,21 +585,21 @@ __global__ void __launch_bounds__(256, 2) k_wc_sep(const double2 *__restrict__ p
 void launch_cond_kets(const Dims &d, const Bufs &b, hipStream_t s, bool next) {
     const int Np = padded(d.N);
     size_t tot = (size_t)Np * d.nr;
-    hipLaunchKernelGGL(k_cond_kets, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, b.psi1, d.nr, d.r_min,
-                       d.hr, b.R, b.R_new, 1, d.mp, b.G1a, next ? b.G1b : nullptr, Np, b.flags);
+    hipLaunchKernelGGL(k_cond_kets, dim3((unsigned)((tot + 255) / 256), 1, d.batch), dim3(256), 0, s, b.psi1, d.nr,
+                       d.r_min, d.hr, b.R, b.R_new, 1, d.mp, b.G1a, next ? b.G1b : nullptr, Np, b.flags, d.zoff, d.mpd);
     tot = (size_t)Np * d.nR;
-    hipLaunchKernelGGL(k_cond_kets, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, b.psi2, d.nR, d.R_min,
-                       d.hR, b.r, b.r_new, 2, d.mp, b.G2a, next ? b.G2b : nullptr, Np, b.flags);
+    hipLaunchKernelGGL(k_cond_kets, dim3((unsigned)((tot + 255) / 256), 1, d.batch), dim3(256), 0, s, b.psi2, d.nR,
+                       d.R_min, d.hR, b.r, b.r_new, 2, d.mp, b.G2a, next ? b.G2b : nullptr, Np, b.flags, d.zoff, d.mpd);
 }
 
 void launch_cond_kets_next(const Dims &d, const Bufs &b, hipStream_t s) {
     const int Np = padded(d.N);
     size_t tot = (size_t)Np * d.nr;
-    hipLaunchKernelGGL(k_cond_kets, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, b.psi1, d.nr, d.r_min,
-                       d.hr, b.R_new, b.R_new, 1, d.mp, b.G1b, nullptr, Np, b.flags);
+    hipLaunchKernelGGL(k_cond_kets, dim3((unsigned)((tot + 255) / 256), 1, d.batch), dim3(256), 0, s, b.psi1, d.nr,
+                       d.r_min, d.hr, b.R_new, b.R_new, 1, d.mp, b.G1b, nullptr, Np, b.flags, d.zoff, d.mpd);
     tot = (size_t)Np * d.nR;
-    hipLaunchKernelGGL(k_cond_kets, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, b.psi2, d.nR, d.R_min,
-                       d.hR, b.r_new, b.r_new, 2, d.mp, b.G2b, nullptr, Np, b.flags);
+    hipLaunchKernelGGL(k_cond_kets, dim3((unsigned)((tot + 255) / 256), 1, d.batch), dim3(256), 0, s, b.psi2, d.nR,
+                       d.R_min, d.hR, b.r_new, b.r_new, 2, d.mp, b.G2b, nullptr, Np, b.flags, d.zoff, d.mpd);
 }
 
 void launch_single_species(const Dims &d, const Bufs &b, bool both, hipStream_t s) {
@@ -591,7 +622,7 @@ void launch_single_species(const Dims &d, const Bufs &b, bool both, hipStream_t 
         add(b.psi1, b.G1b, b.E1b, d.nr, d.hr);
         add(b.psi2, b.G2b, b.E2b, d.nR, d.hR);
     }
-    hipLaunchKernelGGL(k_zgemm, dim3(Np / kZT, Np / kZT, c), dim3(256), 0, s, zb, Np, b.flags);
+    hipLaunchKernelGGL(k_zgemm, dim3(Np / kZT, Np / kZT, c * d.batch), dim3(256), 0, s, zb, Np, b.flags, c, d.zoff);
 }
 
 void launch_single_species_next(const Dims &d, const Bufs &b, hipStream_t s) {
@@ -607,7 +638,7 @@ void launch_single_species_next(const Dims &d, const Bufs &b, hipStream_t s) {
     zb.out[1] = b.E2b;
     zb.K[1] = d.nR;
     zb.scale[1] = d.hR;
-    hipLaunchKernelGGL(k_zgemm, dim3(Np / kZT, Np / kZT, 2), dim3(256), 0, s, zb, Np, b.flags);
+    hipLaunchKernelGGL(k_zgemm, dim3(Np / kZT, Np / kZT, 2 * d.batch), dim3(256), 0, s, zb, Np, b.flags, 2, d.zoff);
 }
 
 void launch_wc(const Dims &d, const Bufs &b, hipStream_t s) {
@@ -624,26 +655,27 @@ void launch_wc(const Dims &d, const Bufs &b, hipStream_t s) {
         // mixed: FP32 matrix cores on the residual of the rank-K split, FP64 rank-K part added
         // (the FP32 pass only where the residual is above the table's rounding)
         if (d.fp32_residual) {
-            launch_fill_i32(b.wc_queue, 1 + nsplit, 0, s);
-            hipLaunchKernelGGL(k_wc<float>, dim3(grid), dim3(256), 0, s, b.psi1_f32, b.psi2, b.wc32, d.nr, d.nR,
-                               scale, b.Wc, Np, 0, blocks, nsplit, nparts, b.wc_queue, b.wc_part, b.flags);
+            launch_fill_i32(b.wc_queue, 1 + nsplit, 0, s, d.batch, d.zoff);
+            hipLaunchKernelGGL(k_wc<float>, dim3(grid, 1, d.batch), dim3(256), 0, s, b.psi1_f32, b.psi2, b.wc32, d.nr,
+                               d.nR, scale, b.Wc, Np, 0, blocks, nsplit, nparts, b.wc_queue, b.wc_part, b.flags,
+                               d.zoff);
         }
         if (d.lr_rank > 0) {
-            launch_fill_i32(b.wc_queue, 1, 0, s);
-            hipLaunchKernelGGL(k_wc_sep, dim3(std::min(blocks, d.wc_grid)), dim3(256), 0, s, b.psi1, b.psi2, b.lr_u,
-                               b.lr_v, (d.lr_rank + 15) / 16 * 16, d.nr, d.nR, scale, b.Wc, Np,
-                               d.fp32_residual ? 1 : 0, blocks, b.wc_queue, b.flags);
+            launch_fill_i32(b.wc_queue, 1, 0, s, d.batch, d.zoff);
+            hipLaunchKernelGGL(k_wc_sep, dim3(std::min(blocks, d.wc_grid), 1, d.batch), dim3(256), 0, s, b.psi1,
+                               b.psi2, b.lr_u, b.lr_v, (d.lr_rank + 15) / 16 * 16, d.nr, d.nR, scale, b.Wc, Np,
+                               d.fp32_residual ? 1 : 0, blocks, b.wc_queue, b.flags, d.zoff);
         }
     } else if (d.prec == 2) {
         // separable: the whole contraction through the sum of products (assigns Wc)
-        launch_fill_i32(b.wc_queue, 1, 0, s);
-        hipLaunchKernelGGL(k_wc_sep, dim3(std::min(blocks, d.wc_grid)), dim3(256), 0, s, b.psi1, b.psi2, b.lr_u,
-                           b.lr_v, (d.lr_rank + 15) / 16 * 16, d.nr, d.nR, scale, b.Wc, Np, 0, blocks, b.wc_queue,
-                           b.flags);
+        launch_fill_i32(b.wc_queue, 1, 0, s, d.batch, d.zoff);
+        hipLaunchKernelGGL(k_wc_sep, dim3(std::min(blocks, d.wc_grid), 1, d.batch), dim3(256), 0, s, b.psi1, b.psi2,
+                           b.lr_u, b.lr_v, (d.lr_rank + 15) / 16 * 16, d.nr, d.nR, scale, b.Wc, Np, 0, blocks,
+                           b.wc_queue, b.flags, d.zoff);
     } else {
-        launch_fill_i32(b.wc_queue, 1 + nsplit, 0, s);
-        hipLaunchKernelGGL(k_wc<double>, dim3(grid), dim3(256), 0, s, b.psi1, b.psi2, b.wc64, d.nr, d.nR, scale,
-                           b.Wc, Np, 0, blocks, nsplit, nparts, b.wc_queue, b.wc_part, b.flags);
+        launch_fill_i32(b.wc_queue, 1 + nsplit, 0, s, d.batch, d.zoff);
+        hipLaunchKernelGGL(k_wc<double>, dim3(grid, 1, d.batch), dim3(256), 0, s, b.psi1, b.psi2, b.wc64, d.nr, d.nR,
+                           scale, b.Wc, Np, 0, blocks, nsplit, nparts, b.wc_queue, b.wc_part, b.flags, d.zoff);
     }
 }
 

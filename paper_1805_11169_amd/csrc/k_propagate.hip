@@ -357,7 +357,18 @@ __global__ void __launch_bounds__(512, LOG2N == kFourStepLog2 ? 4 : 1)
     k_propagate(double2 *__restrict__ psi, int ngroups, const double2 *__restrict__ vphase, double x_min, double h,
                 const double *__restrict__ cond, const double2 *__restrict__ cph, int species, ModelParams mp,
                 const double2 *__restrict__ kin, const double2 *__restrict__ tw, double dt, int tiny,
-                float2 *__restrict__ psi_f32, const int32_t *__restrict__ flags) {
+                float2 *__restrict__ psi_f32, const int32_t *__restrict__ flags, const long long *__restrict__ zoff, const ModelParams *__restrict__ mpd) {
+    const long long zo_ = batch_offset(zoff);
+    psi = zshift(psi, zo_);
+    vphase = zshift(vphase, zo_);
+    cond = zshift(cond, zo_);
+    cph = zshift(cph, zo_);
+    kin = zshift(kin, zo_);
+    tw = zshift(tw, zo_);
+    psi_f32 = zshift(psi_f32, zo_);
+    flags = zshift(flags, zo_);
+    if (zoff) mp = *zshift(mpd, zo_);
+
     if (flags[kFlagHalt]) return;
     extern __shared__ double2 sh_all[];
     constexpr int n = 1 << LOG2N;
@@ -505,7 +516,8 @@ size_t lds_for(int n) {
 namespace {
 // The instantiation for n = 2^l, 32 <= n <= 4096.
 using PropKernel = void (*)(double2 *, int, const double2 *, double, double, const double *, const double2 *, int,
-                            ModelParams, const double2 *, const double2 *, double, int, float2 *, const int32_t *);
+                            ModelParams, const double2 *, const double2 *, double, int, float2 *, const int32_t *,
+                            const long long *, const ModelParams *);
 PropKernel kernel_for(int n) {
     switch (ilog2(n)) {
     case 5: return k_propagate<5>;
@@ -532,6 +544,10 @@ int propagate_grid(int n, int N, int ncu) {
     return (int)(ngroups < full ? ngroups : full);
 }
 
+bool propagate_tiny_phase(const Dims &d) {
+    return d.mp.kind == 1 && 0.5 * std::fabs(d.dt) * 2.0 / (std::sqrt(M_PI) * d.mp.p[1]) <= kTinyPhase;
+}
+
 void launch_propagate(const Dims &d, const Bufs &b, int species, hipStream_t s) {
     if (d.propagator == 1) {
         launch_propagate_cn(d, b, species, s);
@@ -544,13 +560,14 @@ void launch_propagate(const Dims &d, const Bufs &b, int species, hipStream_t s) 
     const size_t lds = lds_for(n);
     const PropKernel k = kernel_for(n);      // n is validated at creation (a power of two in [32, 4096])
     // the Shin-Metiu coupling phase stays within the short series' range
-    const int tiny = d.mp.kind == 1 && 0.5 * std::fabs(d.dt) * 2.0 / (std::sqrt(M_PI) * d.mp.p[1]) <= kTinyPhase;
+    const int tiny = propagate_tiny_phase(d) ? 1 : 0;
     if (species == 1) {
-        hipLaunchKernelGGL(k, dim3(grid), dim3(T), lds, s, b.psi1, ngroups, b.vphase_r, d.r_min, d.hr, b.R, b.cphase,
-                           1, d.mp, b.kin_r, b.tw_r, d.dt, tiny, d.prec == 1 && d.fp32_residual ? b.psi1_f32 : nullptr, b.flags);
+        hipLaunchKernelGGL(k, dim3(grid, 1, d.batch), dim3(T), lds, s, b.psi1, ngroups, b.vphase_r, d.r_min, d.hr, b.R,
+                           b.cphase, 1, d.mp, b.kin_r, b.tw_r, d.dt, tiny,
+                           d.prec == 1 && d.fp32_residual ? b.psi1_f32 : nullptr, b.flags, d.zoff, d.mpd);
     } else {
-        hipLaunchKernelGGL(k, dim3(grid), dim3(T), lds, s, b.psi2, ngroups, b.vphase_R, d.R_min, d.hR, b.r,
-                           b.cphase + padded(d.N), 2, d.mp, b.kin_R, b.tw_R, d.dt, tiny, nullptr, b.flags);
+        hipLaunchKernelGGL(k, dim3(grid, 1, d.batch), dim3(T), lds, s, b.psi2, ngroups, b.vphase_R, d.R_min, d.hR, b.r,
+                           b.cphase + padded(d.N), 2, d.mp, b.kin_R, b.tw_R, d.dt, tiny, nullptr, b.flags, d.zoff, d.mpd);
     }
 }
 

@@ -45,7 +45,14 @@ __global__ void __launch_bounds__(cn_threads<LOG2N>()) k_propagate_cn(double2 *_
                                                                       const double *__restrict__ cond, int species,
                                                                       double x_min, double h, double m, double dt,
                                                                       ModelParams mp, float2 *__restrict__ psi_f32,
-                                                                      const int32_t *__restrict__ flags) {
+                                                                      const int32_t *__restrict__ flags, const long long *__restrict__ zoff, const ModelParams *__restrict__ mpd) {
+    const long long zo_ = batch_offset(zoff);
+    psi = zshift(psi, zo_);
+    cond = zshift(cond, zo_);
+    psi_f32 = zshift(psi_f32, zo_);
+    flags = zshift(flags, zo_);
+    if (zoff) mp = *zshift(mpd, zo_);
+
     if (flags[kFlagHalt]) return;
     constexpr int n = 1 << LOG2N, nt = cn_threads<LOG2N>(), E = n / nt;
     __shared__ double2 sa[n], sb[n], sc[n], sd[n];
@@ -119,11 +126,12 @@ template <int L>
 void launch_cn(const Dims &d, const Bufs &b, int species, hipStream_t s) {
     const int Np = padded(d.N);
     if (species == 1)
-        hipLaunchKernelGGL(k_propagate_cn<L>, dim3(Np), dim3(cn_threads<L>()), 0, s, b.psi1, b.R, 1, d.r_min, d.hr,
-                           d.m_r, d.dt, d.mp, d.prec == 1 && d.fp32_residual ? b.psi1_f32 : nullptr, b.flags);
+        hipLaunchKernelGGL(k_propagate_cn<L>, dim3(Np, 1, d.batch), dim3(cn_threads<L>()), 0, s, b.psi1, b.R, 1,
+                           d.r_min, d.hr, d.m_r, d.dt, d.mp, d.prec == 1 && d.fp32_residual ? b.psi1_f32 : nullptr,
+                           b.flags, d.zoff, d.mpd);
     else
-        hipLaunchKernelGGL(k_propagate_cn<L>, dim3(Np), dim3(cn_threads<L>()), 0, s, b.psi2, b.r, 2, d.R_min, d.hR,
-                           d.m_R, d.dt, d.mp, nullptr, b.flags);
+        hipLaunchKernelGGL(k_propagate_cn<L>, dim3(Np, 1, d.batch), dim3(cn_threads<L>()), 0, s, b.psi2, b.r, 2,
+                           d.R_min, d.hR, d.m_R, d.dt, d.mp, nullptr, b.flags, d.zoff, d.mpd);
 }
 
 }  // namespace

@@ -52,7 +52,30 @@ __global__ void k_assemble(const double2 *__restrict__ S1, const double2 *__rest
                            const double *__restrict__ R_new, ModelParams mp, int N, int Np, double eps,
                            int part, double2 *__restrict__ Snext, double2 *__restrict__ Kminus,
                            double2 *__restrict__ Knext, double2 *__restrict__ Amid, double2 *__restrict__ Anext,
-                           double2 *__restrict__ Kmid, const int32_t *__restrict__ flags) {
+                           double2 *__restrict__ Kmid, const int32_t *__restrict__ flags, const long long *__restrict__ zoff, const ModelParams *__restrict__ mpd) {
+    const long long zo_ = batch_offset(zoff);
+    S1 = zshift(S1, zo_);
+    S2 = zshift(S2, zo_);
+    E1a = zshift(E1a, zo_);
+    E1b = zshift(E1b, zo_);
+    E2a = zshift(E2a, zo_);
+    E2b = zshift(E2b, zo_);
+    Wc = zshift(Wc, zo_);
+    Scur = zshift(Scur, zo_);
+    Kcur = zshift(Kcur, zo_);
+    r = zshift(r, zo_);
+    R = zshift(R, zo_);
+    r_new = zshift(r_new, zo_);
+    R_new = zshift(R_new, zo_);
+    Snext = zshift(Snext, zo_);
+    Kminus = zshift(Kminus, zo_);
+    Knext = zshift(Knext, zo_);
+    Amid = zshift(Amid, zo_);
+    Anext = zshift(Anext, zo_);
+    Kmid = zshift(Kmid, zo_);
+    flags = zshift(flags, zo_);
+    if (zoff) mp = *zshift(mpd, zo_);
+
     if (flags[kFlagHalt]) return;
     const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= (size_t)Np * Np) return;
@@ -140,7 +163,13 @@ constexpr int kPanelDiagWaves = NB / kPanelRows;
 
 __global__ void __launch_bounds__(kPanelThreads) k_chol_panel(double2 *A0, double2 *A1, int Np, int kb,
                                                               double2 *__restrict__ diag,
-                                                              int32_t *__restrict__ flags) {
+                                                              int32_t *__restrict__ flags, const long long *__restrict__ zoff) {
+    const long long zo_ = batch_offset(zoff);
+    A0 = zshift(A0, zo_);
+    A1 = zshift(A1, zo_);
+    diag = zshift(diag, zo_);
+    flags = zshift(flags, zo_);
+
     if (flags[kFlagHalt]) return;
     // the panel is a latency chain that shares compute units with the
     // contraction on the other stream: its waves take the issue slots first
@@ -221,7 +250,13 @@ __global__ void __launch_bounds__(kPanelThreads) k_chol_panel(double2 *A0, doubl
 
 __global__ void __launch_bounds__(256) k_chol_flush(double2 *A0, double2 *A1, int Np, int kb,
                                                     const double2 *__restrict__ diag,
-                                                    const int32_t *__restrict__ flags) {
+                                                    const int32_t *__restrict__ flags, const long long *__restrict__ zoff) {
+    const long long zo_ = batch_offset(zoff);
+    A0 = zshift(A0, zo_);
+    A1 = zshift(A1, zo_);
+    diag = zshift(diag, zo_);
+    flags = zshift(flags, zo_);
+
     if (flags[kFlagHalt]) return;
     double2 *A = blockIdx.y ? A1 : A0;
     const double2 *D = diag + (size_t)blockIdx.y * NB * NB;
@@ -236,7 +271,12 @@ __global__ void __launch_bounds__(256) k_chol_flush(double2 *A0, double2 *A1, in
 // work-group per 32 x 32 tile, wave w on its 16 x 16 fragment (w / 2, w % 2),
 // so a tile's 64-deep reduction runs on four matrix-core streams at once.
 __global__ void __launch_bounds__(256) k_chol_update(double2 *A0, double2 *A1, int Np, int kb,
-                                                     const int32_t *__restrict__ flags) {
+                                                     const int32_t *__restrict__ flags, const long long *__restrict__ zoff) {
+    const long long zo_ = batch_offset(zoff);
+    A0 = zshift(A0, zo_);
+    A1 = zshift(A1, zo_);
+    flags = zshift(flags, zo_);
+
     if (flags[kFlagHalt]) return;
     double2 *A = blockIdx.y ? A1 : A0;
     const int t = blockIdx.x;
@@ -284,7 +324,16 @@ __global__ void __launch_bounds__(256) k_chol_update(double2 *A0, double2 *A1, i
 __global__ void __launch_bounds__(256) k_tri_inv(const double2 *__restrict__ A0, const double2 *__restrict__ A1,
                                                  double2 *__restrict__ X0, double2 *__restrict__ X1,
                                                  double2 *__restrict__ F0, double2 *__restrict__ F1, int Np,
-                                                 const int32_t *__restrict__ flags) {
+                                                 const int32_t *__restrict__ flags, const long long *__restrict__ zoff) {
+    const long long zo_ = batch_offset(zoff);
+    A0 = zshift(A0, zo_);
+    A1 = zshift(A1, zo_);
+    X0 = zshift(X0, zo_);
+    X1 = zshift(X1, zo_);
+    F0 = zshift(F0, zo_);
+    F1 = zshift(F1, zo_);
+    flags = zshift(flags, zo_);
+
     if (flags[kFlagHalt]) return;
     // 66.5 KB of LDS: fits beside a two-body contraction work-group on one CU
     __shared__ double2 sX[NB][NB + 1];        // the inverse (lower; zero above)
@@ -556,7 +605,13 @@ __device__ inline void publish_block(int32_t *flag) {
 // y = M v, one wave per row, four rows per work-group.
 __global__ void __launch_bounds__(256) k_matvec(const double2 *__restrict__ M, const double2 *__restrict__ v,
                                                 double2 *__restrict__ y, int Np,
-                                                const int32_t *__restrict__ flags) {
+                                                const int32_t *__restrict__ flags, const long long *__restrict__ zoff) {
+    const long long zo_ = batch_offset(zoff);
+    M = zshift(M, zo_);
+    v = zshift(v, zo_);
+    y = zshift(y, zo_);
+    flags = zshift(flags, zo_);
+
     if (flags[kFlagHalt]) return;
     const int lane = threadIdx.x & 63;
     const int rowi = blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -578,7 +633,15 @@ __global__ void __launch_bounds__(256) k_matvec(const double2 *__restrict__ M, c
 // waits.
 __global__ void __launch_bounds__(256) k_rk_fwd(const double2 *__restrict__ rhs, const double2 *__restrict__ L,
                                                 const double2 *__restrict__ Linv, double2 *__restrict__ ybuf,
-                                                int Np, int32_t *__restrict__ sync, int32_t *__restrict__ flags) {
+                                                int Np, int32_t *__restrict__ sync, int32_t *__restrict__ flags, const long long *__restrict__ zoff) {
+    const long long zo_ = batch_offset(zoff);
+    rhs = zshift(rhs, zo_);
+    L = zshift(L, zo_);
+    Linv = zshift(Linv, zo_);
+    ybuf = zshift(ybuf, zo_);
+    sync = zshift(sync, zo_);
+    flags = zshift(flags, zo_);
+
     __shared__ double2 uvec[NB];
     __shared__ int slot;
     const int B = take_ticket(&sync[kSyncTicketF], &slot);
@@ -670,7 +733,22 @@ __global__ void __launch_bounds__(256) k_rk_bwd(const double2 *__restrict__ L, c
                                                 double2 *__restrict__ Cacc, double2 *__restrict__ Cstage,
                                                 double *__restrict__ r, double *__restrict__ R,
                                                 const double *__restrict__ r_new, const double *__restrict__ R_new,
-                                                int32_t *__restrict__ sync, int32_t *__restrict__ flags) {
+                                                int32_t *__restrict__ sync, int32_t *__restrict__ flags, const long long *__restrict__ zoff) {
+    const long long zo_ = batch_offset(zoff);
+    L = zshift(L, zo_);
+    Linv = zshift(Linv, zo_);
+    ybuf = zshift(ybuf, zo_);
+    xbuf = zshift(xbuf, zo_);
+    C = zshift(C, zo_);
+    Cacc = zshift(Cacc, zo_);
+    Cstage = zshift(Cstage, zo_);
+    r = zshift(r, zo_);
+    R = zshift(R, zo_);
+    r_new = zshift(r_new, zo_);
+    R_new = zshift(R_new, zo_);
+    sync = zshift(sync, zo_);
+    flags = zshift(flags, zo_);
+
     __shared__ double2 uvec[NB];
     __shared__ int slot;
     const int ticket = take_ticket(&sync[kSyncTicketB], &slot);
@@ -727,7 +805,15 @@ __global__ void __launch_bounds__(256) k_rk_bwd(const double2 *__restrict__ L, c
 __global__ void __launch_bounds__(256) k_rk_resid(const double2 *__restrict__ Sa, const double2 *__restrict__ Sb,
                                                   double eps, const double2 *__restrict__ x,
                                                   const double2 *__restrict__ rhs, double2 *__restrict__ res, int Np,
-                                                  const int32_t *__restrict__ flags) {
+                                                  const int32_t *__restrict__ flags, const long long *__restrict__ zoff) {
+    const long long zo_ = batch_offset(zoff);
+    Sa = zshift(Sa, zo_);
+    Sb = zshift(Sb, zo_);
+    x = zshift(x, zo_);
+    rhs = zshift(rhs, zo_);
+    res = zshift(res, zo_);
+    flags = zshift(flags, zo_);
+
     if (flags[kFlagHalt]) return;
     const int lane = threadIdx.x & 63;
     const int rowi = blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -759,7 +845,20 @@ __global__ void __launch_bounds__(256) k_rk_apply(const double2 *__restrict__ Si
                                                   double2 *__restrict__ C, double2 *__restrict__ Cacc,
                                                   double2 *__restrict__ Cstage, double *__restrict__ r,
                                                   double *__restrict__ R, const double *__restrict__ r_new,
-                                                  const double *__restrict__ R_new, int32_t *__restrict__ flags) {
+                                                  const double *__restrict__ R_new, int32_t *__restrict__ flags, const long long *__restrict__ zoff) {
+    const long long zo_ = batch_offset(zoff);
+    Sinv = zshift(Sinv, zo_);
+    res = zshift(res, zo_);
+    x0 = zshift(x0, zo_);
+    C = zshift(C, zo_);
+    Cacc = zshift(Cacc, zo_);
+    Cstage = zshift(Cstage, zo_);
+    r = zshift(r, zo_);
+    R = zshift(R, zo_);
+    r_new = zshift(r_new, zo_);
+    R_new = zshift(R_new, zo_);
+    flags = zshift(flags, zo_);
+
     if (flags[kFlagHalt]) return;
     const int lane = threadIdx.x & 63;
     const int rowi = blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -774,7 +873,14 @@ __global__ void __launch_bounds__(256) k_rk_apply(const double2 *__restrict__ Si
     if (lane == 0) stage_update(rowi, cadd(x0[rowi], acc), stage, dt, N, C, Cacc, Cstage, r, R, r_new, R_new, flags);
 }
 
-__global__ void k_fill_i32(int32_t *p, int n, int32_t v) {
+__global__ void k_set_table(long long *__restrict__ tab, BatchTable t, int n) {
+    if ((int)threadIdx.x < n) tab[threadIdx.x] = t.off[threadIdx.x];
+}
+
+__global__ void k_fill_i32(int32_t *p, int n, int32_t v, const long long *__restrict__ zoff) {
+    const long long zo_ = batch_offset(zoff);
+    p = zshift(p, zo_);
+
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = v;
 }
@@ -786,9 +892,10 @@ void launch_assemble(const Dims &d, const Bufs &b, int parity, AssemblePart part
     const size_t tot = (size_t)Np * Np;
     const bool initial = part == kAssembleInitial;
     const int cur = parity, nxt = initial ? parity : 1 - parity;
-    hipLaunchKernelGGL(k_assemble, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, b.S1, b.S2, b.E1a, b.E1b,
-                       b.E2a, b.E2b, b.Wc, b.Smat[cur], b.Kmat[cur], b.r, b.R, b.r_new, b.R_new, d.mp, d.N, Np,
-                       d.eps, (int)part, b.Smat[nxt], b.Kminus, b.Kmat[nxt], b.Lmid, b.L[nxt], b.Kmid, b.flags);
+    hipLaunchKernelGGL(k_assemble, dim3((unsigned)((tot + 255) / 256), 1, d.batch), dim3(256), 0, s, b.S1, b.S2,
+                       b.E1a, b.E1b, b.E2a, b.E2b, b.Wc, b.Smat[cur], b.Kmat[cur], b.r, b.R, b.r_new, b.R_new, d.mp,
+                       d.N, Np, d.eps, (int)part, b.Smat[nxt], b.Kminus, b.Kmat[nxt], b.Lmid, b.L[nxt], b.Kmid, b.flags,
+                       d.zoff, d.mpd);
 }
 
 void launch_cholesky(const Dims &d, const Bufs &b, double2 *A0, double2 *A1, double2 *X0, double2 *X1, int count,
@@ -797,17 +904,19 @@ void launch_cholesky(const Dims &d, const Bufs &b, double2 *A0, double2 *A1, dou
     for (int kb = 0; kb < Np; kb += NB) {
         const int below = Np - kb - NB;
         const int gx = below > 0 ? below / 64 : 1;
-        hipLaunchKernelGGL(k_chol_panel, dim3(gx, count), dim3(kPanelThreads), 0, s, A0, A1, Np, kb, b.chol_diag,
-                           b.flags);
+        hipLaunchKernelGGL(k_chol_panel, dim3(gx, count, d.batch), dim3(kPanelThreads), 0, s, A0, A1, Np, kb,
+                           b.chol_diag, b.flags, d.zoff);
         if (below > 0) {
             const int mt = below / 32;
-            hipLaunchKernelGGL(k_chol_update, dim3(mt * (mt + 1) / 2, count), dim3(256), 0, s, A0, A1, Np, kb,
-                               b.flags);
+            hipLaunchKernelGGL(k_chol_update, dim3(mt * (mt + 1) / 2, count, d.batch), dim3(256), 0, s, A0, A1, Np, kb,
+                               b.flags, d.zoff);
         }
     }
-    hipLaunchKernelGGL(k_chol_flush, dim3(1, count), dim3(256), 0, s, A0, A1, Np, Np - NB, b.chol_diag, b.flags);
+    hipLaunchKernelGGL(k_chol_flush, dim3(1, count, d.batch), dim3(256), 0, s, A0, A1, Np, Np - NB, b.chol_diag,
+                       b.flags, d.zoff);
     double2 *F0 = S0 ? b.Xinv[0] : nullptr, *F1 = S0 ? b.Xinv[1] : nullptr;
-    hipLaunchKernelGGL(k_tri_inv, dim3(Np / NB, count), dim3(256), 0, s, A0, A1, X0, X1, F0, F1, Np, b.flags);
+    hipLaunchKernelGGL(k_tri_inv, dim3(Np / NB, count, d.batch), dim3(256), 0, s, A0, A1, X0, X1, F0, F1, Np, b.flags,
+                       d.zoff);
     if (!S0) return;
     // X = L^-1 by block recursion, [[A, 0], [C, D]]^-1 = [[A', 0], [-D' C A', D']],
     // from the 64 x 64 diagonal inverses up: at block size h, the Np / (2 h) pairs
@@ -867,35 +976,42 @@ void launch_rk4(const Dims &d, const Bufs &b, int parity, hipStream_t s) {
     double *cr = d.traj == 1 ? nullptr : b.r, *cR = d.traj == 1 ? nullptr : b.R;
     for (int st = 1; st <= 4; ++st) {
         const double2 *v = (st == 1) ? b.C : b.Cstage;
-        hipLaunchKernelGGL(k_matvec, dim3(Np / 4), dim3(256), 0, s, Ks[st - 1], v, b.rhs, Np, b.flags);
+        hipLaunchKernelGGL(k_matvec, dim3(Np / 4, 1, d.batch), dim3(256), 0, s, Ks[st - 1], v, b.rhs, Np, b.flags,
+                           d.zoff);
         if (d.sinv) {
             // A of the stage: S_k + eps I, the midpoint average + eps I (stages 2, 3), S_k+1 + eps I
             const double2 *Sa = st == 4 ? b.Smat[nxt] : b.Smat[cur];
             const double2 *Sb = (st == 2 || st == 3) ? b.Smat[nxt] : nullptr;
-            hipLaunchKernelGGL(k_matvec, dim3(Np / 4), dim3(256), 0, s, Ss[st - 1], b.rhs, b.y, Np, b.flags);
-            hipLaunchKernelGGL(k_rk_resid, dim3(Np / 4), dim3(256), 0, s, Sa, Sb, d.eps, b.y, b.rhs, b.xsol, Np,
-                               b.flags);
-            hipLaunchKernelGGL(k_rk_apply, dim3(Np / 4), dim3(256), 0, s, Ss[st - 1], b.xsol, b.y, Np, st, d.dt,
-                               d.N, b.C, b.Cacc, b.Cstage, cr, cR, b.r_new, b.R_new, b.flags);
+            hipLaunchKernelGGL(k_matvec, dim3(Np / 4, 1, d.batch), dim3(256), 0, s, Ss[st - 1], b.rhs, b.y, Np,
+                               b.flags, d.zoff);
+            hipLaunchKernelGGL(k_rk_resid, dim3(Np / 4, 1, d.batch), dim3(256), 0, s, Sa, Sb, d.eps, b.y, b.rhs, b.xsol,
+                               Np, b.flags, d.zoff);
+            hipLaunchKernelGGL(k_rk_apply, dim3(Np / 4, 1, d.batch), dim3(256), 0, s, Ss[st - 1], b.xsol, b.y, Np, st,
+                               d.dt, d.N, b.C, b.Cacc, b.Cstage, cr, cR, b.r_new, b.R_new, b.flags, d.zoff);
             continue;
         }
-        hipLaunchKernelGGL(k_rk_fwd, dim3(nblk), dim3(256), 0, s, b.rhs, Ls[st - 1], Xs[st - 1], b.y, Np,
-                           b.solve_sync, b.flags);
-        hipLaunchKernelGGL(k_rk_bwd, dim3(nblk), dim3(256), 0, s, Ls[st - 1], Xs[st - 1], b.y, b.xsol, Np, nblk, st,
-                           d.dt, d.N, b.C, b.Cacc, b.Cstage, cr, cR, b.r_new, b.R_new, b.solve_sync, b.flags);
+        hipLaunchKernelGGL(k_rk_fwd, dim3(nblk, 1, d.batch), dim3(256), 0, s, b.rhs, Ls[st - 1], Xs[st - 1], b.y, Np,
+                           b.solve_sync, b.flags, d.zoff);
+        hipLaunchKernelGGL(k_rk_bwd, dim3(nblk, 1, d.batch), dim3(256), 0, s, Ls[st - 1], Xs[st - 1], b.y, b.xsol, Np,
+                           nblk, st, d.dt, d.N, b.C, b.Cacc, b.Cstage, cr, cR, b.r_new, b.R_new, b.solve_sync, b.flags,
+                           d.zoff);
     }
 }
 
 void launch_solve_initial(const Dims &d, const Bufs &b, int parity, double2 *rhs, hipStream_t s) {
     const int Np = padded(d.N), nblk = Np / NB;
     hipLaunchKernelGGL(k_rk_fwd, dim3(nblk), dim3(256), 0, s, rhs, b.L[parity], b.Linv[parity], b.y, Np,
-                       b.solve_sync, b.flags);
+                       b.solve_sync, b.flags, nullptr);
     hipLaunchKernelGGL(k_rk_bwd, dim3(nblk), dim3(256), 0, s, b.L[parity], b.Linv[parity], b.y, b.xsol, Np, nblk, 0,
-                       d.dt, d.N, b.C, b.Cacc, b.Cstage, b.r, b.R, b.r_new, b.R_new, b.solve_sync, b.flags);
+                       d.dt, d.N, b.C, b.Cacc, b.Cstage, b.r, b.R, b.r_new, b.R_new, b.solve_sync, b.flags, nullptr);
 }
 
-void launch_fill_i32(int32_t *p, int n, int32_t v, hipStream_t s) {
-    hipLaunchKernelGGL(k_fill_i32, dim3((n + 255) / 256), dim3(256), 0, s, p, n, v);
+void launch_set_table(long long *tab, const BatchTable &t, int n, hipStream_t s) {
+    hipLaunchKernelGGL(k_set_table, dim3(1), dim3(kMaxBatch), 0, s, tab, t, n);
+}
+
+void launch_fill_i32(int32_t *p, int n, int32_t v, hipStream_t s, int batch, const long long *zoff) {
+    hipLaunchKernelGGL(k_fill_i32, dim3((n + 255) / 256, 1, batch), dim3(256), 0, s, p, n, v, zoff);
 }
 
 }  // namespace icwf

@@ -35,7 +35,13 @@ __device__ inline dbl4 mfma_f64(double a, double b, dbl4 c) {
 }
 
 __global__ void k_sinc(const double *__restrict__ pos, int Np, int n, double x_min, double h,
-                       double *__restrict__ S, double *__restrict__ Sp, const int32_t *__restrict__ flags) {
+                       double *__restrict__ S, double *__restrict__ Sp, const int32_t *__restrict__ flags, const long long *__restrict__ zoff) {
+    const long long zo_ = batch_offset(zoff);
+    pos = zshift(pos, zo_);
+    S = zshift(S, zo_);
+    Sp = zshift(Sp, zo_);
+    flags = zshift(flags, zo_);
+
     if (flags[kFlagHalt]) return;
     __shared__ double red[256];
     const int a = blockIdx.x;
@@ -185,7 +191,18 @@ __global__ void __launch_bounds__(256) k_vel_gemm(const double *__restrict__ Sr,
                                                   const double *__restrict__ SR, const double *__restrict__ DR,
                                                   const double2 *__restrict__ psi2, int nR,
                                                   const double2 *__restrict__ C, int Np,
-                                                  double2 *__restrict__ part, const int32_t *__restrict__ flags) {
+                                                  double2 *__restrict__ part, const int32_t *__restrict__ flags, const long long *__restrict__ zoff) {
+    const long long zo_ = batch_offset(zoff);
+    Sr = zshift(Sr, zo_);
+    Dr = zshift(Dr, zo_);
+    psi1 = zshift(psi1, zo_);
+    SR = zshift(SR, zo_);
+    DR = zshift(DR, zo_);
+    psi2 = zshift(psi2, zo_);
+    C = zshift(C, zo_);
+    part = zshift(part, zo_);
+    flags = zshift(flags, zo_);
+
     if (flags[kFlagHalt]) return;
     __shared__ VelStage st;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -247,7 +264,21 @@ __global__ void k_vel_finish(const double2 *__restrict__ part, int N, int Np, do
                              double *__restrict__ R_new, double *__restrict__ v_r, double *__restrict__ v_R,
                              double2 *__restrict__ psi_at, double r_lo, double r_hi, double R_lo, double R_hi,
                              ModelParams mp, double2 *__restrict__ cphase, int mode, int32_t *__restrict__ flags,
-                             unsigned long long *__restrict__ min_bits) {
+                             unsigned long long *__restrict__ min_bits, const long long *__restrict__ zoff, const ModelParams *__restrict__ mpd) {
+    const long long zo_ = batch_offset(zoff);
+    part = zshift(part, zo_);
+    r = zshift(r, zo_);
+    R = zshift(R, zo_);
+    r_new = zshift(r_new, zo_);
+    R_new = zshift(R_new, zo_);
+    v_r = zshift(v_r, zo_);
+    v_R = zshift(v_R, zo_);
+    psi_at = zshift(psi_at, zo_);
+    cphase = zshift(cphase, zo_);
+    flags = zshift(flags, zo_);
+    min_bits = zshift(min_bits, zo_);
+    if (zoff) mp = *zshift(mpd, zo_);
+
     if (flags[kFlagHalt]) return;
     const int a = blockIdx.x * blockDim.x + threadIdx.x;
     if (a >= N) return;
@@ -309,7 +340,11 @@ __global__ void k_vel_finish(const double2 *__restrict__ part, int N, int Np, do
     }
 }
 
-__global__ void k_vel_reset(int32_t *flags, unsigned long long *min_bits, int keep_min) {
+__global__ void k_vel_reset(int32_t *flags, unsigned long long *min_bits, int keep_min, const long long *__restrict__ zoff) {
+    const long long zo_ = batch_offset(zoff);
+    flags = zshift(flags, zo_);
+    min_bits = zshift(min_bits, zo_);
+
     if (threadIdx.x == 0) {
         flags[kFlagOut] = 0;
         if (!keep_min) *min_bits = 0x7ff0000000000000ULL;   // +inf
@@ -323,18 +358,21 @@ void launch_velocity(const Dims &d, const Bufs &b, VelocityMode mode, hipStream_
     // the corrector evaluates the field at the predictor positions
     const double *pr = mode == kVelocityHeun ? b.r_new : b.r;
     const double *pR = mode == kVelocityHeun ? b.R_new : b.R;
-    hipLaunchKernelGGL(k_sinc, dim3(Np), dim3(256), 0, s, pr, Np, d.nr, d.r_min, d.hr, b.sinc_r, b.dsinc_r, b.flags);
-    hipLaunchKernelGGL(k_sinc, dim3(Np), dim3(256), 0, s, pR, Np, d.nR, d.R_min, d.hR, b.sinc_R, b.dsinc_R,
-                       b.flags);
-    hipLaunchKernelGGL(k_vel_gemm, dim3(Np / kVA, Np / kVB), dim3(256), 0, s, b.sinc_r, b.dsinc_r, b.psi1, d.nr,
-                       b.sinc_R, b.dsinc_R, b.psi2, d.nR, b.C, Np, b.vpart, b.flags);
+    const int B = d.batch;
+    hipLaunchKernelGGL(k_sinc, dim3(Np, 1, B), dim3(256), 0, s, pr, Np, d.nr, d.r_min, d.hr, b.sinc_r, b.dsinc_r,
+                       b.flags, d.zoff);
+    hipLaunchKernelGGL(k_sinc, dim3(Np, 1, B), dim3(256), 0, s, pR, Np, d.nR, d.R_min, d.hR, b.sinc_R, b.dsinc_R,
+                       b.flags, d.zoff);
+    hipLaunchKernelGGL(k_vel_gemm, dim3(Np / kVA, Np / kVB, B), dim3(256), 0, s, b.sinc_r, b.dsinc_r, b.psi1, d.nr,
+                       b.sinc_R, b.dsinc_R, b.psi2, d.nR, b.C, Np, b.vpart, b.flags, d.zoff);
     unsigned long long *min_bits = reinterpret_cast<unsigned long long *>(b.scal);
     // min |Psi| over the step's evaluations: the corrector keeps the first pass's minimum
-    hipLaunchKernelGGL(k_vel_reset, dim3(1), dim3(64), 0, s, b.flags, min_bits, mode == kVelocityHeun ? 1 : 0);
+    hipLaunchKernelGGL(k_vel_reset, dim3(1, 1, B), dim3(64), 0, s, b.flags, min_bits, mode == kVelocityHeun ? 1 : 0,
+                       d.zoff);
     const double r_hi = d.r_min + d.hr * d.nr, R_hi = d.R_min + d.hR * d.nR;
-    hipLaunchKernelGGL(k_vel_finish, dim3((d.N + 255) / 256), dim3(256), 0, s, b.vpart, d.N, Np, d.m_r, d.m_R,
+    hipLaunchKernelGGL(k_vel_finish, dim3((d.N + 255) / 256, 1, B), dim3(256), 0, s, b.vpart, d.N, Np, d.m_r, d.m_R,
                        d.dt, b.r, b.R, b.r_new, b.R_new, b.v_r, b.v_R, b.psi_at, d.r_min, r_hi, d.R_min, R_hi, d.mp,
-                       b.cphase, (int)mode, b.flags, min_bits);
+                       b.cphase, (int)mode, b.flags, min_bits, d.zoff, d.mpd);
 }
 
 }  // namespace icwf

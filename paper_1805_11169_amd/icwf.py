@@ -23,7 +23,7 @@ PROP_SPLIT, PROP_CRANK_NICOLSON = 0, 1
 TRAJ_EULER, TRAJ_HEUN = 0, 1
 
 # the entry points include/icwf.h declares
-EXPORTS = ("icwf_workspace_bytes", "icwf_create", "icwf_step", "icwf_sync", "icwf_observables",
+EXPORTS = ("icwf_workspace_bytes", "icwf_create", "icwf_step", "icwf_step_batch", "icwf_sync", "icwf_observables",
            "icwf_get_state", "icwf_get_matrices", "icwf_velocities", "icwf_set_timing", "icwf_kernel_time",
            "icwf_contraction_rank",
            "icwf_destroy", "icwf_last_error", "icwf_status_string")
@@ -59,7 +59,7 @@ class Obs(ctypes.Structure):
 
 class ServerConfig(ctypes.Structure):
     _fields_ = [("max_active", c_int32), ("steps_per_turn", c_int32), ("turns_ahead", c_int32),
-                ("device", c_int32)]
+                ("device", c_int32), ("batch", c_int32)]
 
 
 class RequestInfo(ctypes.Structure):
@@ -105,6 +105,8 @@ def lib():
         L.icwf_create.restype = c_int32
         L.icwf_step.argtypes = [c_void_p, c_int32]
         L.icwf_step.restype = c_int32
+        L.icwf_step_batch.argtypes = [POINTER(c_void_p), c_int32, c_int32]
+        L.icwf_step_batch.restype = c_int32
         L.icwf_sync.argtypes = [c_void_p]
         L.icwf_sync.restype = c_int32
         L.icwf_observables.argtypes = [c_void_p, POINTER(Obs)]
@@ -215,6 +217,15 @@ def config_from_workload(wl, precision=PREC_FP64, eps=None, solver=SOLVER_AUTO, 
 
 def workspace_bytes(cfg):
     return int(lib().icwf_workspace_bytes(byref(cfg)))
+
+
+def step_batch(sims, n_steps=1):
+    """icwf_step_batch over Simulation objects that share a stream."""
+    arr = (c_void_p * len(sims))(*[sm.h for sm in sims])
+    st = lib().icwf_step_batch(arr, len(sims), int(n_steps))
+    if st != OK:
+        lead = sims[0].h if sims else None
+        raise ICWFError(st, lib().icwf_last_error(lead).decode())
 
 
 def bo_workspace_bytes(cfg, n_values, n_states):
@@ -441,7 +452,7 @@ class Server:
     library's scheduler thread admits submitted simulations into it as slots
     and memory free up and steps them concurrently."""
 
-    def __init__(self, arena_bytes, max_active=8, steps_per_turn=10, turns_ahead=2, device=0):
+    def __init__(self, arena_bytes, max_active=8, steps_per_turn=10, turns_ahead=2, device=0, batch=False):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("the ICWF library needs a GPU; none is visible")
@@ -450,7 +461,7 @@ class Server:
         self.arena = torch.empty(int(arena_bytes) + 256, dtype=torch.uint8, device=dev)
         torch.cuda.synchronize(dev)
         aligned = (self.arena.data_ptr() + 255) & ~255
-        cfg = ServerConfig(int(max_active), int(steps_per_turn), int(turns_ahead), dev.index or 0)
+        cfg = ServerConfig(int(max_active), int(steps_per_turn), int(turns_ahead), dev.index or 0, 1 if batch else 0)
         h = c_void_p()
         st = L.icwf_server_create(byref(cfg), c_void_p(aligned), c_size_t(int(arena_bytes)), byref(h))
         if st != OK:

@@ -12,9 +12,11 @@ grid.  Inputs are seeded and synthetic and resident in HBM before timing.
 
 Prints one JSON line: traj-steps/s over exactly K timed steps, the roofline
 of the dominant kernel (the two-body contraction, timed live with HIP events
-on the stream it runs on), the serving mix (served sims/s, p50 / p99
-time-to-result under Poisson arrivals, the speedup over running the same
-simulations one by one in FP64), the propagation's HBM rate on the
+on the stream it runs on), the mixed and separable forms on the same
+workload, a subset of the serving mix (served sims/s on streams and with
+fused lanes, p50 / p99 time-to-result under Poisson arrivals, each ratio
+against its own baseline), the GPU build of the BO basis of the large grid
+against the host eigensolver, the propagation's HBM rate on the
 N = 4096, 4096 x 512 workload (whose CWFs do not fit the Infinity Cache), the
 step time of the exact grid propagation of the full wavefunction at
 512 x 256 and 4096 x 512 (the reference ICWF converges to; skipped with
@@ -137,6 +139,35 @@ def exact_grid(steps=50):
         out[f"{nr}x{nR}"] = {"ms_per_step": ms, "bytes_per_step": nbytes, "achieved_gbs": nbytes / (ms / 1e3) / 1e9,
                              "peak_gbs": HBM_PEAK_GBS, "norm_after": norm}
     return out
+
+
+def bo_build(n_states=3):
+    """The BO basis of the large-grid workload on the GPU (include/icwf_bo.h):
+    the 3 lowest states of h_e(R_j) on the 4096-point electronic grid at all 512
+    nuclear grid points, wall clock of one call (upload, solve, copy-out) after
+    a warm-up call; beside it the host path it replaces (the input generator's
+    dense eigensolver) timed on one R value and scaled to 512."""
+    import numpy as np
+    from paper_1805_11169_amd import icwf, inputs
+    n_r, n_R = 4096, 512
+    r_box, R_box = (-75.0, 75.0), (-9.0, 9.0)
+    R = R_box[0] + (R_box[1] - R_box[0]) / n_R * np.arange(n_R)
+    cfg = icwf.make_config(4, n_r, n_R, r_box, R_box, 1.0, 1836.0, 0.1, inputs.MODEL_SHIN_METIU,
+                           inputs.SHIN_METIU_PARAMS)
+    icwf.bo_states(cfg, R[:8], n_states)
+    t0 = time.perf_counter()
+    _, _, info = icwf.bo_states(cfg, R, n_states)
+    gpu_s = time.perf_counter() - t0
+    hr = (r_box[1] - r_box[0]) / n_r
+    r = r_box[0] + hr * np.arange(n_r)
+    t0 = time.perf_counter()
+    inputs.bo_states(inputs.MODEL_SHIN_METIU, inputs.SHIN_METIU_PARAMS, r, hr, 1.0, R[:1], n_states)
+    host_one = time.perf_counter() - t0
+    return {"workload": f"BO states: {n_states} lowest of h_e(R_j), Shin-Metiu, {n_r}-point electronic grid at the "
+                        f"{n_R} nuclear grid points", "gpu_s": gpu_s, "iterations_max": info["iterations"],
+            "max_residual": info["max_residual"], "host_dense_eigh_s_per_value": host_one,
+            "host_extrapolated_s": host_one * n_R, "speedup_vs_host": host_one * n_R / gpu_s,
+            "host_cores": os.cpu_count()}
 
 
 def algorithmic_counts(N, nr, nR):
@@ -335,6 +366,7 @@ def main():
         line["propagation_4096x512"] = large_propagation()
     if not args.no_large_propagation and args.workload != "sm_n4096_large":
         line["exact_grid"] = exact_grid()
+        line["bo_states_4096x512"] = bo_build()
     if not args.no_serving:
         from paper_1805_11169_amd import serving
         line["serving"] = serving.measure(n_sims=args.serve_sims, n_steps=args.serve_steps,

@@ -19,6 +19,14 @@ Measured:
     result time minus arrival time;
   * the baseline: the same simulations one after another through the plain
     FP64 path (icwf_create, icwf_step, icwf_observables, icwf_destroy).
+Ratios are kept apart: served FP64 against sequential FP64 (what serving
+gains), served FP64 with lanes of fused steps against served FP64 without
+(what fusing gains), served mixed against served FP64 (what the precision
+form gains).
+
+`python -m paper_1805_11169_amd.serving --c5 [--precision P]` runs the whole
+256-simulation, 500-step mix (N over 64 ... 2048, both grids) once, closed
+then open loop, printing a line per 16 results.
 """
 
 import time
@@ -49,36 +57,46 @@ def footprints(wls, precision):
     return [icwf.workspace_bytes(icwf.config_from_workload(wl, precision)) for wl in wls]
 
 
-def _collect(server, ids):
-    res = []
-    for i in ids:
-        server.wait(i)
-        res.append(server.result(i))
-    return res
+def _collect(server, ids, say=None, every=16):
+    """Results in completion order as they come (polling), returned in submission order."""
+    res, pending, t0, last = {}, list(ids), time.perf_counter(), 0
+    while pending:
+        for i in list(pending):
+            if server.wait(i, timeout=0.0):
+                res[i] = server.result(i)
+                pending.remove(i)
+        if say and len(res) - last >= every:
+            last = len(res)
+            say(f"[serving] {len(res)}/{len(ids)} done, {time.perf_counter() - t0:.1f} s")
+        if pending:
+            time.sleep(0.002)
+    return [res[i] for i in ids]
 
 
-def run_closed(server, wls, precision):
+def run_closed(server, wls, precision, say=None):
     """Every request at t = 0; returns (sims/s, results)."""
     t0 = server.clock()
     ids = [server.submit_workload(wl, wl.n_steps, precision) for wl in wls]
-    res = _collect(server, ids)
+    res = _collect(server, ids, say)
     t1 = max(r["t_done"] for r in res)
     return len(wls) / (t1 - t0), res
 
 
-def run_open(server, wls, precision, rate, seed=2):
+def run_open(server, wls, precision, rate, seed=2, say=None):
     """Poisson arrivals at `rate` sims/s; returns (latencies in s, results)."""
     rng = np.random.default_rng(seed)
     arrivals = np.cumsum(rng.exponential(1.0 / rate, size=len(wls)))
     arrivals -= arrivals[0]
     start = time.perf_counter()
     ids = []
-    for wl, ta in zip(wls, arrivals):
+    for k, (wl, ta) in enumerate(zip(wls, arrivals)):
         delay = start + ta - time.perf_counter()
         if delay > 0:
             time.sleep(delay)
         ids.append(server.submit_workload(wl, wl.n_steps, precision))
-    res = _collect(server, ids)
+        if say and (k + 1) % 16 == 0:
+            say(f"[serving] {k + 1}/{len(wls)} submitted, {time.perf_counter() - start:.1f} s")
+    res = _collect(server, ids, say)
     lat = np.array([r["t_done"] - r["t_submit"] for r in res])
     return lat, res
 
@@ -104,42 +122,130 @@ def same_result(a, b):
     return all(np.array_equal(np.asarray(a[k]), np.asarray(b[k])) for k in keys)
 
 
-def measure(n_sims=32, n_steps=100, n_choices=(64, 128, 256, 512), load=0.8, max_active=8,
+def observable_difference(a, b):
+    """Largest difference of norm and densities (relative to their maximum)."""
+    d = abs(a["norm"] - b["norm"])
+    for k in ("rho_r", "rho_R"):
+        d = max(d, float(np.max(np.abs(np.asarray(a[k]) - np.asarray(b[k]))) / np.max(np.abs(b[k]))))
+    return d
+
+
+def _arena(fp, fraction):
+    return int(max(2 * max(fp), fraction * sum(fp)))
+
+
+def measure(n_sims=32, n_steps=100, n_choices=(64, 128, 256, 512), load=0.8, max_active=16,
             steps_per_turn=10, arena_fraction=0.35, log=None):
-    """The serving report: capacity, p50 / p99 under load, the sequential FP64
-    baseline and the alone-versus-mix check (a dict)."""
+    """The serving report on a subset of the serving mix (a dict): sequential
+    FP64; served FP64 on per-slot streams and with lanes of fused steps; served
+    mixed with lanes (capacity, then Poisson arrivals at `load` x capacity for
+    p50 / p99); the mixed results against their FP64 runs; alone versus in the
+    mix."""
     say = log or (lambda *_: None)
     wls = mix(n_sims, n_steps, n_choices)
-    prec = icwf.PREC_MIXED
-    fp = footprints(wls, prec)
-    arena = int(max(2 * max(fp), arena_fraction * sum(fp)))
+    fp64, mixed = icwf.PREC_FP64, icwf.PREC_MIXED
+    fp = [max(a, b) for a, b in zip(footprints(wls, fp64), footprints(wls, mixed))]
+    arena = _arena(fp, arena_fraction)
     say(f"[serving] {n_sims} sims, {n_steps} steps, arena {arena / 1e9:.2f} GB of {sum(fp) / 1e9:.2f} GB total")
 
-    seq_rate, seq_obs = run_sequential(wls, icwf.PREC_FP64)
+    seq_rate, seq_obs = run_sequential(wls, fp64)
     say(f"[serving] sequential FP64: {seq_rate:.2f} sims/s")
-    srv = icwf.Server(arena, max_active=max_active, steps_per_turn=steps_per_turn)
-    try:
-        cap64, _ = run_closed(srv, wls, icwf.PREC_FP64)
-        say(f"[serving] served FP64 capacity: {cap64:.2f} sims/s")
-        cap, res_closed = run_closed(srv, wls, prec)
-        say(f"[serving] served mixed capacity: {cap:.2f} sims/s")
-        lat, res_open = run_open(srv, wls, prec, load * cap)
-        say(f"[serving] open loop at {load * cap:.2f} sims/s: p50 {np.median(lat):.3f} s, "
-            f"p99 {np.percentile(lat, 99):.3f} s")
-        stats = srv.stats()
-    finally:
-        srv.close()
-    # alone versus in the mix: the same mixed-precision simulation run by itself
-    _, alone = run_sequential(wls[:4], prec)
-    equal = all(same_result(a, m) for a, m in zip(alone, res_closed[:4])) and \
-        all(same_result(a, m) for a, m in zip(alone, res_open[:4]))
-    failed = sum(r["status"] != icwf.OK for r in res_closed + res_open)
+    out = {}
+    for batch in (False, True):
+        srv = icwf.Server(arena, max_active=max_active, steps_per_turn=steps_per_turn, batch=batch)
+        try:
+            cap64, res64 = run_closed(srv, wls, fp64)
+            say(f"[serving] served FP64 ({'lanes' if batch else 'streams'}): {cap64:.2f} sims/s")
+            out[("fp64", batch)] = (cap64, res64)
+            if batch:
+                cap, res_closed = run_closed(srv, wls, mixed)
+                say(f"[serving] served mixed (lanes): {cap:.2f} sims/s")
+                lat, res_open = run_open(srv, wls, mixed, load * cap)
+                say(f"[serving] open loop at {load * cap:.2f} sims/s: p50 {np.median(lat):.3f} s, "
+                    f"p99 {np.percentile(lat, 99):.3f} s")
+                stats = srv.stats()
+        finally:
+            srv.close()
+    cap64s, res64s = out[("fp64", False)]
+    cap64b, res64b = out[("fp64", True)]
+    # every served result equals its alone (sequential) run; the mixed ones are within 1e-5 of their FP64 runs
+    equal = all(same_result(a, m) for a, m in zip(seq_obs, res64s)) and \
+        all(same_result(a, m) for a, m in zip(seq_obs, res64b))
+    _, alone_mixed = run_sequential(wls[:8], mixed)
+    equal = equal and all(same_result(a, m) for a, m in zip(alone_mixed, res_closed[:8])) and \
+        all(same_result(a, m) for a, m in zip(alone_mixed, res_open[:8]))
+    mixed_err = max(observable_difference(m, f) for m, f in zip(res_closed, seq_obs))
+    failed = sum(r["status"] != icwf.OK for r in res64s + res64b + res_closed + res_open)
     return {
+        "subset": f"{n_sims} of the 256-simulation mix, {n_steps} of its 500 steps, N over {list(n_choices)}",
         "sims": n_sims, "steps": n_steps, "n_choices": list(n_choices), "grids": [list(g) for g in GRIDS],
-        "precision": "mixed", "max_active": max_active, "steps_per_turn": steps_per_turn,
-        "capacity_sims_per_s": cap, "served_fp64_sims_per_s": cap64, "sequential_fp64_sims_per_s": seq_rate,
-        "speedup_vs_sequential_fp64": cap / seq_rate, "arrival_rate_sims_per_s": load * cap,
-        "p50_s": float(np.median(lat)), "p99_s": float(np.percentile(lat, 99)),
+        "max_active": max_active, "steps_per_turn": steps_per_turn,
+        "sequential_fp64_sims_per_s": seq_rate,
+        "served_fp64_streams_sims_per_s": cap64s, "served_fp64_lanes_sims_per_s": cap64b,
+        "served_mixed_lanes_sims_per_s": cap,
+        "ratio_served_fp64_vs_sequential_fp64": max(cap64s, cap64b) / seq_rate,
+        "ratio_fused_lanes_vs_streams_fp64": cap64b / cap64s,
+        "ratio_served_mixed_vs_served_fp64": cap / cap64b,
+        "mixed_vs_fp64_max_observable_difference": mixed_err,
+        "arrival_rate_sims_per_s": load * cap, "p50_s": float(np.median(lat)),
+        "p99_s": float(np.percentile(lat, 99)), "latency_precision": "mixed",
         "arena_bytes": arena, "footprint_total_bytes": int(sum(fp)), "arena_peak_bytes": stats["arena_peak"],
         "peak_active": stats["peak_active"], "failed": failed, "alone_equals_mix_bitwise": bool(equal),
     }
+
+
+C5_CHOICES = (64, 128, 256, 512, 1024, 2048)
+
+
+def c5(precision="mixed", load=0.8, max_active=16, steps_per_turn=10, arena_fraction=0.35, log=None,
+       n_sims=256, n_steps=500):
+    """The whole serving mix: 256 simulations, N log-uniform over 64 ... 2048,
+    both grids, R_f ~ U[4, 6], R_0 ~ U[-5, -3], 500 steps each; capacity
+    (closed loop) then Poisson arrivals at `load` x capacity (open loop)."""
+    say = log or (lambda *_: None)
+    prec = {"fp64": icwf.PREC_FP64, "mixed": icwf.PREC_MIXED, "separable": icwf.PREC_SEPARABLE}[precision]
+    t_in = time.perf_counter()
+    wls = mix(n_sims, n_steps, C5_CHOICES)
+    fp = footprints(wls, prec)
+    arena = _arena(fp, arena_fraction)
+    counts = {int(n): sum(wl.n_traj == n for wl in wls) for n in C5_CHOICES}
+    say(f"[c5] {n_sims} sims built in {time.perf_counter() - t_in:.0f} s; N counts {counts}; arena "
+        f"{arena / 1e9:.1f} GB of {sum(fp) / 1e9:.1f} GB")
+    srv = icwf.Server(arena, max_active=max_active, steps_per_turn=steps_per_turn, batch=True)
+    try:
+        cap, res_closed = run_closed(srv, wls, prec, say)
+        say(f"[c5] capacity {cap:.4f} sims/s")
+        lat, res_open = run_open(srv, wls, prec, load * cap, say=say)
+        stats = srv.stats()
+    finally:
+        srv.close()
+    failed = sum(r["status"] != icwf.OK for r in res_closed + res_open)
+    by_n = {}
+    for n in C5_CHOICES:
+        sel = [l for l, wl in zip(lat, wls) if wl.n_traj == n]
+        if sel:
+            by_n[int(n)] = {"p50_s": float(np.median(sel)), "p99_s": float(np.percentile(sel, 99))}
+    return {"workload": "serving mix: 256 Shin-Metiu simulations, N log-uniform over 64..2048, grids 512x256 or "
+                        "1024x512, R_f ~ U[4,6], R_0 ~ U[-5,-3], 500 steps, Poisson arrivals at 0.8 x capacity",
+            "precision": precision, "sims": n_sims, "steps": n_steps, "n_counts": counts,
+            "capacity_sims_per_s": cap, "arrival_rate_sims_per_s": load * cap,
+            "p50_s": float(np.median(lat)), "p99_s": float(np.percentile(lat, 99)), "latency_by_n": by_n,
+            "arena_bytes": arena, "footprint_total_bytes": int(sum(fp)), "arena_peak_bytes": stats["arena_peak"],
+            "peak_active": stats["peak_active"], "max_active": max_active, "failed": failed}
+
+
+if __name__ == "__main__":
+    import argparse
+    import json
+    import sys
+
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--c5", action="store_true")
+    ap.add_argument("--precision", default="mixed", choices=["fp64", "mixed", "separable"])
+    ap.add_argument("--sims", type=int, default=256)
+    ap.add_argument("--steps", type=int, default=500)
+    a = ap.parse_args()
+    if not a.c5:
+        ap.error("only --c5 runs from the command line")
+    rep = c5(a.precision, n_sims=a.sims, n_steps=a.steps, log=lambda m: print(m, file=sys.stderr, flush=True))
+    print(json.dumps(rep), flush=True)

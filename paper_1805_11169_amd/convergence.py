@@ -7,7 +7,8 @@ conditional wavefunctions grows (text around the Shin-Metiu figures).  Here
 both run on the GPU from the Shin-Metiu product start of the throughput
 workload (512 x 256, dt = 0.1, three BO states): the exact wavefunction from
 Psi_0 = phi_e(r) chi_0(R) on the grid, ICWF with N trajectories sampled from
-|Psi_0|^2 (seed `seed`), FP64, Tikhonov eps and dt as given.
+|Psi_0|^2 (seed `seed`), FP64, Tikhonov eps, dt and the trajectory
+integrator (Euler or Heun) as given.
 
 Reported per N, as the maximum over the checkpoints (every `every` steps):
   * pop: max_n |P_n - P_n^exact|,
@@ -16,7 +17,7 @@ Reported per N, as the maximum over the checkpoints (every `every` steps):
   * norm: |C^H S C - 1| (the exact norm is 1 to rounding),
 with the wall time per step of each propagation and the populations at the
 last checkpoint.  Used as
-    python -m paper_1805_11169_amd.convergence [--steps S] [--every K] [--n 16,64,256,1024]
+    python -m paper_1805_11169_amd.convergence [--steps S] [--every K] [--n 16,64,256,1024] [--heun]
 it prints one JSON line.
 """
 
@@ -36,7 +37,8 @@ def _errors(got, ref):
                 norm=float(abs(got["norm"] - 1.0)))
 
 
-def run(ns=(16, 32, 64, 128, 256, 512, 1024), steps=2000, every=200, seed=0, n_bo=3, eps=1e-8, dt=0.1, log=print):
+def run(ns=(16, 32, 64, 128, 256, 512, 1024), steps=2000, every=200, seed=0, n_bo=3, eps=1e-8, dt=0.1, log=print,
+        trajectories=icwf.TRAJ_EULER):
     import torch
     base = inputs.shin_metiu(ns[0], n_bo=n_bo, seed=seed, dt=dt, eps=eps)
     psi0 = np.outer(base.extra["phi_e"], base.extra["chi0"]).astype(np.complex128)
@@ -58,7 +60,7 @@ def run(ns=(16, 32, 64, 128, 256, 512, 1024), steps=2000, every=200, seed=0, n_b
     rows = []
     for N in ns:
         wl = inputs.shin_metiu(N, n_bo=n_bo, seed=seed, dt=dt, eps=eps)
-        sim = icwf.Simulation.from_workload(wl)
+        sim = icwf.Simulation.from_workload(wl, trajectories=trajectories)
         worst = dict(pop=0.0, rho_R=0.0, D=0.0, norm=0.0)
         status, t_icwf, done, last = "ok", 0.0, 0, None
         try:
@@ -82,6 +84,7 @@ def run(ns=(16, 32, 64, 128, 256, 512, 1024), steps=2000, every=200, seed=0, n_b
                                           for k, v in row.items() if k not in ("N", "final_pop")))
         rows.append(row)
     return dict(workload=base.name.replace(f"_N{ns[0]}", ""), steps=steps, every=every, dt=base.dt, eps=eps, seed=seed,
+                trajectories="heun" if trajectories == icwf.TRAJ_HEUN else "euler",
                 exact_ms_per_step=1e3 * t_exact / steps, exact_final=dict(pop=exact[-1]["pop"].tolist(),
                                                                           norm=exact[-1]["norm"]),
                 icwf=rows)
@@ -95,9 +98,10 @@ def main():
     p.add_argument("--seed", type=int, default=0)
     p.add_argument("--eps", type=float, default=1e-8, help="Tikhonov eps of the coefficient equation")
     p.add_argument("--dt", type=float, default=0.1)
+    p.add_argument("--heun", action="store_true", help="Heun (predictor-corrector) trajectories")
     a = p.parse_args()
     res = run(tuple(int(x) for x in a.n.split(",")), a.steps, a.every, a.seed, eps=a.eps, dt=a.dt,
-              log=lambda m: print(m, flush=True))
+              log=lambda m: print(m, flush=True), trajectories=icwf.TRAJ_HEUN if a.heun else icwf.TRAJ_EULER)
     print(json.dumps(res))
 
 

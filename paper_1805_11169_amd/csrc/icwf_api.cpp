@@ -227,6 +227,7 @@ struct icwf_sim {
     hipStream_t side_stream = nullptr;        // the S assembly and the factorisations, beside the contraction
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     hipGraphExec_t exec[2] = {nullptr, nullptr};
+    std::map<int, hipGraphExec_t> batch_exec;  // steps of batches this simulation leads, by 2 x size + parity
     int parity = 0;
     int64_t step = 0;
     double t = 0.0;
@@ -686,8 +687,23 @@ icwf_status icwf_step_batch(icwf_sim *const *sims, int32_t n_sims, int32_t n_ste
     d.batch = n_sims;
     d.zoff = lead->b.batch_tab;
     for (int k = 0; k < n_steps; ++k) {
-        enqueue_step(lead, d, lead->parity, lead->stream, lead->stream);
-        HIP_OK(hipGetLastError(), lead);
+        // the step of a batch of this size and parity, captured once per lead:
+        // its launches depend on the lead and the size only (the members come
+        // from the table written above)
+        hipGraphExec_t &ex = lead->batch_exec[2 * n_sims + lead->parity];
+        if (!ex) {
+            hipGraph_t g = nullptr;
+            HIP_OK(hipStreamBeginCapture(lead->capture_stream, hipStreamCaptureModeThreadLocal), lead);
+            enqueue_step(lead, d, lead->parity, lead->capture_stream, lead->capture_stream);
+            HIP_OK(hipStreamEndCapture(lead->capture_stream, &g), lead);
+            const hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            if (e != hipSuccess) {
+                ex = nullptr;
+                return fail(lead, ICWF_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+            }
+        }
+        HIP_OK(hipGraphLaunch(ex, lead->stream), lead);
         for (int q = 0; q < n_sims; ++q) {
             sims[q]->parity ^= 1;
             sims[q]->step += 1;
@@ -823,6 +839,7 @@ void icwf_destroy(icwf_sim *s) {
     if (s->stream || s->capture_stream) (void)hipStreamSynchronize(s->stream);
     for (auto &e : s->exec)
         if (e) (void)hipGraphExecDestroy(e);
+    for (auto &kv : s->batch_exec) (void)hipGraphExecDestroy(kv.second);
     if (s->side_stream) (void)hipStreamSynchronize(s->side_stream);
     if (s->capture_stream) (void)hipStreamDestroy(s->capture_stream);
     if (s->side_stream) (void)hipStreamDestroy(s->side_stream);

@@ -99,11 +99,12 @@ __device__ inline T zpick(const T (&a)[6], int z) {
     return r;
 }
 
+template <bool BATCHED>
 __global__ void __launch_bounds__(256, 2) k_zgemm(ZBatch zb, int Np, const int32_t *__restrict__ flags, int zcnt,
                                                   const long long *__restrict__ zoff) {
     // grid z: zcnt products of each simulation of the launch
-    const int sim = blockIdx.z / zcnt, z = blockIdx.z - sim * zcnt;
-    const long long zo_ = batch_offset(zoff, sim);
+    const int sim = BATCHED ? blockIdx.z / zcnt : 0, z = blockIdx.z - sim * zcnt;
+    const long long zo_ = BATCHED ? batch_offset(zoff, sim) : 0;
     flags = zshift(flags, zo_);
     if (flags[kFlagHalt]) return;
     const int bt = blockIdx.y, at = blockIdx.x;
@@ -245,14 +246,14 @@ struct WcChunk {
     static constexpr int PER = KC / 8;                    // elements each thread stages per array
 };
 
-template <typename T>
+template <typename T, bool BATCHED>
 __global__ void __launch_bounds__(256, 2) k_wc(const typename WcTraits<T>::cplx *__restrict__ psi1,
                                                const double2 *__restrict__ psi2,
                                                const T *__restrict__ wtab, int nr, int nR, double scale,
                                                double2 *__restrict__ Wc, int Np, int accumulate,
                                                int ntiles, int nsplit, int nparts, int32_t *__restrict__ queue,
                                                double2 *__restrict__ part, const int32_t *__restrict__ flags, const long long *__restrict__ zoff) {
-    const long long zo_ = batch_offset(zoff);
+    const long long zo_ = BATCHED ? batch_offset(zoff) : 0;
     psi1 = zshift(psi1, zo_);
     psi2 = zshift(psi2, zo_);
     wtab = zshift(wtab, zo_);
@@ -518,12 +519,13 @@ __device__ inline void sep_pass(dbl4 (&acc)[4][2], const double2 *__restrict__ X
     }
 }
 
+template <bool BATCHED>
 __global__ void __launch_bounds__(256, 2) k_wc_sep(const double2 *__restrict__ psi1, const double2 *__restrict__ psi2,
                                                    const double *__restrict__ U, const double *__restrict__ V,
                                                    int kpad, int nr, int nR, double scale,
                                                    double2 *__restrict__ Wc, int Np, int accumulate, int ntiles,
                                                    int32_t *__restrict__ queue, const int32_t *__restrict__ flags, const long long *__restrict__ zoff) {
-    const long long zo_ = batch_offset(zoff);
+    const long long zo_ = BATCHED ? batch_offset(zoff) : 0;
     psi1 = zshift(psi1, zo_);
     psi2 = zshift(psi2, zo_);
     U = zshift(U, zo_);
@@ -622,7 +624,8 @@ void launch_single_species(const Dims &d, const Bufs &b, bool both, hipStream_t 
         add(b.psi1, b.G1b, b.E1b, d.nr, d.hr);
         add(b.psi2, b.G2b, b.E2b, d.nR, d.hR);
     }
-    hipLaunchKernelGGL(k_zgemm, dim3(Np / kZT, Np / kZT, c * d.batch), dim3(256), 0, s, zb, Np, b.flags, c, d.zoff);
+    hipLaunchKernelGGL(d.zoff ? k_zgemm<true> : k_zgemm<false>, dim3(Np / kZT, Np / kZT, c * d.batch), dim3(256), 0, s,
+                       zb, Np, b.flags, c, d.zoff);
 }
 
 void launch_single_species_next(const Dims &d, const Bufs &b, hipStream_t s) {
@@ -638,7 +641,8 @@ void launch_single_species_next(const Dims &d, const Bufs &b, hipStream_t s) {
     zb.out[1] = b.E2b;
     zb.K[1] = d.nR;
     zb.scale[1] = d.hR;
-    hipLaunchKernelGGL(k_zgemm, dim3(Np / kZT, Np / kZT, 2 * d.batch), dim3(256), 0, s, zb, Np, b.flags, 2, d.zoff);
+    hipLaunchKernelGGL(d.zoff ? k_zgemm<true> : k_zgemm<false>, dim3(Np / kZT, Np / kZT, 2 * d.batch), dim3(256), 0, s,
+                       zb, Np, b.flags, 2, d.zoff);
 }
 
 void launch_wc(const Dims &d, const Bufs &b, hipStream_t s) {
@@ -656,25 +660,25 @@ void launch_wc(const Dims &d, const Bufs &b, hipStream_t s) {
         // (the FP32 pass only where the residual is above the table's rounding)
         if (d.fp32_residual) {
             launch_fill_i32(b.wc_queue, 1 + nsplit, 0, s, d.batch, d.zoff);
-            hipLaunchKernelGGL(k_wc<float>, dim3(grid, 1, d.batch), dim3(256), 0, s, b.psi1_f32, b.psi2, b.wc32, d.nr,
+            hipLaunchKernelGGL((d.zoff ? k_wc<float, true> : k_wc<float, false>), dim3(grid, 1, d.batch), dim3(256), 0, s, b.psi1_f32, b.psi2, b.wc32, d.nr,
                                d.nR, scale, b.Wc, Np, 0, blocks, nsplit, nparts, b.wc_queue, b.wc_part, b.flags,
                                d.zoff);
         }
         if (d.lr_rank > 0) {
             launch_fill_i32(b.wc_queue, 1, 0, s, d.batch, d.zoff);
-            hipLaunchKernelGGL(k_wc_sep, dim3(std::min(blocks, d.wc_grid), 1, d.batch), dim3(256), 0, s, b.psi1,
+            hipLaunchKernelGGL(d.zoff ? k_wc_sep<true> : k_wc_sep<false>, dim3(std::min(blocks, d.wc_grid), 1, d.batch), dim3(256), 0, s, b.psi1,
                                b.psi2, b.lr_u, b.lr_v, (d.lr_rank + 15) / 16 * 16, d.nr, d.nR, scale, b.Wc, Np,
                                d.fp32_residual ? 1 : 0, blocks, b.wc_queue, b.flags, d.zoff);
         }
     } else if (d.prec == 2) {
         // separable: the whole contraction through the sum of products (assigns Wc)
         launch_fill_i32(b.wc_queue, 1, 0, s, d.batch, d.zoff);
-        hipLaunchKernelGGL(k_wc_sep, dim3(std::min(blocks, d.wc_grid), 1, d.batch), dim3(256), 0, s, b.psi1, b.psi2,
+        hipLaunchKernelGGL(d.zoff ? k_wc_sep<true> : k_wc_sep<false>, dim3(std::min(blocks, d.wc_grid), 1, d.batch), dim3(256), 0, s, b.psi1, b.psi2,
                            b.lr_u, b.lr_v, (d.lr_rank + 15) / 16 * 16, d.nr, d.nR, scale, b.Wc, Np, 0, blocks,
                            b.wc_queue, b.flags, d.zoff);
     } else {
         launch_fill_i32(b.wc_queue, 1 + nsplit, 0, s, d.batch, d.zoff);
-        hipLaunchKernelGGL(k_wc<double>, dim3(grid, 1, d.batch), dim3(256), 0, s, b.psi1, b.psi2, b.wc64, d.nr, d.nR,
+        hipLaunchKernelGGL((d.zoff ? k_wc<double, true> : k_wc<double, false>), dim3(grid, 1, d.batch), dim3(256), 0, s, b.psi1, b.psi2, b.wc64, d.nr, d.nR,
                            scale, b.Wc, Np, 0, blocks, nsplit, nparts, b.wc_queue, b.wc_part, b.flags, d.zoff);
     }
 }

@@ -352,13 +352,13 @@ __device__ inline double wave_uniform(double x) {
 // for that the per-CWF constant phase comes precomputed (cph) rather than
 // from the model's erf, whose constants would stay in registers across the
 // loop, and every global access is a uniform base plus a 32-bit lane offset.
-template <int LOG2N>
+template <int LOG2N, bool BATCHED>
 __global__ void __launch_bounds__(512, LOG2N == kFourStepLog2 ? 4 : 1)
     k_propagate(double2 *__restrict__ psi, int ngroups, const double2 *__restrict__ vphase, double x_min, double h,
                 const double *__restrict__ cond, const double2 *__restrict__ cph, int species, ModelParams mp,
                 const double2 *__restrict__ kin, const double2 *__restrict__ tw, double dt, int tiny,
                 float2 *__restrict__ psi_f32, const int32_t *__restrict__ flags, const long long *__restrict__ zoff, const ModelParams *__restrict__ mpd) {
-    const long long zo_ = batch_offset(zoff);
+    const long long zo_ = BATCHED ? batch_offset(zoff) : 0;
     psi = zshift(psi, zo_);
     vphase = zshift(vphase, zo_);
     cond = zshift(cond, zo_);
@@ -367,7 +367,7 @@ __global__ void __launch_bounds__(512, LOG2N == kFourStepLog2 ? 4 : 1)
     tw = zshift(tw, zo_);
     psi_f32 = zshift(psi_f32, zo_);
     flags = zshift(flags, zo_);
-    if (zoff) mp = *zshift(mpd, zo_);
+    if (BATCHED) mp = *zshift(mpd, zo_);
 
     if (flags[kFlagHalt]) return;
     extern __shared__ double2 sh_all[];
@@ -518,19 +518,23 @@ namespace {
 using PropKernel = void (*)(double2 *, int, const double2 *, double, double, const double *, const double2 *, int,
                             ModelParams, const double2 *, const double2 *, double, int, float2 *, const int32_t *,
                             const long long *, const ModelParams *);
-PropKernel kernel_for(int n) {
+template <bool B>
+PropKernel kernel_for_t(int n) {
     switch (ilog2(n)) {
-    case 5: return k_propagate<5>;
-    case 6: return k_propagate<6>;
-    case 7: return k_propagate<7>;
-    case 8: return k_propagate<8>;
-    case 9: return k_propagate<9>;
-    case 10: return k_propagate<10>;
-    case 11: return k_propagate<11>;
-    case 12: return k_propagate<12>;
+    case 5: return k_propagate<5, B>;
+    case 6: return k_propagate<6, B>;
+    case 7: return k_propagate<7, B>;
+    case 8: return k_propagate<8, B>;
+    case 9: return k_propagate<9, B>;
+    case 10: return k_propagate<10, B>;
+    case 11: return k_propagate<11, B>;
+    case 12: return k_propagate<12, B>;
     default: return nullptr;
     }
 }
+// batched: the instantiation with the per-simulation offsets (launches of
+// one simulation keep the kernel without them)
+PropKernel kernel_for(int n, bool batched = false) { return batched ? kernel_for_t<true>(n) : kernel_for_t<false>(n); }
 }  // namespace
 
 int propagate_grid(int n, int N, int ncu) {
@@ -558,7 +562,7 @@ void launch_propagate(const Dims &d, const Bufs &b, int species, hipStream_t s) 
     const int ngroups = padded(d.N) / (T / (n / kPts));   // padded rows hold zero CWFs
     const int grid = d.prop_grid[species - 1];
     const size_t lds = lds_for(n);
-    const PropKernel k = kernel_for(n);      // n is validated at creation (a power of two in [32, 4096])
+    const PropKernel k = kernel_for(n, d.zoff != nullptr);   // n validated at creation: a power of two in [32, 4096]
     // the Shin-Metiu coupling phase stays within the short series' range
     const int tiny = propagate_tiny_phase(d) ? 1 : 0;
     if (species == 1) {

@@ -186,13 +186,14 @@ __device__ __forceinline__ void vel_species(const double *__restrict__ Sg, const
     }
 }
 
+template <bool BATCHED>
 __global__ void __launch_bounds__(256) k_vel_gemm(const double *__restrict__ Sr, const double *__restrict__ Dr,
                                                   const double2 *__restrict__ psi1, int nr,
                                                   const double *__restrict__ SR, const double *__restrict__ DR,
                                                   const double2 *__restrict__ psi2, int nR,
                                                   const double2 *__restrict__ C, int Np,
                                                   double2 *__restrict__ part, const int32_t *__restrict__ flags, const long long *__restrict__ zoff) {
-    const long long zo_ = batch_offset(zoff);
+    const long long zo_ = BATCHED ? batch_offset(zoff) : 0;
     Sr = zshift(Sr, zo_);
     Dr = zshift(Dr, zo_);
     psi1 = zshift(psi1, zo_);
@@ -363,7 +364,7 @@ void launch_velocity(const Dims &d, const Bufs &b, VelocityMode mode, hipStream_
                        b.flags, d.zoff);
     hipLaunchKernelGGL(k_sinc, dim3(Np, 1, B), dim3(256), 0, s, pR, Np, d.nR, d.R_min, d.hR, b.sinc_R, b.dsinc_R,
                        b.flags, d.zoff);
-    hipLaunchKernelGGL(k_vel_gemm, dim3(Np / kVA, Np / kVB, B), dim3(256), 0, s, b.sinc_r, b.dsinc_r, b.psi1, d.nr,
+    hipLaunchKernelGGL(d.zoff ? k_vel_gemm<true> : k_vel_gemm<false>, dim3(Np / kVA, Np / kVB, B), dim3(256), 0, s, b.sinc_r, b.dsinc_r, b.psi1, d.nr,
                        b.sinc_R, b.dsinc_R, b.psi2, d.nR, b.C, Np, b.vpart, b.flags, d.zoff);
     unsigned long long *min_bits = reinterpret_cast<unsigned long long *>(b.scal);
     // min |Psi| over the step's evaluations: the corrector keeps the first pass's minimum

@@ -134,7 +134,7 @@ def _arena(fp, fraction):
     return int(max(2 * max(fp), fraction * sum(fp)))
 
 
-def measure(n_sims=32, n_steps=100, n_choices=(64, 128, 256, 512), load=0.8, max_active=16,
+def measure(n_sims=32, n_steps=100, n_choices=(64, 128, 256, 512), load=0.8, max_active=32,
             steps_per_turn=10, arena_fraction=0.35, log=None):
     """The serving report on a subset of the serving mix (a dict): sequential
     FP64; served FP64 on per-slot streams and with lanes of fused steps; served
@@ -197,11 +197,13 @@ def measure(n_sims=32, n_steps=100, n_choices=(64, 128, 256, 512), load=0.8, max
 C5_CHOICES = (64, 128, 256, 512, 1024, 2048)
 
 
-def c5(precision="mixed", load=0.8, max_active=16, steps_per_turn=10, arena_fraction=0.35, log=None,
-       n_sims=256, n_steps=500):
+def c5(precision="mixed", load=0.8, max_active=32, steps_per_turn=10, arena_fraction=0.35, log=None,
+       n_sims=256, n_steps=500, phase="both", capacity=None):
     """The whole serving mix: 256 simulations, N log-uniform over 64 ... 2048,
     both grids, R_f ~ U[4, 6], R_0 ~ U[-5, -3], 500 steps each; capacity
-    (closed loop) then Poisson arrivals at `load` x capacity (open loop)."""
+    (closed loop) then Poisson arrivals at `load` x capacity (open loop).
+    phase "closed" or "open" runs one of the two (the open loop then takes
+    the capacity measured by a closed run)."""
     say = log or (lambda *_: None)
     prec = {"fp64": icwf.PREC_FP64, "mixed": icwf.PREC_MIXED, "separable": icwf.PREC_SEPARABLE}[precision]
     t_in = time.perf_counter()
@@ -212,26 +214,37 @@ def c5(precision="mixed", load=0.8, max_active=16, steps_per_turn=10, arena_frac
     say(f"[c5] {n_sims} sims built in {time.perf_counter() - t_in:.0f} s; N counts {counts}; arena "
         f"{arena / 1e9:.1f} GB of {sum(fp) / 1e9:.1f} GB")
     srv = icwf.Server(arena, max_active=max_active, steps_per_turn=steps_per_turn, batch=True)
+    res_closed, res_open, lat, cap = [], [], None, capacity
     try:
-        cap, res_closed = run_closed(srv, wls, prec, say)
-        say(f"[c5] capacity {cap:.4f} sims/s")
-        lat, res_open = run_open(srv, wls, prec, load * cap, say=say)
+        if phase in ("both", "closed"):
+            cap, res_closed = run_closed(srv, wls, prec, say)
+            say(f"[c5] capacity {cap:.4f} sims/s")
+        if phase in ("both", "open"):
+            lat, res_open = run_open(srv, wls, prec, load * cap, say=say)
         stats = srv.stats()
     finally:
         srv.close()
     failed = sum(r["status"] != icwf.OK for r in res_closed + res_open)
-    by_n = {}
-    for n in C5_CHOICES:
-        sel = [l for l, wl in zip(lat, wls) if wl.n_traj == n]
-        if sel:
-            by_n[int(n)] = {"p50_s": float(np.median(sel)), "p99_s": float(np.percentile(sel, 99))}
-    return {"workload": "serving mix: 256 Shin-Metiu simulations, N log-uniform over 64..2048, grids 512x256 or "
-                        "1024x512, R_f ~ U[4,6], R_0 ~ U[-5,-3], 500 steps, Poisson arrivals at 0.8 x capacity",
-            "precision": precision, "sims": n_sims, "steps": n_steps, "n_counts": counts,
-            "capacity_sims_per_s": cap, "arrival_rate_sims_per_s": load * cap,
-            "p50_s": float(np.median(lat)), "p99_s": float(np.percentile(lat, 99)), "latency_by_n": by_n,
-            "arena_bytes": arena, "footprint_total_bytes": int(sum(fp)), "arena_peak_bytes": stats["arena_peak"],
-            "peak_active": stats["peak_active"], "max_active": max_active, "failed": failed}
+    rep = {"workload": "serving mix: 256 Shin-Metiu simulations, N log-uniform over 64..2048, grids 512x256 or "
+                       "1024x512, R_f ~ U[4,6], R_0 ~ U[-5,-3], 500 steps, Poisson arrivals at 0.8 x capacity",
+           "precision": precision, "phase": phase, "sims": n_sims, "steps": n_steps, "n_counts": counts,
+           "capacity_sims_per_s": cap, "arena_bytes": arena, "footprint_total_bytes": int(sum(fp)),
+           "arena_peak_bytes": stats["arena_peak"], "peak_active": stats["peak_active"], "max_active": max_active,
+           "failed": failed}
+    if res_closed:
+        # per N: time from admission to result in the closed loop (the service time under full load)
+        rep["closed_service_s_by_n"] = {
+            int(n): float(np.median([r["t_done"] - r["t_admit"] for r, wl in zip(res_closed, wls) if wl.n_traj == n]))
+            for n in C5_CHOICES if any(wl.n_traj == n for wl in wls)}
+    if lat is not None:
+        by_n = {}
+        for n in C5_CHOICES:
+            sel = [l for l, wl in zip(lat, wls) if wl.n_traj == n]
+            if sel:
+                by_n[int(n)] = {"p50_s": float(np.median(sel)), "p99_s": float(np.percentile(sel, 99))}
+        rep.update({"arrival_rate_sims_per_s": load * cap, "p50_s": float(np.median(lat)),
+                    "p99_s": float(np.percentile(lat, 99)), "latency_by_n": by_n})
+    return rep
 
 
 if __name__ == "__main__":
@@ -244,8 +257,14 @@ if __name__ == "__main__":
     ap.add_argument("--precision", default="mixed", choices=["fp64", "mixed", "separable"])
     ap.add_argument("--sims", type=int, default=256)
     ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--phase", default="both", choices=["both", "closed", "open"])
+    ap.add_argument("--capacity", type=float, default=None, help="sims/s of a closed run (for --phase open)")
+    ap.add_argument("--max-active", type=int, default=32)
     a = ap.parse_args()
     if not a.c5:
         ap.error("only --c5 runs from the command line")
-    rep = c5(a.precision, n_sims=a.sims, n_steps=a.steps, log=lambda m: print(m, file=sys.stderr, flush=True))
+    if a.phase == "open" and not a.capacity:
+        ap.error("--phase open needs --capacity")
+    rep = c5(a.precision, n_sims=a.sims, n_steps=a.steps, phase=a.phase, capacity=a.capacity,
+             max_active=a.max_active, log=lambda m: print(m, file=sys.stderr, flush=True))
     print(json.dumps(rep), flush=True)

@@ -12,8 +12,11 @@
  *     many simulations are resident;
  *   - keeps every admitted simulation's CWFs, trajectories, coefficients and
  *     matrices resident in its block of the arena until it finishes;
- *   - advances every admitted simulation in turns of steps_per_turn steps,
- *     each step a replay of the simulation's captured HIP graph on the slot's
+ *   - advances every admitted simulation in turns of about equal device
+ *     time: steps_per_turn steps for the costliest resident simulation, and
+ *     for a cheaper one proportionally more (by an estimate of its step's
+ *     cost from its configuration), each step a replay of the simulation's
+ *     captured HIP graph on the slot's
  *     own stream (default priority), keeping up to turns_ahead turns queued,
  *     so the work of different simulations overlaps on the device; with
  *     batching on, small simulations of one shape instead share a lane and
@@ -43,7 +46,8 @@ typedef struct icwf_server icwf_server;
 
 typedef struct {
     int32_t max_active;      /* slots: simulations resident and stepping at once, 1..64        */
-    int32_t steps_per_turn;  /* steps enqueued per simulation per scheduling turn, >= 1          */
+    int32_t steps_per_turn;  /* steps per scheduling turn of the costliest resident simulation
+                                (cheaper ones take proportionally more), >= 1                  */
     int32_t turns_ahead;     /* turns kept queued on a slot's stream, 1..4                      */
     int32_t device;          /* HIP device the arena lives on                                   */
     int32_t batch;           /* 0: every simulation on its own slot stream; 1: simulations of one

@@ -30,6 +30,7 @@ struct Request {
     icwf_config cfg{};
     int32_t n_steps = 0;
     size_t ws = 0;
+    double cost = 1.0;             // estimated device time of one step (ms), for equal-time turns
     std::vector<double> r0, R0, psi1, psi2, C0, b0, bo;
     bool has_C0 = false;
     // result
@@ -86,6 +87,21 @@ struct icwf_server {
 };
 
 namespace {
+
+// Estimated device time of one step (ms): a launch-bound floor plus the
+// step's flops at a sustained 40 TFLOP/s (the two-body contraction, dense or
+// through its rank factors, the single-species products and velocities, two
+// complex factorisations).  Only ratios between simulations matter: the
+// scheduler gives every simulation turns of about the same device time.
+double step_cost_ms(const icwf_config &c) {
+    const double N = (double)((c.n_traj + 63) / 64 * 64), nr = c.n_r, nR = c.n_R;
+    const double pairs = 0.5 * N * (N + 1.0);
+    double contraction = 4.0 * pairs * nr * nR;
+    if (c.precision == ICWF_PREC_MIXED) contraction *= 0.6;
+    if (c.precision == ICWF_PREC_SEPARABLE) contraction = 4.0 * pairs * (nr + nR) * 32.0;
+    const double rest = 28.0 * N * N * (nr + nR) + 2.0 * (8.0 / 3.0) * N * N * N;
+    return 0.4 + (contraction + rest) / 4e10;
+}
 
 void set_message(Request &rq, const std::string &m) {
     std::strncpy(rq.info.message, m.c_str(), sizeof(rq.info.message) - 1);
@@ -239,19 +255,36 @@ bool poll(icwf_server *S, Slot &sl, bool *gone) {
     return progress;
 }
 
+// Steps of the slot's next turn: steps_per_turn for the costliest resident
+// simulation, proportionally more for cheaper ones (turns of about equal
+// device time, so that a small simulation is not held to the pace of the
+// largest), never past its last step.
+int32_t turn_steps(const icwf_server *S, const Slot &sl, double ref_cost) {
+    const double scale = std::max(1.0, ref_cost / sl.req->cost);
+    const double k = std::min(S->cfg.steps_per_turn * scale, 1e6);
+    return std::max(1, std::min((int32_t)k, sl.req->n_steps - sl.enqueued));
+}
+
+double reference_cost(const icwf_server *S) {
+    double ref = 0.0;
+    for (const Slot &sl : S->slots)
+        if (sl.sim) ref = std::max(ref, sl.req->cost);
+    return ref;
+}
+
 // One turn of a lane: the members with room for another turn, grouped by step
 // parity, each group one fused icwf_step_batch on the lane's stream.
-bool advance_lane(icwf_server *S, int li) {
+bool advance_lane(icwf_server *S, int li, double ref_cost) {
     Lane &ln = S->lanes[li];
     bool progress = false;
     for (int par = 0; par < 2; ++par) {
         std::vector<Slot *> grp;
-        int32_t k = S->cfg.steps_per_turn;
+        int32_t k = 1 << 30;
         for (Slot &sl : S->slots)
             if (sl.sim && sl.lane == li && sl.status == ICWF_OK && (int)sl.inflight.size() < S->cfg.turns_ahead &&
                 sl.enqueued < sl.req->n_steps && (sl.enqueued & 1) == par) {
                 grp.push_back(&sl);
-                k = std::min(k, sl.req->n_steps - sl.enqueued);
+                k = std::min(k, turn_steps(S, sl, ref_cost));
             }
         if (grp.empty()) continue;
         std::vector<icwf_sim *> sims;
@@ -276,6 +309,7 @@ bool advance_lane(icwf_server *S, int li) {
 // One pass over the admitted simulations; true if anything moved.
 bool advance(icwf_server *S) {
     bool progress = false;
+    const double ref_cost = reference_cost(S);
     for (Slot &sl : S->slots) {
         if (!sl.sim) continue;
         bool gone = false;
@@ -283,7 +317,7 @@ bool advance(icwf_server *S) {
         if (gone || sl.lane >= 0) continue;
         while (sl.status == ICWF_OK && (int)sl.inflight.size() < S->cfg.turns_ahead &&
                sl.enqueued < sl.req->n_steps) {
-            const int32_t k = std::min(S->cfg.steps_per_turn, sl.req->n_steps - sl.enqueued);
+            const int32_t k = turn_steps(S, sl, ref_cost);
             hipEvent_t ev = take_event(sl);
             if (!ev || icwf_step(sl.sim, k) != ICWF_OK || hipEventRecord(ev, sl.stream) != hipSuccess) {
                 if (ev) sl.pool.push_back(ev);
@@ -296,7 +330,7 @@ bool advance(icwf_server *S) {
         }
     }
     for (int li = 0; li < (int)S->lanes.size(); ++li)
-        if (S->lanes[li].members > 0) progress = advance_lane(S, li) || progress;
+        if (S->lanes[li].members > 0) progress = advance_lane(S, li, ref_cost) || progress;
     return progress;
 }
 
@@ -400,6 +434,7 @@ icwf_status icwf_server_submit(icwf_server *S, const icwf_config *cfg, const dou
     rq->cfg = *cfg;
     rq->n_steps = n_steps;
     rq->ws = ws;
+    rq->cost = step_cost_ms(*cfg);
     rq->r0.assign(r0, r0 + N);
     rq->R0.assign(R0, R0 + N);
     rq->psi1.assign(psi1_0, psi1_0 + 2 * N * nr);

@@ -95,8 +95,10 @@ Bufs carve(const icwf_config &c, char *base, size_t *total) {
     {
         // explicit inverses for the RK4 stages (see use_sinv)
         const size_t nn = icwf::use_sinv((int)Np, c.precision, c.solver) ? Np * Np : 1;
-        for (double2 **m : {&b.Xinv[0], &b.Xinv[1], &b.Tinv[0], &b.Tinv[1], &b.Sinv[0], &b.Sinv[1], &b.Sinvmid})
+        for (double2 **m : {&b.Finv[0], &b.Finv[1], &b.Finvmid, &b.Hinv[0], &b.Hinv[1], &b.Hinvmid, &b.Tinv[0],
+                            &b.Tinv[1]})
             *m = L.take<double2>(nn);
+        b.zvec = L.take<double2>(nn > 1 ? Np : 1);
     }
     b.chol_diag = L.take<double2>(2 * icwf::kCholNb * icwf::kCholNb);
     b.xsol = L.take<double2>(Np);
@@ -323,8 +325,11 @@ void enqueue_step(icwf_sim *s, const Dims &d, int parity, hipStream_t st, hipStr
     if (ss != st) single_species();
     timed(s, "cholesky", side, [&] {
         icwf::launch_assemble(d, b, parity, icwf::kAssembleS, side);
-        icwf::launch_cholesky(d, b, b.Lmid, b.L[1 - parity], b.Linvmid, b.Linv[1 - parity], 2, side,
-                              d.sinv ? b.Sinvmid : nullptr, b.Sinv[1 - parity]);
+        if (d.sinv)
+            icwf::launch_cholesky(d, b, b.Lmid, b.L[1 - parity], b.Linvmid, b.Linv[1 - parity], 2, side, b.Finvmid,
+                                  b.Finv[1 - parity], b.Hinvmid, b.Hinv[1 - parity]);
+        else
+            icwf::launch_cholesky(d, b, b.Lmid, b.L[1 - parity], b.Linvmid, b.Linv[1 - parity], 2, side);
     });
     if (fork) (void)hipEventRecord(s->ev_join, side);
     timed(s, "wc_contract", st, [&] { icwf::launch_wc(d, b, st); });
@@ -613,8 +618,10 @@ icwf_status icwf_create(const icwf_config *cfg, const double *r0, const double *
     icwf::launch_single_species(d, b, false, st);
     icwf::launch_wc(d, b, st);
     icwf::launch_assemble(d, b, 0, icwf::kAssembleInitial, st);
-    icwf::launch_cholesky(d, b, b.L[0], b.L[0], b.Linv[0], b.Linv[0], 1, st, d.sinv ? b.Sinv[0] : nullptr,
-                          nullptr);
+    if (d.sinv)
+        icwf::launch_cholesky(d, b, b.L[0], b.L[0], b.Linv[0], b.Linv[0], 1, st, b.Finv[0], nullptr, b.Hinv[0], nullptr);
+    else
+        icwf::launch_cholesky(d, b, b.L[0], b.L[0], b.Linv[0], b.Linv[0], 1, st);
     if (!C0) icwf::launch_solve_initial(d, b, 0, b.Cstage, st);
     CREATE_HIP(hipGetLastError());
     const icwf_status ds = device_status(s);

@@ -79,10 +79,10 @@ struct Bufs {
     double2 *Kminus, *Kmid;               // K(psi_k+1, x_k) and the midpoint K
     double2 *L[2], *Lmid;                 // Cholesky factors of S + eps I (lower)
     double2 *Linv[2], *Linvmid;           // [Np][64] inverses of their 64 x 64 diagonal blocks
-    double2 *Xinv[2];                     // [Np][Np] inverses of the two factors in flight (lower;
-                                          // zero above the diagonal; sinv only)
+    double2 *Finv[2], *Finvmid;           // [Np][Np] L^-1 of L[0], L[1], Lmid (lower part; sinv only)
+    double2 *Hinv[2], *Hinvmid;           // [Np][Np] L^-H, the conjugate transposes (upper part; sinv only)
     double2 *Tinv[2];                     // [Np][Np] scratch of the block inversion (sinv only)
-    double2 *Sinv[2], *Sinvmid;           // [Np][Np] (S + eps I)^-1 with L, Lmid (sinv only)
+    double2 *zvec;                        // [Np] L^-1 v of an RK stage (sinv only)
     double2 *chol_diag;                   // [2][64][64] factored diagonal blocks in flight
     double2 *xsol;                        // [Np] back-substitution result of an RK stage
     int32_t *solve_sync;                  // [130] block flags and tickets of the stage solves
@@ -183,7 +183,8 @@ void launch_assemble(const Dims &d, const Bufs &b, int parity, AssemblePart part
 // inverses of their 64 x 64 diagonal blocks into X0, X1 ([Np][64]).  With
 // S0 non-null (d.sinv), also (L L^H)^-1 of each factor into S0, S1 ([Np][Np]).
 void launch_cholesky(const Dims &d, const Bufs &b, double2 *A0, double2 *A1, double2 *X0, double2 *X1, int count,
-                     hipStream_t s, double2 *S0 = nullptr, double2 *S1 = nullptr);
+                     hipStream_t s, double2 *F0 = nullptr, double2 *F1 = nullptr, double2 *H0 = nullptr,
+                     double2 *H1 = nullptr);
 
 // One RK4 step of Eq. 8 with the factors / matrices of the given parity.
 void launch_rk4(const Dims &d, const Bufs &b, int parity, hipStream_t s);

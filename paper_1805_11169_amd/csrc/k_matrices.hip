@@ -235,16 +235,51 @@ __device__ inline void triangle_tile(int t, int *tb, int *ta) {
 // MFMA rows are a, columns are j, k is i; lane l supplies A = P1(b, a0 + l%16,
 // i) and B = W_c(i, j0 + l%16) with i in the quarter l/16 of the current i
 // chunk.  Each (j tile, i chunk) step stages the 32 psi1 rows of the tile and
-// the W_c chunk in LDS (two buffers): the coalesced global loads of step s + 1
-// are in flight while the matrix cores work on step s.  The j-sums of the
-// epilogue go to LDS once per j tile.
+// the W_c chunk in LDS (two buffers): the loads of step s + 1 are in flight
+// while the matrix cores work on step s.  The j-sums of the epilogue go to
+// LDS once per j tile.
+//
+// FP64 stages straight from global memory into LDS (16 bytes per lane and
+// load; no staging registers, four times fewer load instructions than 4-byte
+// loads).  A load fills 64 consecutive 16-byte slots of a padded buffer:
+// psi1 rows of KC + 1 slots, W_c rows of 17 slots (16 pairs of doubles and
+// a pad pair), so that the operand reads stay free of bank conflicts; a lane
+// whose slot is padding, or past the tile, loads an in-bounds entry that is
+// never read.  FP32 stages through registers.
 template <typename T>
 struct WcChunk {
+    static constexpr bool DIRECT = sizeof(T) == 8;
     static constexpr int KC = sizeof(T) == 8 ? 32 : 64;   // i per chunk (LDS budget: 2 blocks / CU)
     static constexpr int LDA = KC + 1;                    // padded psi1 row (complex entries)
-    static constexpr int LDW = 32 + 1;                    // padded W_c chunk row
-    static constexpr int PER = KC / 8;                    // elements each thread stages per array
+    static constexpr int LDW = DIRECT ? 34 : 33;          // padded W_c chunk row
+    static constexpr int PER = KC / 8;                    // elements each thread stages per array (FP32)
+    // direct staging: 16-byte slots per buffer and loads of 64 slots
+    static constexpr int ASLOTS = 32 * LDA;
+    static constexpr int ALOADS = (ASLOTS + 63) / 64;
+    static constexpr int AROWS = (64 * ALOADS + LDA - 1) / LDA;   // rows the buffer holds
+    static constexpr int WPAIRS = LDW / 2;
+    static constexpr int WLOADS = (KC * WPAIRS + 63) / 64;
+    static constexpr int WROWS = DIRECT ? (128 * WLOADS + LDW - 1) / LDW : KC;
 };
+
+typedef __attribute__((address_space(3))) void lds_void;
+
+// Sum over the 16 lanes of a row of a double held by each lane (DPP
+// rotations within the row); every lane of the row ends with the sum, lane
+// 16 r in a fixed order.
+template <int CTRL>
+__device__ inline double dpp_rot(double x) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+__device__ inline double row16_sum(double x) {
+    x += dpp_rot<0x128>(x);   // row_ror:8
+    x += dpp_rot<0x124>(x);   // row_ror:4
+    x += dpp_rot<0x122>(x);   // row_ror:2
+    x += dpp_rot<0x121>(x);   // row_ror:1
+    return x;
+}
 
 template <typename T, bool BATCHED>
 __global__ void __launch_bounds__(256, 2) k_wc(const typename WcTraits<T>::cplx *__restrict__ psi1,
@@ -266,9 +301,12 @@ __global__ void __launch_bounds__(256, 2) k_wc(const typename WcTraits<T>::cplx 
     typedef typename WcTraits<T>::cplx C2;
     typedef WcChunk<T> CK;
     constexpr int KC = CK::KC, LDA = CK::LDA, LDW = CK::LDW, PER = CK::PER, QS = KC / 4;
+    constexpr int AROWS = CK::DIRECT ? CK::AROWS : 32, WROWS = CK::WROWS;
     if (flags[kFlagHalt]) return;
-    __shared__ C2 sA[2][32][LDA];      // rows 0..15: a rows, 16..31: b rows of the tile
-    __shared__ T sW[2][KC][LDW];
+    // two staging buffers as separate arrays: the compiler can then tell the
+    // reads of one from the direct loads into the other
+    __shared__ __align__(16) C2 sA0[AROWS][LDA], sA1[AROWS][LDA];   // rows 0..15: a rows, 16..31: b rows
+    __shared__ __align__(16) T sW0[WROWS][LDW], sW1[WROWS][LDW];
     __shared__ double2 wl[4][4][16];   // [wave][b][a] block partial of Wc
     __shared__ int s_tile, s_done;
     // persistent: the work-group takes upper-triangle tiles from a queue until
@@ -304,38 +342,78 @@ __global__ void __launch_bounds__(256, 2) k_wc(const typename WcTraits<T>::cplx 
 
         const int nchunk = nr / KC, ntj = half < 0 ? nR / 32 : nR / 32 / nparts, nsteps = nchunk * ntj;
         const int jt0 = half > 0 ? half * ntj : 0;   // first j tile of this unit
-        // staging registers for one (j tile, i chunk) step
-        C2 ra[PER];
-        T rw[PER];
-        auto fetch = [&](int step) {
-            const int jl = step / nchunk, ch = step - jl * nchunk, jt = jt0 + jl;
-            const int i0 = ch * KC, j0 = jt * 32;
+        typedef C2 ATile[AROWS][LDA];
+        typedef T WTile[WROWS][LDW];
+        // tile row rr of the staging buffers: a rows first, then b rows
+        auto tile_row = [&](int rr) { return rr < 16 ? a_base + rr : b_tile + rr - 16; };
+        // direct staging of one buffer of 32 rows x 32 complex entries
+        // (row stride 33 slots) from the tile's rows of `src` (stride `ld`
+        // entries), columns c0 .. c0 + 31
+        auto stage_rows = [&](const double2 *src, int ld, int c0, double2 *dst) __attribute__((always_inline)) {
     #pragma unroll
-            for (int m = 0; m < PER; ++m) {
-                const int e = t + 256 * m;
-                const int rr = e / KC, cc = e - rr * KC;
-                const int grow = rr < 16 ? a_base + rr : b_tile + rr - 16;
-                ra[m] = psi1[(size_t)grow * nr + i0 + cc];
-                const int ii = e >> 5, jj = e & 31;
-                rw[m] = wtab[(size_t)(i0 + ii) * nR + j0 + jj];
+            for (int m = 0; m < (CK::ALOADS + 3) / 4; ++m) {
+                const int blk = 4 * m + wave;
+                if (blk < CK::ALOADS) {
+                    const int slot = 64 * blk + lane;
+                    int rr = slot / 33, cc = slot - 33 * rr;
+                    if (rr >= 32) rr = 31;
+                    if (cc >= 32) cc = 0;
+                    const uint32_t off = (uint32_t)(tile_row(rr) * ld + c0 + cc);
+                    __builtin_amdgcn_global_load_lds(reinterpret_cast<const float *>(src) + 4u * off,
+                                                     (lds_void *)(dst + 64 * blk), 16, 0, 0);
+                }
             }
         };
-        auto stash = [&](int buf) {
+        // staging registers for one (j tile, i chunk) step (FP32)
+        C2 ra[PER];
+        T rw[PER];
+        auto fetch = [&](int step, ATile &A, WTile &W) __attribute__((always_inline)) {
+            const int jl = step / nchunk, ch = step - jl * nchunk, jt = jt0 + jl;
+            const int i0 = ch * KC, j0 = jt * 32;
+            if constexpr (CK::DIRECT) {
+                stage_rows(reinterpret_cast<const double2 *>(psi1), nr, i0, reinterpret_cast<double2 *>(&A[0][0]));
     #pragma unroll
-            for (int m = 0; m < PER; ++m) {
-                const int e = t + 256 * m;
-                const int rr = e / KC, cc = e - rr * KC;
-                sA[buf][rr][cc] = ra[m];
-                sW[buf][e >> 5][e & 31] = rw[m];
+                for (int m = 0; m < (CK::WLOADS + 3) / 4; ++m) {
+                    const int blk = 4 * m + wave;
+                    if (blk < CK::WLOADS) {
+                        const int slot = 64 * blk + lane;
+                        int ii = slot / CK::WPAIRS, pr = slot - CK::WPAIRS * ii;
+                        if (ii >= KC) ii = KC - 1;
+                        if (pr >= 16) pr = 0;
+                        const uint32_t off = (uint32_t)((i0 + ii) * nR + j0 + 2 * pr);
+                        __builtin_amdgcn_global_load_lds(reinterpret_cast<const float *>(wtab) + 2u * off,
+                                                         (lds_void *)(&W[0][0] + 128 * blk), 16, 0, 0);
+                    }
+                }
+            } else {
+    #pragma unroll
+                for (int m = 0; m < PER; ++m) {
+                    const int e = t + 256 * m;
+                    const int rr = e / KC, cc = e - rr * KC;
+                    ra[m] = psi1[(size_t)tile_row(rr) * nr + i0 + cc];
+                    const int ii = e >> 5, jj = e & 31;
+                    rw[m] = wtab[(size_t)(i0 + ii) * nR + j0 + jj];
+                }
+            }
+        };
+        auto stash = [&](ATile &A, WTile &W) __attribute__((always_inline)) {
+            if constexpr (CK::DIRECT) {
+                __builtin_amdgcn_s_waitcnt(0x0f70);   // vmcnt(0): the direct loads have landed
+            } else {
+    #pragma unroll
+                for (int m = 0; m < PER; ++m) {
+                    const int e = t + 256 * m;
+                    const int rr = e / KC, cc = e - rr * KC;
+                    A[rr][cc] = ra[m];
+                    W[e >> 5][e & 31] = rw[m];
+                }
             }
         };
 
         acc4 acc[4][2][2];   // [b][re/im][j fragment]
-        fetch(0);
-        stash(0);
-        __syncthreads();
-        for (int step = 0; step < nsteps; ++step) {
-            const int buf = step & 1;
+        // one (j tile, i chunk) step on the buffers (A, W); the next step's
+        // operands are staged into (An, Wn) meanwhile
+        auto body = [&](int step, ATile &A, WTile &W, ATile &An, WTile &Wn) __attribute__((always_inline)) {
             const int jl = step / nchunk, ch = step - jl * nchunk, jt = jt0 + jl;
             if (ch == 0) {
     #pragma unroll
@@ -345,34 +423,56 @@ __global__ void __launch_bounds__(256, 2) k_wc(const typename WcTraits<T>::cplx 
     #pragma unroll
                         for (int jf = 0; jf < 2; ++jf) acc[bb][c][jf] = acc4{0, 0, 0, 0};
             }
-            if (step + 1 < nsteps) fetch(step + 1);
-    #pragma unroll 4
-            for (int s = 0; s < QS; ++s) {
+            if (step + 1 < nsteps) fetch(step + 1, An, Wn);
+            // operands of i-quad s + 1 are read from LDS while the matrix
+            // cores work on quad s
+            C2 xa, xb[4];
+            T w0, w1;
+            auto operands = [&](int s, C2 &oa, C2 (&ob)[4], T &o0, T &o1) __attribute__((always_inline)) {
                 const int col = quarter * QS + s;
-                const C2 xa = sA[buf][row][col];
-                const T w0 = sW[buf][col][row];
-                const T w1 = sW[buf][col][row + 16];
+                oa = A[row][col];
+                o0 = W[col][row];
+                o1 = W[col][row + 16];
+    #pragma unroll
+                for (int bb = 0; bb < 4; ++bb) ob[bb] = A[16 + 4 * wave + bb][col];
+            };
+            operands(0, xa, xb, w0, w1);
+    #pragma unroll
+            for (int s = 0; s < QS; ++s) {
+                C2 na, nb[4];
+                T n0, n1;
+                if (s + 1 < QS) operands(s + 1, na, nb, n0, n1);
     #pragma unroll
                 for (int bb = 0; bb < 4; ++bb) {
-                    const C2 p = cmulc(sA[buf][16 + 4 * wave + bb][col], xa);   // conj(psi1^b_i) psi1^a_i
+                    const C2 p = cmulc(xb[bb], xa);   // conj(psi1^b_i) psi1^a_i
                     const T pr = (T)p.x, pi = (T)p.y;
                     acc[bb][0][0] = mfma(pr, w0, acc[bb][0][0]);
                     acc[bb][1][0] = mfma(pi, w0, acc[bb][1][0]);
                     acc[bb][0][1] = mfma(pr, w1, acc[bb][0][1]);
                     acc[bb][1][1] = mfma(pi, w1, acc[bb][1][1]);
                 }
+                if (s + 1 < QS) {
+                    xa = na;
+                    w0 = n0;
+                    w1 = n1;
+    #pragma unroll
+                    for (int bb = 0; bb < 4; ++bb) xb[bb] = nb[bb];
+                }
             }
-            if (step + 1 < nsteps) stash(buf ^ 1);
+            // keep the stores (or the wait) for the next step's operands after
+            // the matrix products
+            __builtin_amdgcn_sched_barrier(0);
+            if (step + 1 < nsteps) stash(An, Wn);
             if (ch == nchunk - 1) {
                 // epilogue: lane holds T(b, a = a_base + mfma_row(T, lane, v), j = j0 + 16 jf + row);
                 // multiply by P2 = conj(psi2^b_j) psi2^a_j and sum over the 16 j of the fragment
                 const int j0 = jt * 32;
+                auto p2 = [&](int rr, int jj) { return psi2[(size_t)tile_row(rr) * nR + j0 + jj]; };
                 double2 p2a[2][4];
     #pragma unroll
                 for (int jf = 0; jf < 2; ++jf)
     #pragma unroll
-                    for (int v = 0; v < 4; ++v)
-                        p2a[jf][v] = psi2[(size_t)(a_base + mfma_row(T(0), lane, v)) * nR + j0 + 16 * jf + row];
+                    for (int v = 0; v < 4; ++v) p2a[jf][v] = p2(mfma_row(T(0), lane, v), 16 * jf + row);
                 // one b at a time keeps the live registers low
     #pragma unroll
                 for (int bb = 0; bb < 4; ++bb) {
@@ -381,7 +481,7 @@ __global__ void __launch_bounds__(256, 2) k_wc(const typename WcTraits<T>::cplx 
                     for (int v = 0; v < 4; ++v) ws[v] = make_double2(0, 0);
     #pragma unroll
                     for (int jf = 0; jf < 2; ++jf) {
-                        const double2 p2b = psi2[(size_t)(b_base + bb) * nR + j0 + 16 * jf + row];
+                        const double2 p2b = p2(16 + 4 * wave + bb, 16 * jf + row);
     #pragma unroll
                         for (int v = 0; v < 4; ++v) {
                             const double2 P2 = cmulc(p2b, p2a[jf][v]);
@@ -391,12 +491,7 @@ __global__ void __launch_bounds__(256, 2) k_wc(const typename WcTraits<T>::cplx 
                     }
     #pragma unroll
                     for (int v = 0; v < 4; ++v) {
-                        double2 x = ws[v];
-    #pragma unroll
-                        for (int off = 8; off > 0; off >>= 1) {
-                            x.x += __shfl_xor(x.x, off, 16);
-                            x.y += __shfl_xor(x.y, off, 16);
-                        }
+                        const double2 x = make_double2(row16_sum(ws[v].x), row16_sum(ws[v].y));
                         if (row == 0) {
                             double2 &dst = wl[wave][bb][mfma_row(T(0), lane, v)];
                             dst = cadd(dst, x);
@@ -405,6 +500,22 @@ __global__ void __launch_bounds__(256, 2) k_wc(const typename WcTraits<T>::cplx 
                 }
             }
             __syncthreads();
+        };
+        fetch(0, sA0, sW0);
+        stash(sA0, sW0);
+        __syncthreads();
+        if constexpr (CK::DIRECT) {
+            // the buffers by name in each half of the loop (the reads of one
+            // need not wait for the direct loads into the other)
+            for (int step = 0; step < nsteps; step += 2) {
+                body(step, sA0, sW0, sA1, sW1);
+                if (step + 1 < nsteps) body(step + 1, sA1, sW1, sA0, sW0);
+            }
+        } else {
+            for (int step = 0; step < nsteps; ++step) {
+                const bool odd = step & 1;
+                body(step, odd ? sA1 : sA0, odd ? sW1 : sW0, odd ? sA0 : sA1, odd ? sW0 : sW1);
+            }
         }
         // write the 4 x 16 partials of this wave
         const int bb = lane >> 4, a = lane & 15;

@@ -435,16 +435,12 @@ __global__ void __launch_bounds__(256) k_tri_inv(const double2 *__restrict__ A0,
     }
 }
 
-// ------------------------------------------------------------------ explicit inverse of L L^H
-// Batched complex GEMM on 64 x 64 output tiles, O = alpha op(A) B with
-// op(A)[i][k] = A[i][k], or conj(A[k][i]) (trans_a); 4 waves per tile, each
-// on a 32 x 32 quarter as 2 x 2 MFMA fragments (rows i, columns j, reduction
-// k), 16-wide k chunks of op(A) and B staged through double-buffered LDS.
-// Batch entry z: factor f = z / npairs, pair p = z % npairs, operands at
-// base[f] + p stride.  herm: the output is op(A) B with A = B lower
-// triangular (X^H X): only tiles with j0 >= i0, the reduction from k = j0
-// (conj(X[k][i]) X[k][j] vanishes below), each off-diagonal tile mirrored as
-// its conjugate transpose.
+// ------------------------------------------------------------------ explicit inverse of L
+// Batched complex GEMM on 64 x 64 output tiles, O = alpha A B; 4 waves per
+// tile, each on a 32 x 32 quarter as 2 x 2 MFMA fragments (rows i, columns j,
+// reduction k), 16-wide k chunks of A and B staged through double-buffered
+// LDS.  Batch entry z: factor f = z / npairs, pair p = z % npairs, operands
+// at base[f] + p stride.
 struct GemmBatch {
     const double2 *A[2], *B[2];
     double2 *O[2];
@@ -453,34 +449,22 @@ struct GemmBatch {
     int M, N, K;           // output rows and columns, reduction length (multiples of 64)
     int npairs;
     double alpha;
-    int trans_a, herm;
-    int lower_a, lower_b;  // op(A) / B lower triangular: the reduction skips the chunks that are zero
+    int lower_a, lower_b;  // A / B lower triangular: the reduction skips the chunks that are zero
 };
 
 constexpr int kGT = 64, kGKC = 16, kGLD = kGKC + 1;
 
 __global__ void __launch_bounds__(256, 2) k_cgemm(GemmBatch g, const int32_t *__restrict__ flags) {
     if (flags[kFlagHalt]) return;
-    __shared__ double2 sA[2][kGT][kGLD];   // [i][k] of op(A)
+    __shared__ double2 sA[2][kGT][kGLD];   // [i][k] of A
     __shared__ double2 sB[2][kGT][kGLD];   // [j][k] of B
     const int z = blockIdx.z, f = z / g.npairs, p = z - f * g.npairs;
     const size_t off = (size_t)p * g.stride;
     const double2 *__restrict__ A = (f ? g.A[1] : g.A[0]) + off;
     const double2 *__restrict__ B = (f ? g.B[1] : g.B[0]) + off;
     double2 *__restrict__ O = (f ? g.O[1] : g.O[0]) + off;
-    int ti, tj;
-    if (g.herm) {
-        const int t = blockIdx.x;   // lower-triangle tile (r >= c) -> i = c, j = r
-        int r = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
-        while ((r + 1) * (r + 2) / 2 <= t) ++r;
-        while (r * (r + 1) / 2 > t) --r;
-        ti = t - r * (r + 1) / 2;
-        tj = r;
-    } else {
-        const int nt = g.N / kGT;
-        ti = blockIdx.x / nt;
-        tj = blockIdx.x - ti * nt;
-    }
+    const int nt = g.N / kGT;
+    const int ti = blockIdx.x / nt, tj = blockIdx.x - ti * nt;
     const int i0 = ti * kGT, j0 = tj * kGT;
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int row = lane & 15, quarter = lane >> 4;
@@ -493,13 +477,13 @@ __global__ void __launch_bounds__(256, 2) k_cgemm(GemmBatch g, const int32_t *__
             re[a][c] = dbl4{0, 0, 0, 0};
             im[a][c] = dbl4{0, 0, 0, 0};
         }
-    // B lower triangular (or the X^H X of herm): B[k][j] = 0 for k < j, so the
-    // tile's columns j >= j0 need k >= j0; op(A) lower triangular: rows i < i0 + 64
-    // need k < i0 + 64.  Only exact zeros are skipped.
-    const int kbeg = (g.herm || g.lower_b) ? j0 : 0;
+    // B lower triangular: B[k][j] = 0 for k < j, so the tile's columns
+    // j >= j0 need k >= j0; A lower triangular: rows i < i0 + 64 need
+    // k < i0 + 64.  Only exact zeros are skipped.
+    const int kbeg = g.lower_b ? j0 : 0;
     const int kend = g.lower_a ? min(g.K, i0 + kGT) : g.K;
     const int nch = kend > kbeg ? (kend - kbeg) / kGKC : 0;
-    // staging: element e = t + 256 m (m < 4); op(A) as [i][k] (64 x 16), B as
+    // staging: element e = t + 256 m (m < 4); A as [i][k] (64 x 16), B as
     // [k][j] (16 x 64); held as plain doubles (an array of double2 would be
     // placed in scratch memory)
     double rax[4], ray[4], rbx[4], rby[4];
@@ -507,9 +491,7 @@ __global__ void __launch_bounds__(256, 2) k_cgemm(GemmBatch g, const int32_t *__
 #pragma unroll
         for (int m = 0; m < 4; ++m) {
             const int e = t + 256 * m;
-            double2 va;
-            if (g.trans_a) va = cconj(A[(size_t)(k0 + (e >> 6)) * g.lda + i0 + (e & 63)]);
-            else va = A[(size_t)(i0 + (e >> 4)) * g.lda + k0 + (e & 15)];
+            const double2 va = A[(size_t)(i0 + (e >> 4)) * g.lda + k0 + (e & 15)];
             const double2 vb = B[(size_t)(k0 + (e >> 6)) * g.ldb + j0 + (e & 63)];
             rax[m] = va.x;
             ray[m] = va.y;
@@ -521,8 +503,7 @@ __global__ void __launch_bounds__(256, 2) k_cgemm(GemmBatch g, const int32_t *__
 #pragma unroll
         for (int m = 0; m < 4; ++m) {
             const int e = t + 256 * m;
-            if (g.trans_a) sA[buf][e & 63][e >> 6] = make_double2(rax[m], ray[m]);
-            else sA[buf][e >> 4][e & 15] = make_double2(rax[m], ray[m]);
+            sA[buf][e >> 4][e & 15] = make_double2(rax[m], ray[m]);
             sB[buf][e & 63][e >> 6] = make_double2(rbx[m], rby[m]);
         }
     };
@@ -558,7 +539,6 @@ __global__ void __launch_bounds__(256, 2) k_cgemm(GemmBatch g, const int32_t *__
         if (more) stash(buf ^ 1);
         __syncthreads();
     }
-    const bool mirror = g.herm && ti != tj;
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -569,7 +549,6 @@ __global__ void __launch_bounds__(256, 2) k_cgemm(GemmBatch g, const int32_t *__
                 const int j = j0 + wj + 16 * c + row;
                 const double2 o = make_double2(g.alpha * re[a][c][v], g.alpha * im[a][c][v]);
                 O[(size_t)i * g.ldo + j] = o;
-                if (mirror) O[(size_t)j * g.ldo + i] = cconj(o);
             }
 }
 
@@ -603,8 +582,29 @@ __device__ inline void publish_block(int32_t *flag) {
 
 
 // y = M v, one wave per row, four rows per work-group.
+// Parts of a matrix a matrix-vector product reads: all of it, the lower
+// triangle with the diagonal, or the upper triangle with the diagonal.
+enum MatPart : int { kPartAll = 0, kPartLower = 1, kPartUpper = 2 };
+
+// Row rowi of M times v over the columns of the part, summed by one wave in a
+// fixed order (every lane ends with the sum).
+__device__ inline double2 row_dot(const double2 *__restrict__ m, const double2 *__restrict__ v, int rowi, int Np,
+                                  int part) {
+    const int lane = threadIdx.x & 63;
+    const int lo = part == kPartUpper ? (rowi & ~63) : 0, hi = part == kPartLower ? rowi + 1 : Np;
+    double2 acc = make_double2(0, 0);
+    for (int c = lo + lane; c < hi; c += 64)
+        if (part != kPartUpper || c >= rowi) acc = cadd(acc, cmul(m[c], v[c]));
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        acc.x += __shfl_xor(acc.x, off);
+        acc.y += __shfl_xor(acc.y, off);
+    }
+    return acc;
+}
+
 __global__ void __launch_bounds__(256) k_matvec(const double2 *__restrict__ M, const double2 *__restrict__ v,
-                                                double2 *__restrict__ y, int Np,
+                                                double2 *__restrict__ y, int Np, int part,
                                                 const int32_t *__restrict__ flags, const long long *__restrict__ zoff) {
     const long long zo_ = batch_offset(zoff);
     M = zshift(M, zo_);
@@ -615,14 +615,7 @@ __global__ void __launch_bounds__(256) k_matvec(const double2 *__restrict__ M, c
     if (flags[kFlagHalt]) return;
     const int lane = threadIdx.x & 63;
     const int rowi = blockIdx.x * 4 + (threadIdx.x >> 6);
-    const double2 *m = M + (size_t)rowi * Np;
-    double2 acc = make_double2(0, 0);
-    for (int c = lane; c < Np; c += 64) acc = cadd(acc, cmul(m[c], v[c]));
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        acc.x += __shfl_xor(acc.x, off);
-        acc.y += __shfl_xor(acc.y, off);
-    }
+    const double2 acc = row_dot(M + (size_t)rowi * Np, v, rowi, Np, part);
     if (lane == 0) y[rowi] = acc;
 }
 
@@ -796,9 +789,10 @@ __global__ void __launch_bounds__(256) k_rk_bwd(const double2 *__restrict__ L, c
     publish_block(&sync[kSyncBwd + B]);
 }
 
-// Stages through the explicit inverse, with one step of iterative
-// refinement: x0 = A^-1 rhs (k_matvec), res = rhs - A x0 (k_rk_resid, A
-// formed from S as in the assembly), x = x0 + A^-1 res (k_rk_apply, then the
+// Stages through the explicit inverse of the factor, A^-1 = L^-H L^-1, with
+// one step of iterative refinement: x0 = L^-H (L^-1 rhs) (two triangular
+// k_matvec), res = rhs - A x0 (k_rk_resid, A formed from S as in the
+// assembly), x = x0 + L^-H (L^-1 res) (k_matvec, then k_rk_apply with the
 // stage update of the row).  The refinement brings the explicit inverse's
 // error, of the order of cond(A) times its rounding, back to that of a
 // solve with the factor.  One wave per row, four rows per work-group.
@@ -840,15 +834,15 @@ __global__ void __launch_bounds__(256) k_rk_resid(const double2 *__restrict__ Sa
     if (lane == 0) res[rowi] = csub(rhs[rowi], acc);
 }
 
-__global__ void __launch_bounds__(256) k_rk_apply(const double2 *__restrict__ Sinv, const double2 *__restrict__ res,
+__global__ void __launch_bounds__(256) k_rk_apply(const double2 *__restrict__ H, const double2 *__restrict__ z,
                                                   const double2 *__restrict__ x0, int Np, int stage, double dt, int N,
                                                   double2 *__restrict__ C, double2 *__restrict__ Cacc,
                                                   double2 *__restrict__ Cstage, double *__restrict__ r,
                                                   double *__restrict__ R, const double *__restrict__ r_new,
                                                   const double *__restrict__ R_new, int32_t *__restrict__ flags, const long long *__restrict__ zoff) {
     const long long zo_ = batch_offset(zoff);
-    Sinv = zshift(Sinv, zo_);
-    res = zshift(res, zo_);
+    H = zshift(H, zo_);
+    z = zshift(z, zo_);
     x0 = zshift(x0, zo_);
     C = zshift(C, zo_);
     Cacc = zshift(Cacc, zo_);
@@ -862,15 +856,28 @@ __global__ void __launch_bounds__(256) k_rk_apply(const double2 *__restrict__ Si
     if (flags[kFlagHalt]) return;
     const int lane = threadIdx.x & 63;
     const int rowi = blockIdx.x * 4 + (threadIdx.x >> 6);
-    const double2 *m = Sinv + (size_t)rowi * Np;
-    double2 acc = make_double2(0, 0);
-    for (int c = lane; c < Np; c += 64) acc = cadd(acc, cmul(m[c], res[c]));
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        acc.x += __shfl_xor(acc.x, off);
-        acc.y += __shfl_xor(acc.y, off);
-    }
+    const double2 acc = row_dot(H + (size_t)rowi * Np, z, rowi, Np, kPartUpper);   // (L^-H z)_rowi
     if (lane == 0) stage_update(rowi, cadd(x0[rowi], acc), stage, dt, N, C, Cacc, Cstage, r, R, r_new, R_new, flags);
+}
+
+// H = F^H over the lower part of F (F = L^-1): 32 x 32 tiles through LDS,
+// tile (bi, bj) of F with bi >= bj to tile (bj, bi) of H (the parts of F
+// above and of H below the diagonal are neither read nor written).
+__global__ void __launch_bounds__(256) k_conj_transpose(const double2 *__restrict__ F0, const double2 *__restrict__ F1,
+                                                        double2 *__restrict__ H0, double2 *__restrict__ H1, int Np,
+                                                        const int32_t *__restrict__ flags) {
+    if (flags[kFlagHalt]) return;
+    const int bi = blockIdx.x, bj = blockIdx.y;
+    if (bi < bj) return;
+    const double2 *F = blockIdx.z ? F1 : F0;
+    double2 *H = blockIdx.z ? H1 : H0;
+    __shared__ double2 tile[32][33];
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 8 rows per pass
+#pragma unroll
+    for (int r = ty; r < 32; r += 8) tile[r][tx] = F[(size_t)(32 * bi + r) * Np + 32 * bj + tx];
+    __syncthreads();
+#pragma unroll
+    for (int r = ty; r < 32; r += 8) H[(size_t)(32 * bj + r) * Np + 32 * bi + tx] = cconj(tile[tx][r]);
 }
 
 __global__ void k_set_table(long long *__restrict__ tab, BatchTable t, int n) {
@@ -899,7 +906,7 @@ void launch_assemble(const Dims &d, const Bufs &b, int parity, AssemblePart part
 }
 
 void launch_cholesky(const Dims &d, const Bufs &b, double2 *A0, double2 *A1, double2 *X0, double2 *X1, int count,
-                     hipStream_t s, double2 *S0, double2 *S1) {
+                     hipStream_t s, double2 *F0, double2 *F1, double2 *H0, double2 *H1) {
     const int Np = padded(d.N);
     for (int kb = 0; kb < Np; kb += NB) {
         const int below = Np - kb - NB;
@@ -914,10 +921,10 @@ void launch_cholesky(const Dims &d, const Bufs &b, double2 *A0, double2 *A1, dou
     }
     hipLaunchKernelGGL(k_chol_flush, dim3(1, count, d.batch), dim3(256), 0, s, A0, A1, Np, Np - NB, b.chol_diag,
                        b.flags, d.zoff);
-    double2 *F0 = S0 ? b.Xinv[0] : nullptr, *F1 = S0 ? b.Xinv[1] : nullptr;
     hipLaunchKernelGGL(k_tri_inv, dim3(Np / NB, count, d.batch), dim3(256), 0, s, A0, A1, X0, X1, F0, F1, Np, b.flags,
                        d.zoff);
-    if (!S0) return;
+    if (!F0) return;
+    double2 *Fs[2] = {F0, F1 ? F1 : F0};
     // X = L^-1 by block recursion, [[A, 0], [C, D]]^-1 = [[A', 0], [-D' C A', D']],
     // from the 64 x 64 diagonal inverses up: at block size h, the Np / (2 h) pairs
     // of every factor take T = C A' and then -D' T (X's upper triangle stays zero)
@@ -931,7 +938,7 @@ void launch_cholesky(const Dims &d, const Bufs &b, double2 *A0, double2 *A1, dou
         const dim3 grid((h / kGT) * (h / kGT), 1, count * g.npairs);
         for (int f = 0; f < 2; ++f) {                      // T = C A'
             g.A[f] = L2[f] + (size_t)h * Np;
-            g.B[f] = b.Xinv[f];
+            g.B[f] = Fs[f];
             g.O[f] = b.Tinv[f] + (size_t)h * Np;
         }
         g.alpha = 1.0;
@@ -939,30 +946,18 @@ void launch_cholesky(const Dims &d, const Bufs &b, double2 *A0, double2 *A1, dou
         g.lower_b = 1;                                     // A' lower triangular
         hipLaunchKernelGGL(k_cgemm, grid, dim3(256), 0, s, g, b.flags);
         for (int f = 0; f < 2; ++f) {                      // X_DA = -D' T
-            g.A[f] = b.Xinv[f] + (size_t)h * Np + h;
+            g.A[f] = Fs[f] + (size_t)h * Np + h;
             g.B[f] = b.Tinv[f] + (size_t)h * Np;
-            g.O[f] = b.Xinv[f] + (size_t)h * Np;
+            g.O[f] = Fs[f] + (size_t)h * Np;
         }
         g.alpha = -1.0;
         g.lower_a = 1;                                     // D' lower triangular
         g.lower_b = 0;
         hipLaunchKernelGGL(k_cgemm, grid, dim3(256), 0, s, g, b.flags);
     }
-    // (L L^H)^-1 = X^H X: upper tiles, mirrored
-    GemmBatch g{};
-    g.lda = g.ldb = g.ldo = Np;
-    g.M = g.N = g.K = Np;
-    g.npairs = 1;
-    g.alpha = 1.0;
-    g.trans_a = 1;
-    g.herm = 1;
-    double2 *S2[2] = {S0, S1};
-    for (int f = 0; f < 2; ++f) {
-        g.A[f] = g.B[f] = b.Xinv[f];
-        g.O[f] = S2[f];
-    }
-    const int T = Np / kGT;
-    hipLaunchKernelGGL(k_cgemm, dim3(T * (T + 1) / 2, 1, count), dim3(256), 0, s, g, b.flags);
+    // L^-H for the stage solves
+    hipLaunchKernelGGL(k_conj_transpose, dim3(Np / 32, Np / 32, count), dim3(256), 0, s, F0, F1 ? F1 : F0, H0,
+                       H1 ? H1 : H0, Np, b.flags);
 }
 
 void launch_rk4(const Dims &d, const Bufs &b, int parity, hipStream_t s) {
@@ -971,22 +966,27 @@ void launch_rk4(const Dims &d, const Bufs &b, int parity, hipStream_t s) {
     const double2 *Ks[4] = {b.Kmat[cur], b.Kmid, b.Kmid, b.Kminus};
     const double2 *Ls[4] = {b.L[cur], b.Lmid, b.Lmid, b.L[nxt]};
     const double2 *Xs[4] = {b.Linv[cur], b.Linvmid, b.Linvmid, b.Linv[nxt]};
-    const double2 *Ss[4] = {b.Sinv[cur], b.Sinvmid, b.Sinvmid, b.Sinv[nxt]};
+    const double2 *Fs[4] = {b.Finv[cur], b.Finvmid, b.Finvmid, b.Finv[nxt]};
+    const double2 *Hs[4] = {b.Hinv[cur], b.Hinvmid, b.Hinvmid, b.Hinv[nxt]};
     // with Heun trajectories the last stage leaves x_k in place for the corrector
     double *cr = d.traj == 1 ? nullptr : b.r, *cR = d.traj == 1 ? nullptr : b.R;
     for (int st = 1; st <= 4; ++st) {
         const double2 *v = (st == 1) ? b.C : b.Cstage;
-        hipLaunchKernelGGL(k_matvec, dim3(Np / 4, 1, d.batch), dim3(256), 0, s, Ks[st - 1], v, b.rhs, Np, b.flags,
-                           d.zoff);
+        hipLaunchKernelGGL(k_matvec, dim3(Np / 4, 1, d.batch), dim3(256), 0, s, Ks[st - 1], v, b.rhs, Np,
+                           (int)kPartAll, b.flags, d.zoff);
         if (d.sinv) {
             // A of the stage: S_k + eps I, the midpoint average + eps I (stages 2, 3), S_k+1 + eps I
             const double2 *Sa = st == 4 ? b.Smat[nxt] : b.Smat[cur];
             const double2 *Sb = (st == 2 || st == 3) ? b.Smat[nxt] : nullptr;
-            hipLaunchKernelGGL(k_matvec, dim3(Np / 4, 1, d.batch), dim3(256), 0, s, Ss[st - 1], b.rhs, b.y, Np,
-                               b.flags, d.zoff);
+            hipLaunchKernelGGL(k_matvec, dim3(Np / 4, 1, d.batch), dim3(256), 0, s, Fs[st - 1], b.rhs, b.zvec, Np,
+                               (int)kPartLower, b.flags, d.zoff);
+            hipLaunchKernelGGL(k_matvec, dim3(Np / 4, 1, d.batch), dim3(256), 0, s, Hs[st - 1], b.zvec, b.y, Np,
+                               (int)kPartUpper, b.flags, d.zoff);
             hipLaunchKernelGGL(k_rk_resid, dim3(Np / 4, 1, d.batch), dim3(256), 0, s, Sa, Sb, d.eps, b.y, b.rhs, b.xsol,
                                Np, b.flags, d.zoff);
-            hipLaunchKernelGGL(k_rk_apply, dim3(Np / 4, 1, d.batch), dim3(256), 0, s, Ss[st - 1], b.xsol, b.y, Np, st,
+            hipLaunchKernelGGL(k_matvec, dim3(Np / 4, 1, d.batch), dim3(256), 0, s, Fs[st - 1], b.xsol, b.zvec, Np,
+                               (int)kPartLower, b.flags, d.zoff);
+            hipLaunchKernelGGL(k_rk_apply, dim3(Np / 4, 1, d.batch), dim3(256), 0, s, Hs[st - 1], b.zvec, b.y, Np, st,
                                d.dt, d.N, b.C, b.Cacc, b.Cstage, cr, cR, b.r_new, b.R_new, b.flags, d.zoff);
             continue;
         }

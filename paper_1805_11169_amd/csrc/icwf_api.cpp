@@ -47,8 +47,9 @@ Bufs carve(const icwf_config &c, char *base, size_t *total) {
     const size_t Np = icwf::padded(c.n_traj), nr = c.n_r, nR = c.n_R, nbo = c.n_bo;
     Bufs b{};
     b.flags = L.take<int32_t>(icwf::kNumFlags);
-    b.wc_queue = L.take<int32_t>(1 + icwf::wc_split_tiles((int)Np));
-    b.wc_part = L.take<double2>((size_t)icwf::wc_split_tiles((int)Np) * icwf::kWcParts * 256);
+    b.wc_queue = L.take<int32_t>(icwf::kWcQueues + icwf::wc_split_slots((int)Np));
+    b.wc_order = L.take<int32_t>((Np / 16) * (Np / 16 + 1) / 2);
+    b.wc_part = L.take<double2>((size_t)icwf::wc_split_slots((int)Np) * icwf::kWcParts * 256);
     b.scal = L.take<double>(8);
     b.psi1 = L.take<double2>(Np * nr);
     b.psi2 = L.take<double2>(Np * nR);
@@ -609,6 +610,8 @@ icwf_status icwf_create(const icwf_config *cfg, const double *r0, const double *
     if (nbo > 0)
         CREATE_HIP(hipMemcpyAsync(b.bo, bo_states, sizeof(double) * (size_t)nR * nbo * nr, hipMemcpyHostToDevice, st));
     CREATE_HIP(hipMemcpyAsync(b.mparams, &d.mp, sizeof(icwf::ModelParams), hipMemcpyHostToDevice, st));
+    const std::vector<int32_t> order = icwf::wc_tile_order(Np);
+    CREATE_HIP(hipMemcpyAsync(b.wc_order, order.data(), sizeof(int32_t) * order.size(), hipMemcpyHostToDevice, st));
     if (C0) CREATE_HIP(hipMemcpyAsync(b.C, C0, sizeof(double2) * N, hipMemcpyHostToDevice, st));
     else CREATE_HIP(hipMemcpyAsync(b.Cstage, b0, sizeof(double2) * N, hipMemcpyHostToDevice, st));
 

@@ -6,6 +6,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <vector>
+
 #include "../../include/icwf.h"
 #include "icwf_device.hpp"
 
@@ -48,6 +50,16 @@ inline int wc_split_tiles(int Np) {
     const int tiles = t * (t + 1) / 2;
     return tiles < kWcSplitMax ? tiles : kWcSplitMax;
 }
+// The contraction's tiles come from one queue per XCD (each XCD's L2 then
+// holds the psi1 rows of its own compact group of tiles); each queue splits
+// at most ceil(split tiles / queues) of its tiles.
+constexpr int kWcQueues = 8;
+inline int wc_split_per_queue(int nsplit) { return (nsplit + kWcQueues - 1) / kWcQueues; }
+inline int wc_split_slots(int Np) { return kWcQueues * wc_split_per_queue(wc_split_tiles(Np)); }
+// Order of the 16 x 16 pair tiles (triangle index ta (ta + 1) / 2 + tb,
+// tb <= ta) in which the queues hand them out: blocks of 8 x 8 tiles, so that
+// consecutive tiles share their rows.
+std::vector<int32_t> wc_tile_order(int Np);
 
 struct Bufs {
     double2 *psi1, *psi2;                 // [N][nr], [N][nR] CWFs (Eq. 7)
@@ -92,9 +104,11 @@ struct Bufs {
     double *obs_part;                     // [kRhoSlices][nR] partial sums of rho_R
     double *obs_out;                      // packed observables
     int32_t *flags;                       // kNumFlags status flags
-    int32_t *wc_queue;                    // [1 + wc_split_tiles(Np)] tile counter of the persistent two-body
-                                          // contraction, then the completion counters of its split tiles
-    double2 *wc_part;                     // [wc_split_tiles(Np)][kWcParts][256] partial sums of split tiles
+    int32_t *wc_queue;                    // [kWcQueues + wc_split_slots(Np)] unit counters of the persistent
+                                          // two-body contraction (one per XCD queue; the separable and rank-K
+                                          // passes use the first), then the completion counters of split tiles
+    int32_t *wc_order;                    // [Np/16 (Np/16 + 1) / 2] tile order of the queues (wc_tile_order)
+    double2 *wc_part;                     // [wc_split_slots(Np)][kWcParts][256] partial sums of split tiles
     double *scal;                         // small device scalars (min |Psi|, ...)
     ModelParams *mparams;                 // device copy of the model parameters
     long long *batch_tab;                 // [kMaxBatch] workspace offsets of a batch this simulation leads

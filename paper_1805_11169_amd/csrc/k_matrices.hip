@@ -286,14 +286,16 @@ __global__ void __launch_bounds__(256, 2) k_wc(const typename WcTraits<T>::cplx 
                                                const double2 *__restrict__ psi2,
                                                const T *__restrict__ wtab, int nr, int nR, double scale,
                                                double2 *__restrict__ Wc, int Np, int accumulate,
-                                               int ntiles, int nsplit, int nparts, int32_t *__restrict__ queue,
-                                               double2 *__restrict__ part, const int32_t *__restrict__ flags, const long long *__restrict__ zoff) {
+                                               int ntiles, int spq, int nparts, int32_t *__restrict__ queue,
+                                               const int32_t *__restrict__ order, double2 *__restrict__ part,
+                                               const int32_t *__restrict__ flags, const long long *__restrict__ zoff) {
     const long long zo_ = BATCHED ? batch_offset(zoff) : 0;
     psi1 = zshift(psi1, zo_);
     psi2 = zshift(psi2, zo_);
     wtab = zshift(wtab, zo_);
     Wc = zshift(Wc, zo_);
     queue = zshift(queue, zo_);
+    order = zshift(order, zo_);
     part = zshift(part, zo_);
     flags = zshift(flags, zo_);
 
@@ -308,28 +310,57 @@ __global__ void __launch_bounds__(256, 2) k_wc(const typename WcTraits<T>::cplx 
     __shared__ __align__(16) C2 sA0[AROWS][LDA], sA1[AROWS][LDA];   // rows 0..15: a rows, 16..31: b rows
     __shared__ __align__(16) T sW0[WROWS][LDW], sW1[WROWS][LDW];
     __shared__ double2 wl[4][4][16];   // [wave][b][a] block partial of Wc
-    __shared__ int s_tile, s_done;
-    // persistent: the work-group takes upper-triangle tiles from a queue until
+    __shared__ int s_unit, s_queue, s_done;
+    // persistent: the work-group takes upper-triangle tiles from queues until
     // none is left (fewer work-groups than CU slots leaves room for work on
-    // another stream).  The last nsplit tiles of the queue come as nparts
-    // units each, one per nparts-th of the j tiles, so that the final round
-    // ends with small pieces of work: each unit leaves its partial sum in
-    // `part`, and the unit that completes last adds them in part order
-    // (whatever the order of completion) and writes the tile.
-    const int nfull = ntiles - nsplit;
+    // another stream).  Queue q hands out the q-th eighth of the tile order
+    // (blocks of neighbouring tiles); a work-group takes from the queue of
+    // its own XCD first, then from the others.  The last spq tiles of each
+    // queue come as nparts units each, one per nparts-th of the j tiles, so
+    // that the final round ends with small pieces of work: each unit leaves
+    // its partial sum in `part`, and the unit that completes last adds them
+    // in part order (whatever the order of completion) and writes the tile.
+    auto queue_range = [&](int q, int *lo, int *nfull, int *nsp) {
+        *lo = (int)((long long)q * ntiles / kWcQueues);
+        const int n = (int)((long long)(q + 1) * ntiles / kWcQueues) - *lo;
+        *nsp = n < spq ? n : spq;
+        *nfull = n - *nsp;
+    };
+    // the XCD this work-group runs on (its queue; any value is correct)
+    const int xcd = __builtin_amdgcn_s_getreg(20 | (0 << 6) | (3 << 11)) & (kWcQueues - 1);   // HW_REG_XCC_ID
     for (;;) {
-        if (threadIdx.x == 0) s_tile = atomicAdd(queue, 1);
+        if (threadIdx.x == 0) {
+            int got = -1, gq = 0;
+            for (int o = 0; o < kWcQueues && got < 0; ++o) {
+                const int q = (xcd + o) & (kWcQueues - 1);
+                int lo, nf, ns;
+                queue_range(q, &lo, &nf, &ns);
+                const int units = nf + ns * nparts;
+                if (__hip_atomic_load(&queue[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= units) continue;
+                const int k = atomicAdd(&queue[q], 1);
+                if (k < units) {
+                    got = k;
+                    gq = q;
+                }
+            }
+            s_unit = got;
+            s_queue = gq;
+        }
         __syncthreads();
-        const int unit = s_tile;
+        const int unit = s_unit, q = s_queue;
         __syncthreads();
-        if (unit >= nfull + nsplit * nparts) break;
-        int tile = unit, half = -1;   // half: this unit's part of a split tile
+        if (unit < 0) break;
+        int lo, nfull, nsp;
+        queue_range(q, &lo, &nfull, &nsp);
+        int pos = lo + unit, half = -1, slot = 0;   // half: this unit's part of a split tile
         if (unit >= nfull) {
-            tile = nfull + (unit - nfull) / nparts;
-            half = (unit - nfull) - (tile - nfull) * nparts;
+            const int j = unit - nfull;
+            pos = lo + nfull + j / nparts;
+            half = j - (j / nparts) * nparts;
+            slot = q * spq + j / nparts;
         }
         int tb, ta;
-        triangle_tile(tile, &tb, &ta);
+        triangle_tile(order[pos], &tb, &ta);
 
         const int t = threadIdx.x;
         const int lane = t & 63, wave = t >> 6;
@@ -524,12 +555,11 @@ __global__ void __launch_bounds__(256, 2) k_wc(const typename WcTraits<T>::cplx 
             const double2 x = cscale(wl[wave][bb][a], scale);
             *dst = accumulate ? cadd(*dst, x) : x;
         } else {
-            const int slot = tile - nfull;
             double2 *pp = part + (size_t)slot * nparts * 256 + wave * 64 + lane;
             pp[256 * half] = wl[wave][bb][a];
             __threadfence();
             __syncthreads();
-            if (threadIdx.x == 0) s_done = atomicAdd(&queue[1 + slot], 1);
+            if (threadIdx.x == 0) s_done = atomicAdd(&queue[kWcQueues + slot], 1);
             __syncthreads();
             if (s_done == nparts - 1) {
                 __threadfence();
@@ -695,6 +725,18 @@ __global__ void __launch_bounds__(256, 2) k_wc_sep(const double2 *__restrict__ p
 
 }  // namespace
 
+std::vector<int32_t> wc_tile_order(int Np) {
+    const int T = Np / 16, S = 8, nS = (T + S - 1) / S;
+    std::vector<int32_t> ord;
+    ord.reserve((size_t)T * (T + 1) / 2);
+    for (int sb = 0; sb < nS; ++sb)
+        for (int sa = sb; sa < nS; ++sa)
+            for (int tb = sb * S; tb < std::min(T, sb * S + S); ++tb)
+                for (int ta = std::max(tb, sa * S); ta < std::min(T, sa * S + S); ++ta)
+                    ord.push_back(ta * (ta + 1) / 2 + tb);
+    return ord;
+}
+
 void launch_cond_kets(const Dims &d, const Bufs &b, hipStream_t s, bool next) {
     const int Np = padded(d.N);
     size_t tot = (size_t)Np * d.nr;
@@ -766,14 +808,15 @@ void launch_wc(const Dims &d, const Bufs &b, hipStream_t s) {
     const int grid = std::min(blocks, d.wc_grid);
     const int nparts = std::min(kWcParts, d.nR / 32);
     const int nsplit = nparts >= 2 ? std::min(grid, wc_split_tiles(Np)) : 0;
+    const int spq = wc_split_per_queue(nsplit);   // split tiles per queue
     if (d.prec == 1) {
         // mixed: FP32 matrix cores on the residual of the rank-K split, FP64 rank-K part added
         // (the FP32 pass only where the residual is above the table's rounding)
         if (d.fp32_residual) {
-            launch_fill_i32(b.wc_queue, 1 + nsplit, 0, s, d.batch, d.zoff);
+            launch_fill_i32(b.wc_queue, kWcQueues + kWcQueues * spq, 0, s, d.batch, d.zoff);
             hipLaunchKernelGGL((d.zoff ? k_wc<float, true> : k_wc<float, false>), dim3(grid, 1, d.batch), dim3(256), 0, s, b.psi1_f32, b.psi2, b.wc32, d.nr,
-                               d.nR, scale, b.Wc, Np, 0, blocks, nsplit, nparts, b.wc_queue, b.wc_part, b.flags,
-                               d.zoff);
+                               d.nR, scale, b.Wc, Np, 0, blocks, spq, nparts, b.wc_queue, b.wc_order, b.wc_part,
+                               b.flags, d.zoff);
         }
         if (d.lr_rank > 0) {
             launch_fill_i32(b.wc_queue, 1, 0, s, d.batch, d.zoff);
@@ -788,9 +831,10 @@ void launch_wc(const Dims &d, const Bufs &b, hipStream_t s) {
                            b.lr_u, b.lr_v, (d.lr_rank + 15) / 16 * 16, d.nr, d.nR, scale, b.Wc, Np, 0, blocks,
                            b.wc_queue, b.flags, d.zoff);
     } else {
-        launch_fill_i32(b.wc_queue, 1 + nsplit, 0, s, d.batch, d.zoff);
+        launch_fill_i32(b.wc_queue, kWcQueues + kWcQueues * spq, 0, s, d.batch, d.zoff);
         hipLaunchKernelGGL((d.zoff ? k_wc<double, true> : k_wc<double, false>), dim3(grid, 1, d.batch), dim3(256), 0, s, b.psi1, b.psi2, b.wc64, d.nr, d.nR,
-                           scale, b.Wc, Np, 0, blocks, nsplit, nparts, b.wc_queue, b.wc_part, b.flags, d.zoff);
+                           scale, b.Wc, Np, 0, blocks, spq, nparts, b.wc_queue, b.wc_order, b.wc_part, b.flags,
+                           d.zoff);
     }
 }
 

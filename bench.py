@@ -45,13 +45,14 @@ HBM_PEAK_GBS = 8000.0
 # any change the traffic is reported as null until measured again.
 TRAFFIC = {
     "sm_n1024": {
-        "sources_sha256_16": "4ca89a513f6dc5fd",
-        "fp64": 1308726052.9,      # k_wc<double>: fetch 629867.3 KiB x2, write 18353.0 KiB
-        "mixed": 541047281.1,       # k_wc<float> + k_wc_sep
-        "separable": 571406616.9,   # k_wc_sep (K = 29)
+        "sources_sha256_16": "da40efe242530393",
+        "fp64": 315649331.2,        # k_wc<double>: fetch 142940.1 KiB x2, write 22371.1 KiB
+        "mixed": 420417433.6,       # k_wc<float> + k_wc_sep: fetch 41343.3 + 149225.5 KiB x2, write 21027.3 + 8399.0 KiB
+        "separable": 601427763.2,   # k_wc_sep (K = 29): fetch 289466.4 KiB x2, write 8399.0 KiB
     },
 }
-TRAFFIC_SOURCES = ("paper_1805_11169_amd/csrc/k_matrices.hip", "paper_1805_11169_amd/csrc/icwf_device.hpp")
+TRAFFIC_SOURCES = ("paper_1805_11169_amd/csrc/k_matrices.hip", "paper_1805_11169_amd/csrc/icwf_device.hpp",
+                   "paper_1805_11169_amd/csrc/icwf_plan.hpp")
 
 
 def measured_traffic(workload, precision):

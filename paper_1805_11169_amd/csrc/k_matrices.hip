@@ -239,27 +239,28 @@ __device__ inline void triangle_tile(int t, int *tb, int *ta) {
 // while the matrix cores work on step s.  The j-sums of the epilogue go to
 // LDS once per j tile.
 //
-// FP64 stages straight from global memory into LDS (16 bytes per lane and
-// load; no staging registers, four times fewer load instructions than 4-byte
-// loads).  A load fills 64 consecutive 16-byte slots of a padded buffer:
-// psi1 rows of KC + 1 slots, W_c rows of 17 slots (16 pairs of doubles and
-// a pad pair), so that the operand reads stay free of bank conflicts; a lane
-// whose slot is padding, or past the tile, loads an in-bounds entry that is
-// never read.  FP32 stages through registers.
+// The staging goes straight from global memory into LDS (16 bytes per lane
+// and load; no staging registers, four times fewer load instructions than
+// 4-byte loads).  A load fills 64 consecutive 16-byte slots of a padded
+// buffer: psi1 rows of 32 slots plus a pad slot (528 bytes), W_c rows of
+// 16 slots plus one (FP64) or 8 plus 4 (FP32), so that the operand reads stay
+// free of bank conflicts; a lane whose slot is padding, or past the tile,
+// loads an in-bounds entry that is never read.  FP32 takes the i of a chunk
+// interleaved over the four lane quarters (i = 4 s + quarter at quad s), FP64
+// in four consecutive runs (i = QS quarter + s).
 template <typename T>
 struct WcChunk {
-    static constexpr bool DIRECT = sizeof(T) == 8;
     static constexpr int KC = sizeof(T) == 8 ? 32 : 64;   // i per chunk (LDS budget: 2 blocks / CU)
-    static constexpr int LDA = KC + 1;                    // padded psi1 row (complex entries)
-    static constexpr int LDW = DIRECT ? 34 : 33;          // padded W_c chunk row
-    static constexpr int PER = KC / 8;                    // elements each thread stages per array (FP32)
-    // direct staging: 16-byte slots per buffer and loads of 64 slots
-    static constexpr int ASLOTS = 32 * LDA;
-    static constexpr int ALOADS = (ASLOTS + 63) / 64;
-    static constexpr int AROWS = (64 * ALOADS + LDA - 1) / LDA;   // rows the buffer holds
-    static constexpr int WPAIRS = LDW / 2;
-    static constexpr int WLOADS = (KC * WPAIRS + 63) / 64;
-    static constexpr int WROWS = DIRECT ? (128 * WLOADS + LDW - 1) / LDW : KC;
+    static constexpr int CPLX = 2 * sizeof(T);            // bytes of a psi1 entry
+    static constexpr int LDA = 528 / CPLX;                 // padded psi1 row (entries): 33 slots
+    static constexpr int LDW = sizeof(T) == 8 ? 34 : 48;   // padded W_c chunk row (entries)
+    static constexpr bool INTERLEAVE = sizeof(T) == 4;
+    static constexpr int ALOADS = (32 * 33 + 63) / 64;                 // loads per psi1 buffer
+    static constexpr int AROWS = (64 * 16 * ALOADS + 527) / 528;       // rows the buffer holds
+    static constexpr int WSLOTS = LDW * sizeof(T) / 16;                // slots per W_c row
+    static constexpr int WDATA = 32 * sizeof(T) / 16;                  // of which data
+    static constexpr int WLOADS = (KC * WSLOTS + 63) / 64;
+    static constexpr int WROWS = (64 * 16 * WLOADS + LDW * (int)sizeof(T) - 1) / (LDW * (int)sizeof(T));
 };
 
 typedef __attribute__((address_space(3))) void lds_void;
@@ -302,8 +303,8 @@ __global__ void __launch_bounds__(256, 2) k_wc(const typename WcTraits<T>::cplx 
     typedef typename WcTraits<T>::acc4 acc4;
     typedef typename WcTraits<T>::cplx C2;
     typedef WcChunk<T> CK;
-    constexpr int KC = CK::KC, LDA = CK::LDA, LDW = CK::LDW, PER = CK::PER, QS = KC / 4;
-    constexpr int AROWS = CK::DIRECT ? CK::AROWS : 32, WROWS = CK::WROWS;
+    constexpr int KC = CK::KC, LDA = CK::LDA, LDW = CK::LDW, QS = KC / 4;
+    constexpr int AROWS = CK::AROWS, WROWS = CK::WROWS;
     if (flags[kFlagHalt]) return;
     // two staging buffers as separate arrays: the compiler can then tell the
     // reads of one from the direct loads into the other
@@ -377,69 +378,45 @@ __global__ void __launch_bounds__(256, 2) k_wc(const typename WcTraits<T>::cplx 
         typedef T WTile[WROWS][LDW];
         // tile row rr of the staging buffers: a rows first, then b rows
         auto tile_row = [&](int rr) { return rr < 16 ? a_base + rr : b_tile + rr - 16; };
-        // direct staging of one buffer of 32 rows x 32 complex entries
-        // (row stride 33 slots) from the tile's rows of `src` (stride `ld`
-        // entries), columns c0 .. c0 + 31
-        auto stage_rows = [&](const double2 *src, int ld, int c0, double2 *dst) __attribute__((always_inline)) {
+        // one step's operands into (A, W): 64 slots per load, load m of
+        // the buffer by wave m mod 4; slot -> (row, slot in the row)
+        auto fetch = [&](int step, ATile &A, WTile &W) __attribute__((always_inline)) {
+            const int jl = step / nchunk, ch = step - jl * nchunk, jt = jt0 + jl;
+            const int i0 = ch * KC, j0 = jt * 32;
+            const float4 *src_a = reinterpret_cast<const float4 *>(psi1);
+            const float4 *src_w = reinterpret_cast<const float4 *>(wtab);
     #pragma unroll
             for (int m = 0; m < (CK::ALOADS + 3) / 4; ++m) {
                 const int blk = 4 * m + wave;
                 if (blk < CK::ALOADS) {
                     const int slot = 64 * blk + lane;
-                    int rr = slot / 33, cc = slot - 33 * rr;
+                    int rr = slot / 33, c = slot - 33 * rr;
                     if (rr >= 32) rr = 31;
-                    if (cc >= 32) cc = 0;
-                    const uint32_t off = (uint32_t)(tile_row(rr) * ld + c0 + cc);
-                    __builtin_amdgcn_global_load_lds(reinterpret_cast<const float *>(src) + 4u * off,
-                                                     (lds_void *)(dst + 64 * blk), 16, 0, 0);
+                    if (c >= 32) c = 0;
+                    // 16-byte units: a psi1 row is nr entries of CPLX bytes
+                    const uint32_t off = (uint32_t)(((size_t)tile_row(rr) * nr + i0) * CK::CPLX / 16 + c);
+                    __builtin_amdgcn_global_load_lds(reinterpret_cast<const float *>(src_a + off),
+                                                     (lds_void *)(reinterpret_cast<char *>(&A[0][0]) + 1024 * blk), 16,
+                                                     0, 0);
+                }
+            }
+    #pragma unroll
+            for (int m = 0; m < (CK::WLOADS + 3) / 4; ++m) {
+                const int blk = 4 * m + wave;
+                if (blk < CK::WLOADS) {
+                    const int slot = 64 * blk + lane;
+                    int ii = slot / CK::WSLOTS, c = slot - CK::WSLOTS * ii;
+                    if (ii >= KC) ii = KC - 1;
+                    if (c >= CK::WDATA) c = 0;
+                    const uint32_t off = (uint32_t)(((size_t)(i0 + ii) * nR + j0) * sizeof(T) / 16 + c);
+                    __builtin_amdgcn_global_load_lds(reinterpret_cast<const float *>(src_w + off),
+                                                     (lds_void *)(reinterpret_cast<char *>(&W[0][0]) + 1024 * blk), 16,
+                                                     0, 0);
                 }
             }
         };
-        // staging registers for one (j tile, i chunk) step (FP32)
-        C2 ra[PER];
-        T rw[PER];
-        auto fetch = [&](int step, ATile &A, WTile &W) __attribute__((always_inline)) {
-            const int jl = step / nchunk, ch = step - jl * nchunk, jt = jt0 + jl;
-            const int i0 = ch * KC, j0 = jt * 32;
-            if constexpr (CK::DIRECT) {
-                stage_rows(reinterpret_cast<const double2 *>(psi1), nr, i0, reinterpret_cast<double2 *>(&A[0][0]));
-    #pragma unroll
-                for (int m = 0; m < (CK::WLOADS + 3) / 4; ++m) {
-                    const int blk = 4 * m + wave;
-                    if (blk < CK::WLOADS) {
-                        const int slot = 64 * blk + lane;
-                        int ii = slot / CK::WPAIRS, pr = slot - CK::WPAIRS * ii;
-                        if (ii >= KC) ii = KC - 1;
-                        if (pr >= 16) pr = 0;
-                        const uint32_t off = (uint32_t)((i0 + ii) * nR + j0 + 2 * pr);
-                        __builtin_amdgcn_global_load_lds(reinterpret_cast<const float *>(wtab) + 2u * off,
-                                                         (lds_void *)(&W[0][0] + 128 * blk), 16, 0, 0);
-                    }
-                }
-            } else {
-    #pragma unroll
-                for (int m = 0; m < PER; ++m) {
-                    const int e = t + 256 * m;
-                    const int rr = e / KC, cc = e - rr * KC;
-                    ra[m] = psi1[(size_t)tile_row(rr) * nr + i0 + cc];
-                    const int ii = e >> 5, jj = e & 31;
-                    rw[m] = wtab[(size_t)(i0 + ii) * nR + j0 + jj];
-                }
-            }
-        };
-        auto stash = [&](ATile &A, WTile &W) __attribute__((always_inline)) {
-            if constexpr (CK::DIRECT) {
-                __builtin_amdgcn_s_waitcnt(0x0f70);   // vmcnt(0): the direct loads have landed
-            } else {
-    #pragma unroll
-                for (int m = 0; m < PER; ++m) {
-                    const int e = t + 256 * m;
-                    const int rr = e / KC, cc = e - rr * KC;
-                    A[rr][cc] = ra[m];
-                    W[e >> 5][e & 31] = rw[m];
-                }
-            }
-        };
+        // the loads have landed (vmcnt(0))
+        auto stash = [&]() __attribute__((always_inline)) { __builtin_amdgcn_s_waitcnt(0x0f70); };
 
         acc4 acc[4][2][2];   // [b][re/im][j fragment]
         // one (j tile, i chunk) step on the buffers (A, W); the next step's
@@ -460,7 +437,7 @@ __global__ void __launch_bounds__(256, 2) k_wc(const typename WcTraits<T>::cplx 
             C2 xa, xb[4];
             T w0, w1;
             auto operands = [&](int s, C2 &oa, C2 (&ob)[4], T &o0, T &o1) __attribute__((always_inline)) {
-                const int col = quarter * QS + s;
+                const int col = CK::INTERLEAVE ? 4 * s + quarter : quarter * QS + s;
                 oa = A[row][col];
                 o0 = W[col][row];
                 o1 = W[col][row + 16];
@@ -490,10 +467,10 @@ __global__ void __launch_bounds__(256, 2) k_wc(const typename WcTraits<T>::cplx 
                     for (int bb = 0; bb < 4; ++bb) xb[bb] = nb[bb];
                 }
             }
-            // keep the stores (or the wait) for the next step's operands after
-            // the matrix products
+            // keep the wait for the next step's operands after the matrix
+            // products
             __builtin_amdgcn_sched_barrier(0);
-            if (step + 1 < nsteps) stash(An, Wn);
+            if (step + 1 < nsteps) stash();
             if (ch == nchunk - 1) {
                 // epilogue: lane holds T(b, a = a_base + mfma_row(T, lane, v), j = j0 + 16 jf + row);
                 // multiply by P2 = conj(psi2^b_j) psi2^a_j and sum over the 16 j of the fragment
@@ -533,20 +510,13 @@ __global__ void __launch_bounds__(256, 2) k_wc(const typename WcTraits<T>::cplx 
             __syncthreads();
         };
         fetch(0, sA0, sW0);
-        stash(sA0, sW0);
+        stash();
         __syncthreads();
-        if constexpr (CK::DIRECT) {
-            // the buffers by name in each half of the loop (the reads of one
-            // need not wait for the direct loads into the other)
-            for (int step = 0; step < nsteps; step += 2) {
-                body(step, sA0, sW0, sA1, sW1);
-                if (step + 1 < nsteps) body(step + 1, sA1, sW1, sA0, sW0);
-            }
-        } else {
-            for (int step = 0; step < nsteps; ++step) {
-                const bool odd = step & 1;
-                body(step, odd ? sA1 : sA0, odd ? sW1 : sW0, odd ? sA0 : sA1, odd ? sW0 : sW1);
-            }
+        // the buffers by name in each half of the loop (the reads of one need
+        // not wait for the direct loads into the other)
+        for (int step = 0; step < nsteps; step += 2) {
+            body(step, sA0, sW0, sA1, sW1);
+            if (step + 1 < nsteps) body(step + 1, sA1, sW1, sA0, sW0);
         }
         // write the 4 x 16 partials of this wave
         const int bb = lane >> 4, a = lane & 15;
@@ -809,7 +779,10 @@ void launch_wc(const Dims &d, const Bufs &b, hipStream_t s) {
     const int nparts = std::min(kWcParts, d.nR / 32);
     const int nsplit = nparts >= 2 ? std::min(grid, wc_split_tiles(Np)) : 0;
     const int spq = wc_split_per_queue(nsplit);   // split tiles per queue
-    if (d.prec == 1) {
+    // the FP32 pass tiles the electron grid in chunks of 64 points: a 32-point
+    // grid takes the dense FP64 contraction of the whole table instead
+    const bool fp32_fits = d.nr >= WcChunk<float>::KC;
+    if (d.prec == 1 && fp32_fits) {
         // mixed: FP32 matrix cores on the residual of the rank-K split, FP64 rank-K part added
         // (the FP32 pass only where the residual is above the table's rounding)
         if (d.fp32_residual) {

@@ -247,18 +247,25 @@ __device__ inline void triangle_tile(int t, int *tb, int *ta) {
 // free of bank conflicts; a lane whose slot is padding, or past the tile,
 // loads an in-bounds entry that is never read.  FP32 takes the i of a chunk
 // interleaved over the four lane quarters (i = 4 s + quarter at quad s), FP64
-// in four consecutive runs (i = QS quarter + s).
+// in four consecutive runs (i = QS quarter + s).  FP32 accumulators take half
+// the registers of FP64 ones, so its j tiles are 64 wide (each pair product
+// feeds eight matrix products instead of four).
 template <typename T>
 struct WcChunk {
     static constexpr int KC = sizeof(T) == 8 ? 32 : 64;   // i per chunk (LDS budget: 2 blocks / CU)
+    static constexpr int JT = sizeof(T) == 8 ? 32 : 64;   // j per tile
+    static constexpr int JF = JT / 16;                    // 16-wide j fragments
     static constexpr int CPLX = 2 * sizeof(T);            // bytes of a psi1 entry
     static constexpr int LDA = 528 / CPLX;                 // padded psi1 row (entries): 33 slots
-    static constexpr int LDW = sizeof(T) == 8 ? 34 : 48;   // padded W_c chunk row (entries)
+    static constexpr int LDW = sizeof(T) == 8 ? 34 : 80;   // padded W_c chunk row (entries)
     static constexpr bool INTERLEAVE = sizeof(T) == 4;
+    // operands of the next i-quad read before this quad's matrix products
+    // (FP64; the FP32 kernel has no registers to spare for them)
+    static constexpr bool PREFETCH = sizeof(T) == 8;
     static constexpr int ALOADS = (32 * 33 + 63) / 64;                 // loads per psi1 buffer
     static constexpr int AROWS = (64 * 16 * ALOADS + 527) / 528;       // rows the buffer holds
     static constexpr int WSLOTS = LDW * sizeof(T) / 16;                // slots per W_c row
-    static constexpr int WDATA = 32 * sizeof(T) / 16;                  // of which data
+    static constexpr int WDATA = JT * sizeof(T) / 16;                  // of which data
     static constexpr int WLOADS = (KC * WSLOTS + 63) / 64;
     static constexpr int WROWS = (64 * 16 * WLOADS + LDW * (int)sizeof(T) - 1) / (LDW * (int)sizeof(T));
 };
@@ -303,7 +310,7 @@ __global__ void __launch_bounds__(256, 2) k_wc(const typename WcTraits<T>::cplx 
     typedef typename WcTraits<T>::acc4 acc4;
     typedef typename WcTraits<T>::cplx C2;
     typedef WcChunk<T> CK;
-    constexpr int KC = CK::KC, LDA = CK::LDA, LDW = CK::LDW, QS = KC / 4;
+    constexpr int KC = CK::KC, LDA = CK::LDA, LDW = CK::LDW, QS = KC / 4, JT = CK::JT, JF = CK::JF;
     constexpr int AROWS = CK::AROWS, WROWS = CK::WROWS;
     if (flags[kFlagHalt]) return;
     // two staging buffers as separate arrays: the compiler can then tell the
@@ -372,7 +379,7 @@ __global__ void __launch_bounds__(256, 2) k_wc(const typename WcTraits<T>::cplx 
 
         for (int e = lane; e < 64; e += 64) wl[wave][e >> 4][e & 15] = make_double2(0, 0);
 
-        const int nchunk = nr / KC, ntj = half < 0 ? nR / 32 : nR / 32 / nparts, nsteps = nchunk * ntj;
+        const int nchunk = nr / KC, ntj = half < 0 ? nR / JT : nR / JT / nparts, nsteps = nchunk * ntj;
         const int jt0 = half > 0 ? half * ntj : 0;   // first j tile of this unit
         typedef C2 ATile[AROWS][LDA];
         typedef T WTile[WROWS][LDW];
@@ -382,7 +389,7 @@ __global__ void __launch_bounds__(256, 2) k_wc(const typename WcTraits<T>::cplx 
         // the buffer by wave m mod 4; slot -> (row, slot in the row)
         auto fetch = [&](int step, ATile &A, WTile &W) __attribute__((always_inline)) {
             const int jl = step / nchunk, ch = step - jl * nchunk, jt = jt0 + jl;
-            const int i0 = ch * KC, j0 = jt * 32;
+            const int i0 = ch * KC, j0 = jt * JT;
             const float4 *src_a = reinterpret_cast<const float4 *>(psi1);
             const float4 *src_w = reinterpret_cast<const float4 *>(wtab);
     #pragma unroll
@@ -418,7 +425,7 @@ __global__ void __launch_bounds__(256, 2) k_wc(const typename WcTraits<T>::cplx 
         // the loads have landed (vmcnt(0))
         auto stash = [&]() __attribute__((always_inline)) { __builtin_amdgcn_s_waitcnt(0x0f70); };
 
-        acc4 acc[4][2][2];   // [b][re/im][j fragment]
+        acc4 acc[4][2][JF];   // [b][re/im][j fragment]
         // one (j tile, i chunk) step on the buffers (A, W); the next step's
         // operands are staged into (An, Wn) meanwhile
         auto body = [&](int step, ATile &A, WTile &W, ATile &An, WTile &Wn) __attribute__((always_inline)) {
@@ -429,40 +436,42 @@ __global__ void __launch_bounds__(256, 2) k_wc(const typename WcTraits<T>::cplx 
     #pragma unroll
                     for (int c = 0; c < 2; ++c)
     #pragma unroll
-                        for (int jf = 0; jf < 2; ++jf) acc[bb][c][jf] = acc4{0, 0, 0, 0};
+                        for (int jf = 0; jf < JF; ++jf) acc[bb][c][jf] = acc4{0, 0, 0, 0};
             }
             if (step + 1 < nsteps) fetch(step + 1, An, Wn);
-            // operands of i-quad s + 1 are read from LDS while the matrix
-            // cores work on quad s
+            // (FP64) operands of i-quad s + 1 are read from LDS while the
+            // matrix cores work on quad s
             C2 xa, xb[4];
-            T w0, w1;
-            auto operands = [&](int s, C2 &oa, C2 (&ob)[4], T &o0, T &o1) __attribute__((always_inline)) {
+            T w[JF];
+            auto operands = [&](int s, C2 &oa, C2 (&ob)[4], T (&ow)[JF]) __attribute__((always_inline)) {
                 const int col = CK::INTERLEAVE ? 4 * s + quarter : quarter * QS + s;
                 oa = A[row][col];
-                o0 = W[col][row];
-                o1 = W[col][row + 16];
+    #pragma unroll
+                for (int jf = 0; jf < JF; ++jf) ow[jf] = W[col][16 * jf + row];
     #pragma unroll
                 for (int bb = 0; bb < 4; ++bb) ob[bb] = A[16 + 4 * wave + bb][col];
             };
-            operands(0, xa, xb, w0, w1);
+            operands(0, xa, xb, w);
     #pragma unroll
             for (int s = 0; s < QS; ++s) {
                 C2 na, nb[4];
-                T n0, n1;
-                if (s + 1 < QS) operands(s + 1, na, nb, n0, n1);
+                T nw[JF];
+                if (CK::PREFETCH && s + 1 < QS) operands(s + 1, na, nb, nw);
     #pragma unroll
                 for (int bb = 0; bb < 4; ++bb) {
                     const C2 p = cmulc(xb[bb], xa);   // conj(psi1^b_i) psi1^a_i
                     const T pr = (T)p.x, pi = (T)p.y;
-                    acc[bb][0][0] = mfma(pr, w0, acc[bb][0][0]);
-                    acc[bb][1][0] = mfma(pi, w0, acc[bb][1][0]);
-                    acc[bb][0][1] = mfma(pr, w1, acc[bb][0][1]);
-                    acc[bb][1][1] = mfma(pi, w1, acc[bb][1][1]);
+    #pragma unroll
+                    for (int jf = 0; jf < JF; ++jf) {
+                        acc[bb][0][jf] = mfma(pr, w[jf], acc[bb][0][jf]);
+                        acc[bb][1][jf] = mfma(pi, w[jf], acc[bb][1][jf]);
+                    }
                 }
+                if (!CK::PREFETCH && s + 1 < QS) operands(s + 1, na, nb, nw);
                 if (s + 1 < QS) {
                     xa = na;
-                    w0 = n0;
-                    w1 = n1;
+    #pragma unroll
+                    for (int jf = 0; jf < JF; ++jf) w[jf] = nw[jf];
     #pragma unroll
                     for (int bb = 0; bb < 4; ++bb) xb[bb] = nb[bb];
                 }
@@ -474,13 +483,19 @@ __global__ void __launch_bounds__(256, 2) k_wc(const typename WcTraits<T>::cplx 
             if (ch == nchunk - 1) {
                 // epilogue: lane holds T(b, a = a_base + mfma_row(T, lane, v), j = j0 + 16 jf + row);
                 // multiply by P2 = conj(psi2^b_j) psi2^a_j and sum over the 16 j of the fragment
-                const int j0 = jt * 32;
+                const int j0 = jt * JT;
                 auto p2 = [&](int rr, int jj) { return psi2[(size_t)tile_row(rr) * nR + j0 + jj]; };
-                double2 p2a[2][4];
+                // the a-row entries are loaded once for all b (two j
+                // fragments), or again for each b (four: their registers are
+                // needed for the accumulators)
+                constexpr bool HOIST = JF <= 2;
+                double2 p2a[HOIST ? JF : 1][4];
+                if constexpr (HOIST) {
     #pragma unroll
-                for (int jf = 0; jf < 2; ++jf)
+                    for (int jf = 0; jf < JF; ++jf)
     #pragma unroll
-                    for (int v = 0; v < 4; ++v) p2a[jf][v] = p2(mfma_row(T(0), lane, v), 16 * jf + row);
+                        for (int v = 0; v < 4; ++v) p2a[jf][v] = p2(mfma_row(T(0), lane, v), 16 * jf + row);
+                }
                 // one b at a time keeps the live registers low
     #pragma unroll
                 for (int bb = 0; bb < 4; ++bb) {
@@ -488,11 +503,12 @@ __global__ void __launch_bounds__(256, 2) k_wc(const typename WcTraits<T>::cplx 
     #pragma unroll
                     for (int v = 0; v < 4; ++v) ws[v] = make_double2(0, 0);
     #pragma unroll
-                    for (int jf = 0; jf < 2; ++jf) {
+                    for (int jf = 0; jf < JF; ++jf) {
                         const double2 p2b = p2(16 + 4 * wave + bb, 16 * jf + row);
     #pragma unroll
                         for (int v = 0; v < 4; ++v) {
-                            const double2 P2 = cmulc(p2b, p2a[jf][v]);
+                            const double2 pa = HOIST ? p2a[HOIST ? jf : 0][v] : p2(mfma_row(T(0), lane, v), 16 * jf + row);
+                            const double2 P2 = cmulc(p2b, pa);
                             const double2 Tv = make_double2((double)acc[bb][0][jf][v], (double)acc[bb][1][jf][v]);
                             ws[v] = cadd(ws[v], cmul(P2, Tv));
                         }
@@ -773,19 +789,23 @@ void launch_wc(const Dims &d, const Bufs &b, hipStream_t s) {
     const int T16 = Np / 16;
     const int blocks = T16 * (T16 + 1) / 2;
     const double scale = d.hr * d.hR;
-    // the last round of tiles split in kWcParts (fewer where R has fewer
-    // 32-point j tiles)
+    // the last round of tiles split in kWcParts (fewer where R has fewer j
+    // tiles)
     const int grid = std::min(blocks, d.wc_grid);
-    const int nparts = std::min(kWcParts, d.nR / 32);
-    const int nsplit = nparts >= 2 ? std::min(grid, wc_split_tiles(Np)) : 0;
-    const int spq = wc_split_per_queue(nsplit);   // split tiles per queue
-    // the FP32 pass tiles the electron grid in chunks of 64 points: a 32-point
-    // grid takes the dense FP64 contraction of the whole table instead
-    const bool fp32_fits = d.nr >= WcChunk<float>::KC;
+    auto split = [&](int jt, int *nparts, int *spq) {
+        *nparts = std::min(kWcParts, d.nR / jt);
+        const int nsplit = *nparts >= 2 ? std::min(grid, wc_split_tiles(Np)) : 0;
+        *spq = wc_split_per_queue(nsplit);   // split tiles per queue
+    };
+    int nparts, spq;
+    // the FP32 pass tiles the grid in chunks of 64 x 64 points: smaller grids
+    // take the dense FP64 contraction of the whole table instead
+    const bool fp32_fits = d.nr >= WcChunk<float>::KC && d.nR >= WcChunk<float>::JT;
     if (d.prec == 1 && fp32_fits) {
         // mixed: FP32 matrix cores on the residual of the rank-K split, FP64 rank-K part added
         // (the FP32 pass only where the residual is above the table's rounding)
         if (d.fp32_residual) {
+            split(WcChunk<float>::JT, &nparts, &spq);
             launch_fill_i32(b.wc_queue, kWcQueues + kWcQueues * spq, 0, s, d.batch, d.zoff);
             hipLaunchKernelGGL((d.zoff ? k_wc<float, true> : k_wc<float, false>), dim3(grid, 1, d.batch), dim3(256), 0, s, b.psi1_f32, b.psi2, b.wc32, d.nr,
                                d.nR, scale, b.Wc, Np, 0, blocks, spq, nparts, b.wc_queue, b.wc_order, b.wc_part,
@@ -804,6 +824,7 @@ void launch_wc(const Dims &d, const Bufs &b, hipStream_t s) {
                            b.lr_u, b.lr_v, (d.lr_rank + 15) / 16 * 16, d.nr, d.nR, scale, b.Wc, Np, 0, blocks,
                            b.wc_queue, b.flags, d.zoff);
     } else {
+        split(WcChunk<double>::JT, &nparts, &spq);
         launch_fill_i32(b.wc_queue, kWcQueues + kWcQueues * spq, 0, s, d.batch, d.zoff);
         hipLaunchKernelGGL((d.zoff ? k_wc<double, true> : k_wc<double, false>), dim3(grid, 1, d.batch), dim3(256), 0, s, b.psi1, b.psi2, b.wc64, d.nr, d.nR,
                            scale, b.Wc, Np, 0, blocks, spq, nparts, b.wc_queue, b.wc_order, b.wc_part, b.flags,

@@ -230,3 +230,26 @@ def test_heun_trajectories_ten_steps(case):
         assert rel_max(o[key], ref[key]) < 1e-10, key
     for key in ("r", "R"):
         assert np.max(np.abs(o[key] - ref[key])) < 1e-10 * max(1.0, np.max(np.abs(ref[key]))), key
+
+
+@pytest.mark.parametrize("n_r,n_R,N", [(32, 64, 37), (64, 32, 37), (64, 64, 37), (128, 256, 130), (512, 128, 70)])
+def test_mixed_form_contraction_on_every_grid_shape(n_r, n_R, N):
+    """The mixed form's two-body contraction at t = 0 against the FP64
+    definition (Eq. 9b), Shin-Metiu, relative to its largest entry: within
+    1e-9 where the FP32 residual pass runs (grids of at least 64 x 64 points,
+    64-point i chunks and 64-point j tiles; one or more tiles of each, and a
+    ragged N), within 1e-12 where a grid too small for it takes the FP64
+    contraction of the whole table (32 electronic or nuclear points)."""
+    wl = inputs.gaussian_basis(N, n_r=n_r, n_R=n_R, model=inputs.MODEL_SHIN_METIU, seed=17)
+    _print_case(f"mixed {n_r}x{n_R}", wl)
+    setup = setup_for(wl)
+    st0 = init_for(setup, wl)
+    sim = icwf.Simulation.from_workload(wl, precision=icwf.PREC_MIXED, C0=wl.extra["C0"])
+    S, K, Wc = sim.matrices()
+    sim.close()
+    Wc_ref = omat.two_body(st0.psi1, st0.psi2, wc_table(setup), setup.hr, setup.hR)
+    fp32_pass = n_r >= 64 and n_R >= 64
+    err = rel_max(Wc, Wc_ref)
+    print(f"[result] mixed Wc error {err:.2e} (FP32 pass: {fp32_pass})", flush=True)
+    assert err < (1e-9 if fp32_pass else 1e-12)
+    assert rel_max(S, st0.S) < 1e-12

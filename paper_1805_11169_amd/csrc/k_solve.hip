@@ -580,29 +580,33 @@ __device__ inline void publish_block(int32_t *flag) {
     }
 }
 
-
-// y = M v, one wave per row, four rows per work-group.
 // Parts of a matrix a matrix-vector product reads: all of it, the lower
 // triangle with the diagonal, or the upper triangle with the diagonal.
 enum MatPart : int { kPartAll = 0, kPartLower = 1, kPartUpper = 2 };
 
-// Row rowi of M times v over the columns of the part, summed by one wave in a
-// fixed order (every lane ends with the sum).
-__device__ inline double2 row_dot(const double2 *__restrict__ m, const double2 *__restrict__ v, int rowi, int Np,
-                                  int part) {
-    const int lane = threadIdx.x & 63;
+// Row-times-vector sums of the stage solves: one row per 256-thread
+// work-group, wave w taking the 64-column chunks w, w + 4, ... (so that a
+// triangular part spreads evenly), the four wave sums added in wave order
+// (a fixed summation order).  Every thread returns the row's sum.
+template <typename Term>
+__device__ inline double2 row_sum_wg(int rowi, int Np, int part, Term term) {
+    __shared__ double2 wsum[4];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int lo = part == kPartUpper ? (rowi & ~63) : 0, hi = part == kPartLower ? rowi + 1 : Np;
     double2 acc = make_double2(0, 0);
-    for (int c = lo + lane; c < hi; c += 64)
-        if (part != kPartUpper || c >= rowi) acc = cadd(acc, cmul(m[c], v[c]));
+    for (int c = lo + 64 * wave + lane; c < hi; c += 256)
+        if (part != kPartUpper || c >= rowi) acc = cadd(acc, term(c));
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
         acc.x += __shfl_xor(acc.x, off);
         acc.y += __shfl_xor(acc.y, off);
     }
-    return acc;
+    if (lane == 0) wsum[wave] = acc;
+    __syncthreads();
+    return cadd(cadd(wsum[0], wsum[1]), cadd(wsum[2], wsum[3]));
 }
 
+// y = M v over the part of M (one row per work-group)
 __global__ void __launch_bounds__(256) k_matvec(const double2 *__restrict__ M, const double2 *__restrict__ v,
                                                 double2 *__restrict__ y, int Np, int part,
                                                 const int32_t *__restrict__ flags, const long long *__restrict__ zoff) {
@@ -613,10 +617,10 @@ __global__ void __launch_bounds__(256) k_matvec(const double2 *__restrict__ M, c
     flags = zshift(flags, zo_);
 
     if (flags[kFlagHalt]) return;
-    const int lane = threadIdx.x & 63;
-    const int rowi = blockIdx.x * 4 + (threadIdx.x >> 6);
-    const double2 acc = row_dot(M + (size_t)rowi * Np, v, rowi, Np, part);
-    if (lane == 0) y[rowi] = acc;
+    const int rowi = blockIdx.x;
+    const double2 *m = M + (size_t)rowi * Np;
+    const double2 acc = row_sum_wg(rowi, Np, part, [&](int c) { return cmul(m[c], v[c]); });
+    if (threadIdx.x == 0) y[rowi] = acc;
 }
 
 // Forward stage kernel: y_B = L_BB^-1 (rhs_B - sum_{C<B} L_BC y_C), with
@@ -795,7 +799,7 @@ __global__ void __launch_bounds__(256) k_rk_bwd(const double2 *__restrict__ L, c
 // assembly), x = x0 + L^-H (L^-1 res) (k_matvec, then k_rk_apply with the
 // stage update of the row).  The refinement brings the explicit inverse's
 // error, of the order of cond(A) times its rounding, back to that of a
-// solve with the factor.  One wave per row, four rows per work-group.
+// solve with the factor.  One row per work-group.
 __global__ void __launch_bounds__(256) k_rk_resid(const double2 *__restrict__ Sa, const double2 *__restrict__ Sb,
                                                   double eps, const double2 *__restrict__ x,
                                                   const double2 *__restrict__ rhs, double2 *__restrict__ res, int Np,
@@ -809,12 +813,10 @@ __global__ void __launch_bounds__(256) k_rk_resid(const double2 *__restrict__ Sa
     flags = zshift(flags, zo_);
 
     if (flags[kFlagHalt]) return;
-    const int lane = threadIdx.x & 63;
-    const int rowi = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int rowi = blockIdx.x;
     const double2 *ma = Sa + (size_t)rowi * Np;
     const double2 *mb = Sb ? Sb + (size_t)rowi * Np : nullptr;
-    double2 acc = make_double2(0, 0);
-    for (int c = lane; c < Np; c += 64) {
+    const double2 acc = row_sum_wg(rowi, Np, kPartAll, [&](int c) {
         const double reg = (c == rowi) ? eps : 0.0;
         const double2 sa = ma[c];
         double2 a;
@@ -824,14 +826,9 @@ __global__ void __launch_bounds__(256) k_rk_resid(const double2 *__restrict__ Sa
         } else {                                     // endpoint: S_a + eps I
             a = make_double2(sa.x + reg, sa.y);
         }
-        acc = cadd(acc, cmul(a, x[c]));
-    }
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        acc.x += __shfl_xor(acc.x, off);
-        acc.y += __shfl_xor(acc.y, off);
-    }
-    if (lane == 0) res[rowi] = csub(rhs[rowi], acc);
+        return cmul(a, x[c]);
+    });
+    if (threadIdx.x == 0) res[rowi] = csub(rhs[rowi], acc);
 }
 
 __global__ void __launch_bounds__(256) k_rk_apply(const double2 *__restrict__ H, const double2 *__restrict__ z,
@@ -854,10 +851,11 @@ __global__ void __launch_bounds__(256) k_rk_apply(const double2 *__restrict__ H,
     flags = zshift(flags, zo_);
 
     if (flags[kFlagHalt]) return;
-    const int lane = threadIdx.x & 63;
-    const int rowi = blockIdx.x * 4 + (threadIdx.x >> 6);
-    const double2 acc = row_dot(H + (size_t)rowi * Np, z, rowi, Np, kPartUpper);   // (L^-H z)_rowi
-    if (lane == 0) stage_update(rowi, cadd(x0[rowi], acc), stage, dt, N, C, Cacc, Cstage, r, R, r_new, R_new, flags);
+    const int rowi = blockIdx.x;
+    const double2 *m = H + (size_t)rowi * Np;
+    const double2 acc = row_sum_wg(rowi, Np, kPartUpper, [&](int c) { return cmul(m[c], z[c]); });   // (L^-H z)_rowi
+    if (threadIdx.x == 0)
+        stage_update(rowi, cadd(x0[rowi], acc), stage, dt, N, C, Cacc, Cstage, r, R, r_new, R_new, flags);
 }
 
 // H = F^H over the lower part of F (F = L^-1): 32 x 32 tiles through LDS,
@@ -972,21 +970,21 @@ void launch_rk4(const Dims &d, const Bufs &b, int parity, hipStream_t s) {
     double *cr = d.traj == 1 ? nullptr : b.r, *cR = d.traj == 1 ? nullptr : b.R;
     for (int st = 1; st <= 4; ++st) {
         const double2 *v = (st == 1) ? b.C : b.Cstage;
-        hipLaunchKernelGGL(k_matvec, dim3(Np / 4, 1, d.batch), dim3(256), 0, s, Ks[st - 1], v, b.rhs, Np,
+        hipLaunchKernelGGL(k_matvec, dim3(Np, 1, d.batch), dim3(256), 0, s, Ks[st - 1], v, b.rhs, Np,
                            (int)kPartAll, b.flags, d.zoff);
         if (d.sinv) {
             // A of the stage: S_k + eps I, the midpoint average + eps I (stages 2, 3), S_k+1 + eps I
             const double2 *Sa = st == 4 ? b.Smat[nxt] : b.Smat[cur];
             const double2 *Sb = (st == 2 || st == 3) ? b.Smat[nxt] : nullptr;
-            hipLaunchKernelGGL(k_matvec, dim3(Np / 4, 1, d.batch), dim3(256), 0, s, Fs[st - 1], b.rhs, b.zvec, Np,
+            hipLaunchKernelGGL(k_matvec, dim3(Np, 1, d.batch), dim3(256), 0, s, Fs[st - 1], b.rhs, b.zvec, Np,
                                (int)kPartLower, b.flags, d.zoff);
-            hipLaunchKernelGGL(k_matvec, dim3(Np / 4, 1, d.batch), dim3(256), 0, s, Hs[st - 1], b.zvec, b.y, Np,
+            hipLaunchKernelGGL(k_matvec, dim3(Np, 1, d.batch), dim3(256), 0, s, Hs[st - 1], b.zvec, b.y, Np,
                                (int)kPartUpper, b.flags, d.zoff);
-            hipLaunchKernelGGL(k_rk_resid, dim3(Np / 4, 1, d.batch), dim3(256), 0, s, Sa, Sb, d.eps, b.y, b.rhs, b.xsol,
+            hipLaunchKernelGGL(k_rk_resid, dim3(Np, 1, d.batch), dim3(256), 0, s, Sa, Sb, d.eps, b.y, b.rhs, b.xsol,
                                Np, b.flags, d.zoff);
-            hipLaunchKernelGGL(k_matvec, dim3(Np / 4, 1, d.batch), dim3(256), 0, s, Fs[st - 1], b.xsol, b.zvec, Np,
+            hipLaunchKernelGGL(k_matvec, dim3(Np, 1, d.batch), dim3(256), 0, s, Fs[st - 1], b.xsol, b.zvec, Np,
                                (int)kPartLower, b.flags, d.zoff);
-            hipLaunchKernelGGL(k_rk_apply, dim3(Np / 4, 1, d.batch), dim3(256), 0, s, Hs[st - 1], b.zvec, b.y, Np, st,
+            hipLaunchKernelGGL(k_rk_apply, dim3(Np, 1, d.batch), dim3(256), 0, s, Hs[st - 1], b.zvec, b.y, Np, st,
                                d.dt, d.N, b.C, b.Cacc, b.Cstage, cr, cR, b.r_new, b.R_new, b.flags, d.zoff);
             continue;
         }

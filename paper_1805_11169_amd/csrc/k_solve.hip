@@ -213,7 +213,14 @@ __global__ void __launch_bounds__(kPanelThreads) k_chol_panel(double2 *A0, doubl
             bad = true;
             piv = 1.0;
         }
-        const double d = sqrt(piv), dinv = 1.0 / d;
+        // 1/sqrt(piv) from the hardware estimate and two Newton steps
+        // y <- y (3 - piv y^2) / 2 (each squares the relative error), then
+        // sqrt(piv) = piv y: a few FP64 operations instead of the correctly
+        // rounded sqrt and division sequences on the panel's serial chain
+        double dinv = __builtin_amdgcn_rsq(piv);
+        dinv = dinv * fma(-0.5 * piv * dinv, dinv, 1.5);
+        dinv = dinv * fma(-0.5 * piv * dinv, dinv, 1.5);
+        const double d = piv * dinv;
         if (c > j) {
             const double2 lc = cscale(cconj(lcj), dinv * dinv);
 #pragma unroll

@@ -105,8 +105,8 @@ struct Bufs {
     double *obs_out;                      // packed observables
     int32_t *flags;                       // kNumFlags status flags
     int32_t *wc_queue;                    // [kWcQueues + wc_split_slots(Np)] unit counters of the persistent
-                                          // two-body contraction (one per XCD queue; the separable and rank-K
-                                          // passes use the first), then the completion counters of split tiles
+                                          // two-body contractions (one per XCD queue), then the completion
+                                          // counters of split tiles
     int32_t *wc_order;                    // [Np/16 (Np/16 + 1) / 2] tile order of the queues (wc_tile_order)
     double2 *wc_part;                     // [wc_split_slots(Np)][kWcParts][256] partial sums of split tiles
     double *scal;                         // small device scalars (min |Psi|, ...)

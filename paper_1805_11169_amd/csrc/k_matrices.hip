@@ -651,7 +651,8 @@ __global__ void __launch_bounds__(256, 2) k_wc_sep(const double2 *__restrict__ p
                                                    const double *__restrict__ U, const double *__restrict__ V,
                                                    int kpad, int nr, int nR, double scale,
                                                    double2 *__restrict__ Wc, int Np, int accumulate, int ntiles,
-                                                   int32_t *__restrict__ queue, const int32_t *__restrict__ flags, const long long *__restrict__ zoff) {
+                                                   int32_t *__restrict__ queue, const int32_t *__restrict__ order,
+                                                   const int32_t *__restrict__ flags, const long long *__restrict__ zoff) {
     const long long zo_ = BATCHED ? batch_offset(zoff) : 0;
     psi1 = zshift(psi1, zo_);
     psi2 = zshift(psi2, zo_);
@@ -659,6 +660,7 @@ __global__ void __launch_bounds__(256, 2) k_wc_sep(const double2 *__restrict__ p
     V = zshift(V, zo_);
     Wc = zshift(Wc, zo_);
     queue = zshift(queue, zo_);
+    order = zshift(order, zo_);
     flags = zshift(flags, zo_);
 
     if (flags[kFlagHalt]) return;
@@ -666,14 +668,27 @@ __global__ void __launch_bounds__(256, 2) k_wc_sep(const double2 *__restrict__ p
     __shared__ double sF[2][kSepKC][17];
     __shared__ double2 wl[4][4][16];     // [wave][b][a] block partial of Wc
     __shared__ int s_tile;
+    // tiles from the per-XCD queues over the blocked tile order, as k_wc
+    const int xcd = __builtin_amdgcn_s_getreg(20 | (0 << 6) | (3 << 11)) & (kWcQueues - 1);   // HW_REG_XCC_ID
     for (;;) {
-        if (threadIdx.x == 0) s_tile = atomicAdd(queue, 1);
+        if (threadIdx.x == 0) {
+            int got = -1;
+            for (int o = 0; o < kWcQueues && got < 0; ++o) {
+                const int q = (xcd + o) & (kWcQueues - 1);
+                const int lo = (int)((long long)q * ntiles / kWcQueues);
+                const int n = (int)((long long)(q + 1) * ntiles / kWcQueues) - lo;
+                if (__hip_atomic_load(&queue[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= n) continue;
+                const int k = atomicAdd(&queue[q], 1);
+                if (k < n) got = lo + k;
+            }
+            s_tile = got;
+        }
         __syncthreads();
-        const int tile = s_tile;
+        const int pos = s_tile;
         __syncthreads();
-        if (tile >= ntiles) break;
+        if (pos < 0) break;
         int tb, ta;
-        triangle_tile(tile, &tb, &ta);
+        triangle_tile(order[pos], &tb, &ta);
         const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
         const int row = lane & 15;
         const int a_base = ta * 16, b_tile = tb * 16, b_base = b_tile + 4 * wave;
@@ -812,17 +827,17 @@ void launch_wc(const Dims &d, const Bufs &b, hipStream_t s) {
                                b.flags, d.zoff);
         }
         if (d.lr_rank > 0) {
-            launch_fill_i32(b.wc_queue, 1, 0, s, d.batch, d.zoff);
+            launch_fill_i32(b.wc_queue, kWcQueues, 0, s, d.batch, d.zoff);
             hipLaunchKernelGGL(d.zoff ? k_wc_sep<true> : k_wc_sep<false>, dim3(std::min(blocks, d.wc_grid), 1, d.batch), dim3(256), 0, s, b.psi1,
                                b.psi2, b.lr_u, b.lr_v, (d.lr_rank + 15) / 16 * 16, d.nr, d.nR, scale, b.Wc, Np,
-                               d.fp32_residual ? 1 : 0, blocks, b.wc_queue, b.flags, d.zoff);
+                               d.fp32_residual ? 1 : 0, blocks, b.wc_queue, b.wc_order, b.flags, d.zoff);
         }
     } else if (d.prec == 2) {
         // separable: the whole contraction through the sum of products (assigns Wc)
-        launch_fill_i32(b.wc_queue, 1, 0, s, d.batch, d.zoff);
+        launch_fill_i32(b.wc_queue, kWcQueues, 0, s, d.batch, d.zoff);
         hipLaunchKernelGGL(d.zoff ? k_wc_sep<true> : k_wc_sep<false>, dim3(std::min(blocks, d.wc_grid), 1, d.batch), dim3(256), 0, s, b.psi1, b.psi2,
                            b.lr_u, b.lr_v, (d.lr_rank + 15) / 16 * 16, d.nr, d.nR, scale, b.Wc, Np, 0, blocks,
-                           b.wc_queue, b.flags, d.zoff);
+                           b.wc_queue, b.wc_order, b.flags, d.zoff);
     } else {
         split(WcChunk<double>::JT, &nparts, &spq);
         launch_fill_i32(b.wc_queue, kWcQueues + kWcQueues * spq, 0, s, d.batch, d.zoff);

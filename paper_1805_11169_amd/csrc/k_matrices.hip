@@ -259,9 +259,6 @@ struct WcChunk {
     static constexpr int LDA = 528 / CPLX;                 // padded psi1 row (entries): 33 slots
     static constexpr int LDW = sizeof(T) == 8 ? 34 : 80;   // padded W_c chunk row (entries)
     static constexpr bool INTERLEAVE = sizeof(T) == 4;
-    // operands of the next i-quad read before this quad's matrix products
-    // (FP64; the FP32 kernel has no registers to spare for them)
-    static constexpr bool PREFETCH = sizeof(T) == 8;
     static constexpr int ALOADS = (32 * 33 + 63) / 64;                 // loads per psi1 buffer
     static constexpr int AROWS = (64 * 16 * ALOADS + 527) / 528;       // rows the buffer holds
     static constexpr int WSLOTS = LDW * sizeof(T) / 16;                // slots per W_c row
@@ -439,8 +436,8 @@ __global__ void __launch_bounds__(256, 2) k_wc(const typename WcTraits<T>::cplx 
                         for (int jf = 0; jf < JF; ++jf) acc[bb][c][jf] = acc4{0, 0, 0, 0};
             }
             if (step + 1 < nsteps) fetch(step + 1, An, Wn);
-            // (FP64) operands of i-quad s + 1 are read from LDS while the
-            // matrix cores work on quad s
+            // operands of i-quad s + 1 are read from LDS while the matrix
+            // cores work on quad s
             C2 xa, xb[4];
             T w[JF];
             auto operands = [&](int s, C2 &oa, C2 (&ob)[4], T (&ow)[JF]) __attribute__((always_inline)) {
@@ -456,7 +453,7 @@ __global__ void __launch_bounds__(256, 2) k_wc(const typename WcTraits<T>::cplx 
             for (int s = 0; s < QS; ++s) {
                 C2 na, nb[4];
                 T nw[JF];
-                if (CK::PREFETCH && s + 1 < QS) operands(s + 1, na, nb, nw);
+                if (s + 1 < QS) operands(s + 1, na, nb, nw);
     #pragma unroll
                 for (int bb = 0; bb < 4; ++bb) {
                     const C2 p = cmulc(xb[bb], xa);   // conj(psi1^b_i) psi1^a_i
@@ -467,7 +464,6 @@ __global__ void __launch_bounds__(256, 2) k_wc(const typename WcTraits<T>::cplx 
                         acc[bb][1][jf] = mfma(pi, w[jf], acc[bb][1][jf]);
                     }
                 }
-                if (!CK::PREFETCH && s + 1 < QS) operands(s + 1, na, nb, nw);
                 if (s + 1 < QS) {
                     xa = na;
     #pragma unroll

@@ -243,8 +243,8 @@ __device__ inline void triangle_tile(int t, int *tb, int *ta) {
 // and load; no staging registers, four times fewer load instructions than
 // 4-byte loads).  A load fills 64 consecutive 16-byte slots of a padded
 // buffer: psi1 rows of 32 slots plus a pad slot (528 bytes), W_c rows of
-// 16 slots plus one (FP64) or 8 plus 4 (FP32), so that the operand reads stay
-// free of bank conflicts; a lane whose slot is padding, or past the tile,
+// 16 slots plus one (FP64) or plus four (FP32), so that the operand reads
+// stay free of bank conflicts; a lane whose slot is padding, or past the tile,
 // loads an in-bounds entry that is never read.  FP32 takes the i of a chunk
 // interleaved over the four lane quarters (i = 4 s + quarter at quad s), FP64
 // in four consecutive runs (i = QS quarter + s).  FP32 accumulators take half

@@ -28,8 +28,9 @@ extern "C" {
 typedef struct icwf_exact icwf_exact;
 
 /* Bytes of device workspace icwf_exact_create needs (0 if the configuration
- * is invalid): the state, one scratch copy, the potential and kinetic phase
- * tables (four n_r n_R complex128 arrays) and the BO states. */
+ * is invalid): the state, one scratch copy and the potential phase table
+ * (three n_r n_R complex128 arrays), the kinetic phase (one factor per
+ * coordinate) and the BO states. */
 size_t icwf_exact_workspace_bytes(const icwf_config *cfg);
 
 /* Create a grid propagation from Psi_0.
@@ -46,7 +47,8 @@ size_t icwf_exact_workspace_bytes(const icwf_config *cfg);
 icwf_status icwf_exact_create(const icwf_config *cfg, const double *psi0, const double *bo_states, void *workspace,
                               size_t ws_bytes, void *hip_stream, icwf_exact **out);
 
-/* Enqueue n_steps >= 0 steps of dt (three kernels each); does not wait. */
+/* Enqueue n_steps >= 0 steps of dt (2 n_steps + 1 kernels: the half-step
+ * phases of consecutive steps meet in one pass); does not wait. */
 icwf_status icwf_exact_step(icwf_exact *ex, int64_t n_steps);
 
 /* Wait for the enqueued work, then the observables of Psi at the current

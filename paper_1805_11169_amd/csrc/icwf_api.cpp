@@ -908,7 +908,8 @@ icwf::ExactBufs carve_exact(const icwf_config &c, char *base, size_t *total, dou
     e.psi = L.take<double2>(nr * nR);
     e.tmp = L.take<double2>(nr * nR);
     e.half = L.take<double2>(nr * nR);
-    e.kinT = L.take<double2>(nr * nR);
+    e.kin_r = L.take<double2>(nr);
+    e.kin_R = L.take<double2>(nR);
     e.tw_r = L.take<double2>(nr);
     e.tw_R = L.take<double2>(nR);
     *bo = L.take<double>(std::max<size_t>(1, nR * nbo * nr));
@@ -952,7 +953,7 @@ icwf_status icwf_exact_create(const icwf_config *cfg, const double *psi0, const 
 
     const double hr = (cfg->r_max - cfg->r_min) / nr, hR = (cfg->R_max - cfg->R_min) / nR, dt = cfg->dt;
     // half-step phase of the full interaction W = V_1 + V_2 + W_c on the grid
-    std::vector<double2> half(np), kinT(np), tw_r(nr), tw_R(nR);
+    std::vector<double2> half(np), kin_r(nr), kin_R(nR), tw_r(nr), tw_R(nR);
     for (int i = 0; i < nr; ++i) {
         const double r = cfg->r_min + i * hr;
         for (int j = 0; j < nR; ++j) {
@@ -962,18 +963,19 @@ icwf_status icwf_exact_create(const icwf_config *cfg, const double *psi0, const 
             half[(size_t)i * nR + j] = make_double2(std::cos(-0.5 * dt * w), std::sin(-0.5 * dt * w));
         }
     }
-    // kinetic phase of both species, transposed ([k_R][k_r]), times 1/(n_r n_R)
-    // (the normalisation of the inverse transform; exact, both are powers of two)
+    // kinetic phase of both species, a product of one factor per species; the
+    // nuclear one carries 1/(n_r n_R) (the normalisation of the inverse
+    // transform; exact, both are powers of two)
     const double inv = 1.0 / ((double)nr * nR);
+    for (int kr = 0; kr < nr; ++kr) {
+        const int mr = (kr <= nr / 2) ? kr : kr - nr;
+        const double kw = 2.0 * M_PI * mr / (nr * hr), ph = -dt * kw * kw / (2.0 * cfg->m_r);
+        kin_r[kr] = make_double2(std::cos(ph), std::sin(ph));
+    }
     for (int kR = 0; kR < nR; ++kR) {
         const int mR = (kR <= nR / 2) ? kR : kR - nR;
-        const double kwR = 2.0 * M_PI * mR / (nR * hR);
-        for (int kr = 0; kr < nr; ++kr) {
-            const int mr = (kr <= nr / 2) ? kr : kr - nr;
-            const double kwr = 2.0 * M_PI * mr / (nr * hr);
-            const double ph = -dt * (kwr * kwr / (2.0 * cfg->m_r) + kwR * kwR / (2.0 * cfg->m_R));
-            kinT[(size_t)kR * nr + kr] = make_double2(std::cos(ph) * inv, std::sin(ph) * inv);
-        }
+        const double kw = 2.0 * M_PI * mR / (nR * hR), ph = -dt * kw * kw / (2.0 * cfg->m_R);
+        kin_R[kR] = make_double2(std::cos(ph) * inv, std::sin(ph) * inv);
     }
     for (int k = 0; k < nr; ++k) tw_r[k] = make_double2(std::cos(-2.0 * M_PI * k / nr), std::sin(-2.0 * M_PI * k / nr));
     for (int k = 0; k < nR; ++k) tw_R[k] = make_double2(std::cos(-2.0 * M_PI * k / nR), std::sin(-2.0 * M_PI * k / nR));
@@ -990,7 +992,8 @@ icwf_status icwf_exact_create(const icwf_config *cfg, const double *psi0, const 
         return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st) == hipSuccess;
     };
     bool ok = hipMemsetAsync(workspace, 0, total, st) == hipSuccess && copy(x->e.psi, psi0, sizeof(double2) * np) &&
-              copy(x->e.half, half.data(), sizeof(double2) * np) && copy(x->e.kinT, kinT.data(), sizeof(double2) * np) &&
+              copy(x->e.half, half.data(), sizeof(double2) * np) && copy(x->e.kin_r, kin_r.data(), sizeof(double2) * nr) &&
+              copy(x->e.kin_R, kin_R.data(), sizeof(double2) * nR) &&
               copy(x->e.tw_r, tw_r.data(), sizeof(double2) * tw_r.size()) &&
               copy(x->e.tw_R, tw_R.data(), sizeof(double2) * tw_R.size());
     if (ok && nbo > 0) ok = copy(x->bo, bo_states, sizeof(double) * (size_t)nR * nbo * nr);
@@ -1005,7 +1008,7 @@ icwf_status icwf_exact_create(const icwf_config *cfg, const double *psi0, const 
 
 icwf_status icwf_exact_step(icwf_exact *x, int64_t n_steps) {
     if (!x || n_steps < 0) return fail(nullptr, ICWF_EINVAL, "bad arguments to icwf_exact_step");
-    for (int64_t k = 0; k < n_steps; ++k) icwf::launch_exact_step(x->cfg.n_r, x->cfg.n_R, x->e, x->stream);
+    icwf::launch_exact_steps(x->cfg.n_r, x->cfg.n_R, x->e, n_steps, x->stream);
     if (hipGetLastError() != hipSuccess) return fail(nullptr, ICWF_EDEVICE, "exact step launch failed");
     x->step += n_steps;
     return ICWF_OK;

@@ -223,13 +223,16 @@ void launch_grid_observables(const double2 *Psi, int nr, int nR, double hr, doub
 // One Strang step of the full two-dimensional wavefunction (Eqs. 1-2 on the
 // product grid; the reference the ansatz converges to):
 //   Psi <- e^{-i W dt/2} IFFT2[ e^{-i T dt} FFT2[ e^{-i W dt/2} Psi ] ].
-// psi [nr][nR] in place, tmp [nR][nr] scratch, half [nr][nR] = e^{-i W dt/2},
-// kinT [nR][nr] = e^{-i (k_r^2/2m_r + k_R^2/2m_R) dt} / (nr nR) (transposed),
-// tw_r [nr], tw_R [nR] = e^{-2 pi i k/n}.  nr, nR powers of two in [32, 4096].
+// psi [nr][nR] in place, tmp [nR][nr] scratch, half [nr][nR] = e^{-i W dt/2};
+// the kinetic phase e^{-i (k_r^2/2m_r + k_R^2/2m_R) dt} / (nr nR) is the
+// product kin_r [nr] x kin_R [nR] (e^{-i k_r^2 dt/2m_r} and
+// e^{-i k_R^2 dt/2m_R} / (nr nR)); tw_r [nr], tw_R [nR] = e^{-2 pi i k/n}.
+// nr, nR powers of two in [32, 4096].
 struct ExactBufs {
-    double2 *psi, *tmp, *half, *kinT, *tw_r, *tw_R;
+    double2 *psi, *tmp, *half, *kin_r, *kin_R, *tw_r, *tw_R;
 };
-void launch_exact_step(int nr, int nR, const ExactBufs &e, hipStream_t s);
+// nsteps >= 0 whole steps (2 nsteps + 1 passes over the state).
+void launch_exact_steps(int nr, int nR, const ExactBufs &e, int64_t nsteps, hipStream_t s);
 
 // FP32 copy of psi1 (mixed form; the propagation keeps it current afterwards).
 void launch_psi1_f32(const Dims &d, const Bufs &b, hipStream_t s);

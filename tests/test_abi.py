@@ -114,11 +114,12 @@ def test_too_small_workspace_and_missing_inputs():
 
 
 def test_exact_workspace_and_invalid_configs():
-    """The grid propagator's footprint is four n_r n_R complex128 arrays plus
-    small tables; an invalid configuration sizes to 0 and fails creation."""
+    """The grid propagator's footprint is three n_r n_R complex128 arrays (the
+    state, its transposed copy, the potential phase) plus tables of n_r and
+    n_R entries; an invalid configuration sizes to 0 and fails creation."""
     cfg = _cfg(n_r=512, n_R=256, n_bo=0)
     ex = icwf.lib().icwf_exact_workspace_bytes(ctypes.byref(cfg))
-    assert 4 * 16 * 512 * 256 <= ex < 4 * 16 * 512 * 256 + 256 * 1024
+    assert 3 * 16 * 512 * 256 <= ex < 3 * 16 * 512 * 256 + 256 * 1024
     bad = _cfg(n_r=500)
     assert icwf.lib().icwf_exact_workspace_bytes(ctypes.byref(bad)) == 0
     h = ctypes.c_void_p()

@@ -101,6 +101,25 @@ def test_zero_steps_and_norm_conservation():
     assert abs(n1 - n0) < 1e-12 * n0
 
 
+def test_steps_split_across_calls_match_one_call():
+    """A call of n steps joins the closing half-step phase of each step and the
+    opening one of the next in one pass; calls of 3 + 4 + 1 steps (each ending
+    with its own closing pass) give the state of one call of 8, to a few
+    roundings, on a grid with both transform shapes (two- and three-pass)."""
+    wl = inputs.gaussian_basis(4, n_r=256, n_R=512, model=inputs.MODEL_SHIN_METIU, seed=36)
+    psi0 = _correlated_start(wl, 36)
+    cfg = icwf.config_from_workload(wl)
+    one = icwf.ExactPropagator(cfg, psi0)
+    one.step(8)
+    split = icwf.ExactPropagator(cfg, psi0)
+    for n in (3, 4, 1):
+        split.step(n)
+    a, b = one.psi(), split.psi()
+    one.close()
+    split.close()
+    assert rel_max(b, a) < 1e-14
+
+
 def test_icwf_tracks_the_exact_propagation():
     """The method against what it approximates: Shin-Metiu product start,
     512 x 256, N = 256 trajectories, 1000 steps (100 a.u.).  ICWF's

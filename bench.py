@@ -354,7 +354,7 @@ def main():
         "sh_build_tflops_summed_kernel_time": build_tflops_summed,
         "propagation": {"achieved_gbs": prop_gbs, "peak_gbs": HBM_PEAK_GBS, "frac": prop_gbs / HBM_PEAK_GBS,
                         "avg_launch_ms": ms_pr / n_pr},
-        "kernel_ms_per_step": {k: (ms / n if n else None) for k, (n, ms) in kt.items()},
+        "kernel_ms_per_step": {k: (ms / n_wc if n else None) for k, (n, ms) in kt.items()},
         "observables_ms": obs_ms,
         "final_norm": obs["norm"],
         "ms_per_step_graph_replay": elapsed_graph / args.steps * 1e3,

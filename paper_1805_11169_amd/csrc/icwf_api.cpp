@@ -285,8 +285,9 @@ void timed(icwf_sim *s, const char *name, hipStream_t st, F fn) {
 // from kOverlapMinN padded trajectories on, the step forks, the side stream
 // assembles S and factors S + eps I (in the FP64 form, where the contraction
 // is the longest branch, after computing the single-species integrals
-// itself) while st contracts W_c; st then waits for the side stream,
-// assembles K and runs the RK4 stages.  The persistent contraction leaves CU slots free for the side
+// itself) while st contracts W_c (in the separable form, whose contraction is
+// short, followed by the coupling integrals); st then waits for the side
+// stream, assembles K and runs the RK4 stages.  The persistent contraction leaves CU slots free for the side
 // stream's latency-bound kernels.  Smaller simulations (whose contraction
 // does not fill the GPU, and which a server runs many at a time) stay on one
 // stream: event waits between streams would serialise other simulations'
@@ -311,19 +312,24 @@ void enqueue_step(icwf_sim *s, const Dims &d, int parity, hipStream_t st, hipStr
     // the fork
     const bool roomy = d.prec != ICWF_PREC_SEPARABLE && (size_t)d.nr * d.nR >= 256 * (size_t)s->Np;
     const hipStream_t ss = fork && ((d.prec == ICWF_PREC_FP64 && !d.sinv) || roomy) ? side : st;
-    auto single_species = [&] {
+    // the separable form's contraction is the short branch: ahead of the fork
+    // only the overlaps (all that S needs), the coupling integrals (needed by
+    // K only) on st after the contraction, while the factorisation stream
+    // still runs
+    const bool late_couplings = fork && ss == st && d.prec == ICWF_PREC_SEPARABLE;
+    auto single_species = [&](hipStream_t q, int parts) {
         // with Heun trajectories the integrals at x_k+1 wait for the corrector
-        timed(s, "zgemm", ss, [&] {
-            icwf::launch_cond_kets(d, b, ss, !heun);
-            icwf::launch_single_species(d, b, !heun, ss);
+        timed(s, "zgemm", q, [&] {
+            if (parts & icwf::kSingleCouplings) icwf::launch_cond_kets(d, b, q, !heun);
+            icwf::launch_single_species(d, b, !heun, q, parts);
         });
     };
-    if (ss == st) single_species();
+    if (ss == st) single_species(st, late_couplings ? icwf::kSingleOverlaps : icwf::kSingleAll);
     if (fork) {
         (void)hipEventRecord(s->ev_fork, st);
         (void)hipStreamWaitEvent(side, s->ev_fork, 0);
     }
-    if (ss != st) single_species();
+    if (ss != st) single_species(ss, icwf::kSingleAll);
     timed(s, "cholesky", side, [&] {
         icwf::launch_assemble(d, b, parity, icwf::kAssembleS, side);
         if (d.sinv)
@@ -334,6 +340,7 @@ void enqueue_step(icwf_sim *s, const Dims &d, int parity, hipStream_t st, hipStr
     });
     if (fork) (void)hipEventRecord(s->ev_join, side);
     timed(s, "wc_contract", st, [&] { icwf::launch_wc(d, b, st); });
+    if (late_couplings) single_species(st, icwf::kSingleCouplings);
     if (fork) (void)hipStreamWaitEvent(st, s->ev_join, 0);
     timed(s, "assemble", st, [&] {
         icwf::launch_assemble(d, b, parity, heun ? icwf::kAssembleKminus : icwf::kAssembleK, st);

@@ -169,9 +169,13 @@ void launch_cond_kets(const Dims &d, const Bufs &b, hipStream_t s, bool next = t
 // G1b, G2b alone, at (r_new, R_new).
 void launch_cond_kets_next(const Dims &d, const Bufs &b, hipStream_t s);
 
-// Batched h * conj(X) Y^T complex products: S1, S2, E1a, E2a and, with
-// both_conditionings, E1b, E2b.
-void launch_single_species(const Dims &d, const Bufs &b, bool both_conditionings, hipStream_t s);
+// Batched h * conj(X) Y^T complex products: the overlaps S1, S2 (parts &
+// kSingleOverlaps: all that S needs) and the coupling integrals E1a, E2a
+// and, with both_conditionings, E1b, E2b (parts & kSingleCouplings: needed by
+// K only).
+enum SingleParts { kSingleOverlaps = 1, kSingleCouplings = 2, kSingleAll = 3 };
+void launch_single_species(const Dims &d, const Bufs &b, bool both_conditionings, hipStream_t s,
+                           int parts = kSingleAll);
 // E1b, E2b alone.
 void launch_single_species_next(const Dims &d, const Bufs &b, hipStream_t s);
 

@@ -754,7 +754,7 @@ void launch_cond_kets_next(const Dims &d, const Bufs &b, hipStream_t s) {
                        d.R_min, d.hR, b.r_new, b.r_new, 2, d.mp, b.G2b, nullptr, Np, b.flags, d.zoff, d.mpd);
 }
 
-void launch_single_species(const Dims &d, const Bufs &b, bool both, hipStream_t s) {
+void launch_single_species(const Dims &d, const Bufs &b, bool both, hipStream_t s, int parts) {
     const int Np = padded(d.N);
     ZBatch zb{};
     int c = 0;
@@ -766,14 +766,19 @@ void launch_single_species(const Dims &d, const Bufs &b, bool both, hipStream_t 
         zb.scale[c] = sc;
         ++c;
     };
-    add(b.psi1, b.psi1, b.S1, d.nr, d.hr);
-    add(b.psi2, b.psi2, b.S2, d.nR, d.hR);
-    add(b.psi1, b.G1a, b.E1a, d.nr, d.hr);
-    add(b.psi2, b.G2a, b.E2a, d.nR, d.hR);
-    if (both) {
-        add(b.psi1, b.G1b, b.E1b, d.nr, d.hr);
-        add(b.psi2, b.G2b, b.E2b, d.nR, d.hR);
+    if (parts & kSingleOverlaps) {
+        add(b.psi1, b.psi1, b.S1, d.nr, d.hr);
+        add(b.psi2, b.psi2, b.S2, d.nR, d.hR);
     }
+    if (parts & kSingleCouplings) {
+        add(b.psi1, b.G1a, b.E1a, d.nr, d.hr);
+        add(b.psi2, b.G2a, b.E2a, d.nR, d.hR);
+        if (both) {
+            add(b.psi1, b.G1b, b.E1b, d.nr, d.hr);
+            add(b.psi2, b.G2b, b.E2b, d.nR, d.hR);
+        }
+    }
+    if (c == 0) return;
     hipLaunchKernelGGL(d.zoff ? k_zgemm<true> : k_zgemm<false>, dim3(Np / kZT, Np / kZT, c * d.batch), dim3(256), 0, s,
                        zb, Np, b.flags, c, d.zoff);
 }

@@ -144,13 +144,16 @@ def test_forked_step_with_the_integrals_beside_the_contraction():
     """N = 1024 on a 512 x 512 grid: the dense contraction is long enough that
     the single-species integrals run on the factorisation stream beside it.
     Replay and eager launches agree bitwise; the result agrees with the
-    separable form (FP64 throughout, integrals ahead of the fork) at the FP64
-    bar."""
+    separable form (FP64 throughout; its overlaps ahead of the fork, its
+    coupling integrals after its short contraction, while the factorisation
+    stream runs) at the FP64 bar, whose replays and eager launches agree
+    bitwise as well."""
     w = inputs.gaussian_basis(1024, n_r=512, n_R=512, seed=24)
     print(f"[case] {w.name}: integrals on the side stream, 3 steps", flush=True)
     a = _run(w, 3)
     assert _same(a, _run(w, 3, timing=True))
     sep = _run(w, 3, precision=icwf.PREC_SEPARABLE)
+    assert _same(sep, _run(w, 3, precision=icwf.PREC_SEPARABLE, timing=True))
     for key in ("r", "R"):
         assert np.max(np.abs(a[key] - sep[key])) < 1e-10 * max(1.0, np.max(np.abs(a[key]))), key
     assert rel_max(sep["psi1"], a["psi1"]) < 1e-10

@@ -288,7 +288,7 @@ def main():
     elapsed = max(time.perf_counter() - t0, elapsed_graph)
 
     kt = {}
-    for name in ("wc_contract", "zgemm", "velocity", "propagate", "assemble", "cholesky", "rk4"):
+    for name in ("wc_contract", "zgemm", "velocity", "propagate", "assemble", "cholesky", "inverse", "rk4"):
         n, ms = sim.kernel_time(name)
         kt[name] = (n, ms)
     sim.set_timing(False)
@@ -319,7 +319,7 @@ def main():
     # longer of the two; otherwise they run one after the other.
     Np = (N + 63) // 64 * 64
     dense = args.precision != "separable"
-    sinv = Np >= 1024 and (Np & (Np - 1)) == 0 and dense
+    sinv = Np >= 1024 and (Np & (Np - 1)) == 0
     roomy = dense and nr * nR >= 256 * Np
     concurrent = Np >= 1024 and ((args.precision == "fp64" and not sinv) or roomy)
     build_ms = max(ms_wc, ms_zg) if concurrent else ms_wc + ms_zg

@@ -85,9 +85,8 @@ typedef enum {
 /* How the RK4 stages solve (S + eps I) x = r (Eq. 8).  Both factor S + eps I
  * by Cholesky at every step; they differ in what the stages apply. */
 typedef enum {
-    ICWF_SOLVER_AUTO = 0,       /* explicit inverses where they hide beside the
-                                   contraction (FP64 and mixed forms, from 1024
-                                   padded trajectories, a power of two), else
+    ICWF_SOLVER_AUTO = 0,       /* explicit inverses from 1024 padded
+                                   trajectories (a power of two), else
                                    triangular solves                             */
     ICWF_SOLVER_TRIANGULAR = 1, /* forward and backward substitution with the factor */
     ICWF_SOLVER_INVERSE = 2     /* (S + eps I)^-1 = L^-H L^-1 formed per step, each

@@ -330,11 +330,15 @@ void enqueue_step(icwf_sim *s, const Dims &d, int parity, hipStream_t st, hipStr
         (void)hipStreamWaitEvent(side, s->ev_fork, 0);
     }
     if (ss != st) single_species(ss, icwf::kSingleAll);
+    // with the factorisations as the longer branch (the separable form), the
+    // explicit inverses wait for the join and then take the whole GPU on st
+    // instead of stretching the second stream further
+    const bool late_inverses = late_couplings && d.sinv;
     timed(s, "cholesky", side, [&] {
         icwf::launch_assemble(d, b, parity, icwf::kAssembleS, side);
         if (d.sinv)
             icwf::launch_cholesky(d, b, b.Lmid, b.L[1 - parity], b.Linvmid, b.Linv[1 - parity], 2, side, b.Finvmid,
-                                  b.Finv[1 - parity], b.Hinvmid, b.Hinv[1 - parity]);
+                                  b.Finv[1 - parity], b.Hinvmid, b.Hinv[1 - parity], !late_inverses);
         else
             icwf::launch_cholesky(d, b, b.Lmid, b.L[1 - parity], b.Linvmid, b.Linv[1 - parity], 2, side);
     });
@@ -342,6 +346,11 @@ void enqueue_step(icwf_sim *s, const Dims &d, int parity, hipStream_t st, hipStr
     timed(s, "wc_contract", st, [&] { icwf::launch_wc(d, b, st); });
     if (late_couplings) single_species(st, icwf::kSingleCouplings);
     if (fork) (void)hipStreamWaitEvent(st, s->ev_join, 0);
+    if (late_inverses)
+        timed(s, "inverse", st, [&] {
+            icwf::launch_factor_inverses(d, b, b.Lmid, b.L[1 - parity], 2, st, b.Finvmid, b.Finv[1 - parity],
+                                         b.Hinvmid, b.Hinv[1 - parity]);
+        });
     timed(s, "assemble", st, [&] {
         icwf::launch_assemble(d, b, parity, heun ? icwf::kAssembleKminus : icwf::kAssembleK, st);
     });

@@ -124,16 +124,19 @@ struct BatchTable {
 // Writes the first n offsets into tab (device) in stream order.
 void launch_set_table(long long *tab, const BatchTable &t, int n, hipStream_t s);
 
-// RK4 through explicit inverses of S + eps I.  Automatic choice: where the
-// factorisations run on the second stream beside a contraction long enough
-// to hide the inversion (FP64 and mixed forms, from 1024 padded
-// trajectories).  Either way Np must be a power of two, so that the block
-// inversion halves evenly.  solver: 0 automatic, 1 triangular, 2 inverse.
+// RK4 through explicit inverses of S + eps I.  Automatic choice: from 1024
+// padded trajectories, where the factorisations run on the second stream
+// (the inversion then follows them there beside the FP64 or mixed
+// contraction, or, in the separable form, whose contraction is the shorter
+// branch, runs on the main stream after the join); each stage is then a few
+// matrix-vector products instead of two chains of dependent block solves.
+// Either way Np must be a power of two, so that the block inversion halves
+// evenly.  solver: 0 automatic, 1 triangular, 2 inverse.
 inline bool use_sinv(int Np, int precision, int solver) {
     const bool pow2 = (Np & (Np - 1)) == 0;
     if (solver == 2) return pow2;
     if (solver == 1) return false;
-    return Np >= 1024 && pow2 && precision != 2;
+    return Np >= 1024 && pow2;
 }
 
 // ---- launchers (each defined next to its kernels) -------------------------------------------
@@ -199,10 +202,16 @@ void launch_assemble(const Dims &d, const Bufs &b, int parity, AssemblePart part
 
 // In-place lower Cholesky of `count` matrices (A0, A1), each Np x Np, and the
 // inverses of their 64 x 64 diagonal blocks into X0, X1 ([Np][64]).  With
-// S0 non-null (d.sinv), also (L L^H)^-1 of each factor into S0, S1 ([Np][Np]).
+// F0 non-null (d.sinv), the diagonal blocks of L^-1 go into F0, F1 as well
+// and, with `inverses`, launch_factor_inverses completes them.
 void launch_cholesky(const Dims &d, const Bufs &b, double2 *A0, double2 *A1, double2 *X0, double2 *X1, int count,
                      hipStream_t s, double2 *F0 = nullptr, double2 *F1 = nullptr, double2 *H0 = nullptr,
-                     double2 *H1 = nullptr);
+                     double2 *H1 = nullptr, bool inverses = true);
+// The explicit inverses of `count` factors (A0, A1) whose diagonal blocks of
+// L^-1 are in F0, F1 (launch_cholesky): L^-1 into F0, F1 ([Np][Np], by block
+// recursion) and L^-H into H0, H1.
+void launch_factor_inverses(const Dims &d, const Bufs &b, const double2 *A0, const double2 *A1, int count,
+                            hipStream_t s, double2 *F0, double2 *F1, double2 *H0, double2 *H1);
 
 // One RK4 step of Eq. 8 with the factors / matrices of the given parity.
 void launch_rk4(const Dims &d, const Bufs &b, int parity, hipStream_t s);

@@ -911,7 +911,7 @@ void launch_assemble(const Dims &d, const Bufs &b, int parity, AssemblePart part
 }
 
 void launch_cholesky(const Dims &d, const Bufs &b, double2 *A0, double2 *A1, double2 *X0, double2 *X1, int count,
-                     hipStream_t s, double2 *F0, double2 *F1, double2 *H0, double2 *H1) {
+                     hipStream_t s, double2 *F0, double2 *F1, double2 *H0, double2 *H1, bool inverses) {
     const int Np = padded(d.N);
     for (int kb = 0; kb < Np; kb += NB) {
         const int below = Np - kb - NB;
@@ -928,7 +928,12 @@ void launch_cholesky(const Dims &d, const Bufs &b, double2 *A0, double2 *A1, dou
                        b.flags, d.zoff);
     hipLaunchKernelGGL(k_tri_inv, dim3(Np / NB, count, d.batch), dim3(256), 0, s, A0, A1, X0, X1, F0, F1, Np, b.flags,
                        d.zoff);
-    if (!F0) return;
+    if (F0 && inverses) launch_factor_inverses(d, b, A0, A1, count, s, F0, F1, H0, H1);
+}
+
+void launch_factor_inverses(const Dims &d, const Bufs &b, const double2 *A0, const double2 *A1, int count,
+                            hipStream_t s, double2 *F0, double2 *F1, double2 *H0, double2 *H1) {
+    const int Np = padded(d.N);
     double2 *Fs[2] = {F0, F1 ? F1 : F0};
     // X = L^-1 by block recursion, [[A, 0], [C, D]]^-1 = [[A', 0], [-D' C A', D']],
     // from the 64 x 64 diagonal inverses up: at block size h, the Np / (2 h) pairs

@@ -65,10 +65,12 @@ def test_workspace_holds_the_explicit_inverses_only_where_they_are_used():
     tri = icwf.workspace_bytes(_cfg(n_traj=1024, solver=icwf.SOLVER_TRIANGULAR))
     assert icwf.workspace_bytes(_cfg(n_traj=1024, solver=icwf.SOLVER_INVERSE)) == auto
     assert auto >= tri + extra(1024)
-    # the separable form keeps the triangular solves unless asked
+    # the separable form too, from 1024 padded trajectories
     sep = icwf.workspace_bytes(_cfg(n_traj=1024, precision=icwf.PREC_SEPARABLE))
     assert icwf.workspace_bytes(_cfg(n_traj=1024, precision=icwf.PREC_SEPARABLE,
-                                     solver=icwf.SOLVER_INVERSE)) >= sep + extra(1024)
+                                     solver=icwf.SOLVER_INVERSE)) == sep
+    assert sep >= icwf.workspace_bytes(_cfg(n_traj=1024, precision=icwf.PREC_SEPARABLE,
+                                            solver=icwf.SOLVER_TRIANGULAR)) + extra(1024)
     # padded N = 192 is not a power of two: automatic falls back to the triangular solves
     assert icwf.workspace_bytes(_cfg(n_traj=150)) == icwf.workspace_bytes(_cfg(n_traj=150, solver=1))
 

@@ -45,10 +45,10 @@ HBM_PEAK_GBS = 8000.0
 # any change the traffic is reported as null until measured again.
 TRAFFIC = {
     "sm_n1024": {
-        "sources_sha256_16": "a2dc6dde5c1beaa8",
-        "fp64": 349509120.0,        # k_wc<double>: fetch 159697.2 KiB x2, write 21923.1 KiB
-        "mixed": 308852633.6,       # k_wc<float> + k_wc_sep: fetch 78834.2 + 49954.2 KiB x2, write 35651.8 + 8385.3 KiB
-        "separable": 161184972.8,   # k_wc_sep (K = 29): fetch 74510.9 KiB x2, write 8385.4 KiB
+        "sources_sha256_16": "f7e36e1c54569dda",
+        "fp64": 348255744.0,        # k_wc<double>: fetch 159085.2 KiB x2, write 21923.1 KiB
+        "mixed": 309099520.0,       # k_wc<float> + k_wc_sep: fetch 79068.6 + 49840.5 KiB x2, write 35651.5 + 8385.3 KiB
+        "separable": 162296422.4,   # k_wc_sep (K = 28): fetch 75053.6 KiB x2, write 8385.4 KiB
     },
 }
 TRAFFIC_SOURCES = ("paper_1805_11169_amd/csrc/k_matrices.hip", "paper_1805_11169_amd/csrc/icwf_device.hpp",

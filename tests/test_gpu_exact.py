@@ -145,10 +145,24 @@ def test_icwf_tracks_the_exact_propagation():
 
 @pytest.mark.parametrize("n_r,n_R", [(64, 1024), (32, 2048), (32, 4096)])
 def test_long_nuclear_grids(n_r, n_R):
-    """n_R = 1024, 2048, 4096: the transposing R pass takes 4, 2 and 1 grid
-    rows per work-group there (8 on the shorter grids); 5 steps against the
-    oracle on a narrow r grid."""
+    """n_R = 1024, 2048, 4096 on a narrow r grid (few grid rows: the R passes
+    take one row per work-group, 64, 128 and 256 threads); 5 steps against
+    the oracle."""
     wl = inputs.gaussian_basis(4, n_r=n_r, n_R=n_R, r_box=(-30.0, 30.0), R_box=(-12.0, 12.0),
                                model=inputs.MODEL_SHIN_METIU, seed=36)
     print(f"[case] exact {n_r}x{n_R}: 5 steps", flush=True)
     _compare(wl, _correlated_start(wl, 36), 5)
+
+
+@pytest.mark.parametrize("n_r,n_R", [(1024, 32), (2048, 32), (1024, 1024), (512, 2048), (2048, 512)])
+def test_long_electronic_grids_and_wide_passes(n_r, n_R):
+    """The r pass on 1024 and 2048 points (three-pass transforms with a last
+    radix of 4 and 8) with one row per work-group (n_R = 32), and, from 256
+    work-groups on, the wide variants: four 1024-point rows per work-group in
+    both passes (1024 x 1024), two 2048-point rows in the R passes and eight
+    512-point rows in the r pass (512 x 2048), and the converse (2048 x 512);
+    3 steps against the oracle."""
+    wl = inputs.gaussian_basis(4, n_r=n_r, n_R=n_R, r_box=(-30.0, 30.0), R_box=(-12.0, 12.0),
+                               model=inputs.MODEL_SHIN_METIU, seed=37)
+    print(f"[case] exact {n_r}x{n_R}: 3 steps", flush=True)
+    _compare(wl, _correlated_start(wl, 37), 3)

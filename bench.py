@@ -242,8 +242,8 @@ def other_precision(wl, precision, steps, warmup, fp64_ms):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU sharding is a design "
-              "in DESIGN.md, not a measured path", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}): the sharding over GPUs is a design, "
+              "not a measured path", file=sys.stderr)
         sys.exit(2)
     import torch
 

@@ -12,7 +12,7 @@
 //
 // Cholesky (lower, in place, two matrices per launch): right-looking with
 // 64-wide panels.  Each k_chol_panel work-group eliminates, column by column,
-// the 128 x 64 slab of the diagonal block and 64 of the rows below it, held
+// the 96 x 64 slab of the diagonal block and 32 of the rows below it, held
 // in registers (lane = column, wave = 8 rows; the pivot column through LDS,
 // one barrier per column); every work-group factors the diagonal block
 // itself, so the panel needs no communication between work-groups.
@@ -135,15 +135,15 @@ __device__ inline double bcast(double v, int src) {
     return __hiloint2double(hi, lo);
 }
 
-// The panel: the 64 x 64 diagonal block stacked on this work-group's 64 rows
-// below it (a 128 x 64 slab), eliminated column by column (right-looking):
+// The panel: the 64 x 64 diagonal block stacked on this work-group's 32 rows
+// below it (a 96 x 64 slab), eliminated column by column (right-looking):
 // step j takes the pivot d = sqrt(a_jj) and subtracts
 // l_rj conj(l_cj) = a_rj conj(a_cj) / d^2 from every later column c; column j
 // below the pivot is scaled by 1/d once, after the last step (its entries do
 // not change after step j, and the updates use the unscaled values).  On the
 // diagonal rows this is the Cholesky factor L11; on the rows below it is
 // x L11^H = a.
-// 1024 threads: wave g owns slab rows 8 g .. 8 g + 7 (g < 8: diagonal-block
+// 768 threads: wave g owns slab rows 8 g .. 8 g + 7 (g < 8: diagonal-block
 // rows; g >= 8: 8 of the rows below), lane c owns column c; 8 entries per
 // thread in registers with static indices.  At step j a wave takes its rows'
 // column-j entries from lane j by readlane; the column-j entries of the
@@ -156,9 +156,14 @@ __device__ inline double bcast(double v, int src) {
 // The factored diagonal block goes to a scratch tile, not into A: other
 // work-groups of the same launch may still be reading the unfactored block.
 // Work-group 0 of the next launch (or k_chol_flush after the last panel) copies
-// it into place.
+// it into place.  32 rows below per work-group rather than 64: twice the
+// work-groups (the first panel at N = 1024 takes 60 of the CU slots the
+// contraction leaves free), a quarter fewer waves per SIMD issuing each
+// column's updates (the factorisation stream at N = 1024: 3.87 -> 3.70 ms
+// stretched).
 constexpr int kPanelRows = 8;                   // slab rows per wave
-constexpr int kPanelThreads = 64 * 2 * NB / kPanelRows;
+constexpr int kPanelBelow = 32;                 // rows below the diagonal block per work-group
+constexpr int kPanelThreads = 64 * (NB + kPanelBelow) / kPanelRows;
 constexpr int kPanelDiagWaves = NB / kPanelRows;
 
 __global__ void __launch_bounds__(kPanelThreads) k_chol_panel(double2 *A0, double2 *A1, int Np, int kb,
@@ -190,7 +195,7 @@ __global__ void __launch_bounds__(kPanelThreads) k_chol_panel(double2 *A0, doubl
     const bool diagw = g < kPanelDiagWaves;
     const bool mine = diagw || below;                 // rows below exist for this wave
     const int srow = kPanelRows * g;                  // first slab row of this wave
-    const int grow = diagw ? kb + srow : kb + NB + blockIdx.x * NB + kPanelRows * (g - kPanelDiagWaves);
+    const int grow = diagw ? kb + srow : kb + NB + blockIdx.x * kPanelBelow + kPanelRows * (g - kPanelDiagWaves);
     double2 a[kPanelRows];
 #pragma unroll
     for (int v = 0; v < kPanelRows; ++v)
@@ -915,7 +920,7 @@ void launch_cholesky(const Dims &d, const Bufs &b, double2 *A0, double2 *A1, dou
     const int Np = padded(d.N);
     for (int kb = 0; kb < Np; kb += NB) {
         const int below = Np - kb - NB;
-        const int gx = below > 0 ? below / 64 : 1;
+        const int gx = below > 0 ? below / kPanelBelow : 1;
         hipLaunchKernelGGL(k_chol_panel, dim3(gx, count, d.batch), dim3(kPanelThreads), 0, s, A0, A1, Np, kb,
                            b.chol_diag, b.flags, d.zoff);
         if (below > 0) {

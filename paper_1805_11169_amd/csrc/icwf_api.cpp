@@ -535,8 +535,9 @@ icwf_status icwf_create(const icwf_config *cfg, const double *r0, const double *
     // mixed form: W_c = (rank-K part, FP64) + (residual, FP32 matrix cores)
     std::vector<double> lr_u, lr_v;
     d.lr_rank = 0;
+    int ncu = 0;
     {
-        int dev = 0, ncu = 0;
+        int dev = 0;
         if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu <= 0)
             ncu = 256;
         // two contraction work-groups fit a CU; kWcReserve of those slots stay free
@@ -578,6 +579,14 @@ icwf_status icwf_create(const icwf_config *cfg, const double *r0, const double *
         }
         if (rmax > kSeparableTol * wmax)
             return cleanup_fail(ICWF_EINVAL, "W_c is not a sum of at most 64 products to FP64 rounding; use the FP64 form");
+        // a contraction through few products is the short branch of a forked
+        // step where (n_r + n_R) K < 32 N (K in blocks of 16; N = 1024 on 512 x
+        // 256, K = 28: 1.2 ms beside 1.9 ms of factorisations; N = 4096 on 4096
+        // x 512, K = 41: 88 ms beside 49 ms): it then takes one work-group per
+        // CU and leaves the other slots to the factorisation stream
+        const size_t kp = (size_t)(d.lr_rank + 15) / 16 * 16;
+        if (icwf::padded(N) >= kOverlapMinN && (size_t)(nr + nR) * kp < 32 * (size_t)icwf::padded(N))
+            d.wc_grid = ncu;
     }
     auto fill_k = [&](std::vector<double2> &kin, std::vector<double2> &tw, int n, double h, double m) {
         for (int k = 0; k < n; ++k) {

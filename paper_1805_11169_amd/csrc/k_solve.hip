@@ -156,17 +156,18 @@ __device__ inline double bcast(double v, int src) {
 // The factored diagonal block goes to a scratch tile, not into A: other
 // work-groups of the same launch may still be reading the unfactored block.
 // Work-group 0 of the next launch (or k_chol_flush after the last panel) copies
-// it into place.  32 rows below per work-group rather than 64: twice the
-// work-groups (the first panel at N = 1024 takes 60 of the CU slots the
-// contraction leaves free), a quarter fewer waves per SIMD issuing each
-// column's updates (the factorisation stream at N = 1024: 3.87 -> 3.70 ms
-// stretched).
+// it into place.  32 rows below per work-group rather than 64 where the
+// launch's work-groups fit the CU slots left to the factorisations (the first
+// panel at N = 1024 takes 60 of the 64 the FP64 contraction leaves free):
+// a quarter fewer waves per SIMD issue each column's updates (the
+// factorisation stream at N = 1024: 3.87 -> 3.69 ms stretched); else 64, in
+// one round of work-groups rather than two.
 constexpr int kPanelRows = 8;                   // slab rows per wave
-constexpr int kPanelBelow = 32;                 // rows below the diagonal block per work-group
-constexpr int kPanelThreads = 64 * (NB + kPanelBelow) / kPanelRows;
 constexpr int kPanelDiagWaves = NB / kPanelRows;
+constexpr int panel_threads(int below) { return 64 * (NB + below) / kPanelRows; }
 
-__global__ void __launch_bounds__(kPanelThreads) k_chol_panel(double2 *A0, double2 *A1, int Np, int kb,
+template <int BELOW>   // rows below the diagonal block per work-group: 32 or 64
+__global__ void __launch_bounds__(panel_threads(BELOW)) k_chol_panel(double2 *A0, double2 *A1, int Np, int kb,
                                                               double2 *__restrict__ diag,
                                                               int32_t *__restrict__ flags, const long long *__restrict__ zoff) {
     const long long zo_ = batch_offset(zoff);
@@ -186,7 +187,7 @@ __global__ void __launch_bounds__(kPanelThreads) k_chol_panel(double2 *A0, doubl
     const int t = threadIdx.x, c = t & 63, g = t >> 6;
     if (blockIdx.x == 0 && kb > 0) {
         const int pb = kb - NB;
-        for (int e = t; e < NB * NB; e += kPanelThreads) {
+        for (int e = t; e < NB * NB; e += panel_threads(BELOW)) {
             const int rr = e / NB, cc = e % NB;
             if (cc <= rr) A[(size_t)(pb + rr) * Np + pb + cc] = D[e];
         }
@@ -195,7 +196,7 @@ __global__ void __launch_bounds__(kPanelThreads) k_chol_panel(double2 *A0, doubl
     const bool diagw = g < kPanelDiagWaves;
     const bool mine = diagw || below;                 // rows below exist for this wave
     const int srow = kPanelRows * g;                  // first slab row of this wave
-    const int grow = diagw ? kb + srow : kb + NB + blockIdx.x * kPanelBelow + kPanelRows * (g - kPanelDiagWaves);
+    const int grow = diagw ? kb + srow : kb + NB + blockIdx.x * BELOW + kPanelRows * (g - kPanelDiagWaves);
     double2 a[kPanelRows];
 #pragma unroll
     for (int v = 0; v < kPanelRows; ++v)
@@ -918,11 +919,25 @@ void launch_assemble(const Dims &d, const Bufs &b, int parity, AssemblePart part
 void launch_cholesky(const Dims &d, const Bufs &b, double2 *A0, double2 *A1, double2 *X0, double2 *X1, int count,
                      hipStream_t s, double2 *F0, double2 *F1, double2 *H0, double2 *H1, bool inverses) {
     const int Np = padded(d.N);
+    // the CU slots the contraction leaves free (two work-groups per CU):
+    // 32 rows below per panel work-group where the first launch fits them
+    int dev = 0, ncu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu <= 0)
+        ncu = 256;
+    const int free_slots = std::max(2 * ncu - d.wc_grid, 1);
+    const bool narrow = (long long)count * d.batch * ((Np - NB) / 32) <= free_slots;
     for (int kb = 0; kb < Np; kb += NB) {
         const int below = Np - kb - NB;
-        const int gx = below > 0 ? below / kPanelBelow : 1;
-        hipLaunchKernelGGL(k_chol_panel, dim3(gx, count, d.batch), dim3(kPanelThreads), 0, s, A0, A1, Np, kb,
-                           b.chol_diag, b.flags, d.zoff);
+        if (narrow) {
+            const int gx = below > 0 ? below / 32 : 1;
+            hipLaunchKernelGGL(k_chol_panel<32>, dim3(gx, count, d.batch), dim3(panel_threads(32)), 0, s, A0, A1, Np,
+                               kb, b.chol_diag, b.flags, d.zoff);
+        } else {
+            const int gx = below > 0 ? below / 64 : 1;
+            hipLaunchKernelGGL(k_chol_panel<64>, dim3(gx, count, d.batch), dim3(panel_threads(64)), 0, s, A0, A1, Np,
+                               kb, b.chol_diag, b.flags, d.zoff);
+        }
         if (below > 0) {
             const int mt = below / 32;
             hipLaunchKernelGGL(k_chol_update, dim3(mt * (mt + 1) / 2, count, d.batch), dim3(256), 0, s, A0, A1, Np, kb,
